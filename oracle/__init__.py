@@ -1,0 +1,32 @@
+"""CPU FP64 oracle for the model-visibility prediction path.
+
+TEST INFRASTRUCTURE.  Only tests/, __graft_entry__.smoke() and the
+cpu_baseline leg of bench.py may import, call or execute anything here.  It
+shares no code with the GPU library (paper_1909_03956_amd) and imports
+nothing from it; both are fed by the seeded generators in synth/.
+
+Plain, slow NumPy: the direct sum of Eq. 12, the nested equal-area sphere
+pixelisation of section 3.2, the wavelet tree of Eqs. 9, 10, 16, 17, the
+exact adjoint of Eq. 12 and the chi^2 gradients.  What pins each part
+(tests/test_oracle_*.py, all CPU):
+
+visibility.predict_direct  unit source at the phase centre gives V = 1; a
+    shifted source has |V| = 1 and V(B1 + B2) = V(B1) V(B2); w = 0 on a
+    regular grid equals numpy's 2-D FFT (Eq. 2); Pythagorean directions with
+    integer phases give V = 1 including the w-term; Hermitian symmetry and
+    the sign flip; 50-digit mpmath brute force on small random inputs.
+visibility.adjoint         <A x, y> = <x, A^H y> for random complex x, y;
+    unit source at the centre with y = 1 gives N_vis; FFT special case.
+visibility.grad_direct     central finite differences of chi^2; flux
+    gradient equals -2/sigma^2 Re(A^H r); zero at the true model.
+visibility.residual_chi2   chi^2 of known residuals (closed form).
+sphere.*                   N_j = 12 4^(j-1); the twelve base-pixel centres;
+    nested parent rule k_j = k_J >> 2(J-j); round trip pix -> centre -> pix;
+    equal areas (Monte-Carlo chi^2); frame axes (P -> (alpha_P, delta_P),
+    u east, v north); the recommended-resolution table (tests/golden).
+tree.*                     analysis followed by synthesis recovers lambda_J;
+    uniform model gives gamma = 0; single component gives F eta_leaf; J = 1;
+    Eq. 17 equals the snapped direct sum; the unmasked full-sphere tree
+    gives the same V (zero branches may be skipped).
+"""
+from . import sphere, tree, visibility  # noqa: F401

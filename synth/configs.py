@@ -1,0 +1,181 @@
+"""The five seeded workloads (input recipes only).
+
+cfg1  parity case: 64 antennas in a 5 km-radius disk, dec +45 deg, 2 h,
+      60 samples, 1.4 GHz -> 2016 baselines x 60 = 120,960 rows; 200 components
+      uniform in a 2 deg field; tree at J = 6.
+cfg2  measured case: 256 antennas in a 20 km-radius disk, dec +30 deg, 8 h,
+      256 samples, 1.4 GHz -> 32,640 x 256 = 8,355,840 rows; 2,000 components
+      (70 % in 5 Gaussian blobs of sigma 0.1 deg, 30 % uniform over 4 deg);
+      trees at J = 8, 9, 10.
+cfg3  precision case: cfg2's layout with a 50 km-radius disk (baselines to
+      ~100 km, w-term active), 10,000 components uniform over 3 deg.
+cfg4  batched case: 64 channels (0.95-1.75 GHz) x 4 pointings; per instance
+      2M-8M unflagged rows after 0-40 % random flagging, N_C log-uniform in
+      [100, 20000], J uniform in 7..10.
+cfg5  adjoint case: cfg2 tracks and model; a perturbed model plus complex
+      noise (sigma 0.01 Jy) gives observed visibilities; residual image on the
+      level-9 pixels within 4 deg of the phase centre.
+
+The phase centre of every config is at right ascension 12h, the
+declination of its tracks.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import models, tracks
+
+
+@dataclass(frozen=True)
+class TrackSpec:
+    n_ant: int
+    radius_m: float
+    dec_deg: float
+    duration_s: float
+    n_t: int
+    freq_hz: float
+    seed: int
+    ra_deg: float = 180.0
+
+    @property
+    def n_baselines(self) -> int:
+        return self.n_ant * (self.n_ant - 1) // 2
+
+    @property
+    def n_vis(self) -> int:
+        return self.n_baselines * self.n_t
+
+    def uvw(self):
+        return tracks.array_tracks(self.n_ant, self.radius_m, self.dec_deg,
+                                   self.duration_s, self.n_t, self.freq_hz, self.seed)
+
+    def uvw_rows(self, rows):
+        bxyz = tracks.array_baselines_xyz(self.n_ant, self.radius_m, self.seed)
+        return tracks.uvw_rows(bxyz, self.n_t, self.duration_s, self.dec_deg,
+                               self.freq_hz, rows)
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    track: TrackSpec
+    model: str                      # "uniform" or "mixture"
+    n_comp: int
+    field_deg: float
+    seed_model: int
+    J: tuple = ()
+    description: str = ""
+
+    @property
+    def ra_p(self) -> float:
+        return math.radians(self.track.ra_deg)
+
+    @property
+    def dec_p(self) -> float:
+        return math.radians(self.track.dec_deg)
+
+    def components(self):
+        rng = np.random.default_rng(self.seed_model)
+        if self.model == "uniform":
+            return models.uniform_components(self.n_comp, self.field_deg, rng)
+        return models.blob_mixture_components(self.n_comp, 0.7, 5, 0.1, 3.0,
+                                              self.field_deg, rng)
+
+
+H = 3600.0
+
+CFG1 = Workload("cfg1", TrackSpec(64, 5e3, 45.0, 2 * H, 60, 1.4e9, seed=101),
+                "uniform", 200, 2.0, seed_model=102, J=(6,),
+                description="direct FP64 parity, 120,960 vis x 200 comps")
+CFG2 = Workload("cfg2", TrackSpec(256, 20e3, 30.0, 8 * H, 256, 1.4e9, seed=201),
+                "mixture", 2000, 4.0, seed_model=202, J=(8, 9, 10),
+                description="direct vs tree FP64, 8,355,840 vis x 2,000 comps")
+CFG3 = Workload("cfg3", TrackSpec(256, 50e3, 30.0, 8 * H, 256, 1.4e9, seed=301),
+                "uniform", 10_000, 3.0, seed_model=302,
+                description="FP32-compensated vs FP64, 8,355,840 vis x 10,000 comps")
+CFG5_NOISE_SIGMA = 0.01
+CFG5_J = 9
+CFG5_DISK_RADIUS_DEG = 4.0
+CFG5_SEED_PERTURB = 502
+CFG5_SEED_NOISE = 503
+
+WORKLOADS = {w.name: w for w in (CFG1, CFG2, CFG3)}
+
+
+def sample_rows(n_vis: int, n_sample: int, seed: int, tile: int = 256) -> np.ndarray:
+    """Sorted row indices: the first and last `tile` rows plus a seeded random
+    sample, so a sample spans several kernel tiles and the ragged tail."""
+    rng = np.random.default_rng(seed)
+    head = np.arange(min(tile, n_vis))
+    tail = np.arange(max(0, n_vis - tile), n_vis)
+    rnd = rng.choice(n_vis, size=min(n_sample, n_vis), replace=False)
+    return np.unique(np.concatenate([head, tail, rnd])).astype(np.int64)
+
+
+# ---------------------------------------------------------------- cfg4 ----
+@dataclass(frozen=True)
+class Instance:
+    index: int
+    channel_hz: float
+    dec_deg: float
+    n_target: int
+    flag_frac: float
+    n_t: int
+    n_comp: int
+    J: int
+    seed: int
+
+
+@dataclass
+class BatchedWorkload:
+    """64 channels x 4 pointings on cfg2's 256-antenna, 20 km array."""
+    n_channels: int = 64
+    f_lo: float = 0.95e9
+    f_hi: float = 1.75e9
+    decs: tuple = (30.0, 45.0, 60.0, 10.0)
+    n_min: int = 2_000_000
+    n_max: int = 8_000_000
+    flag_max: float = 0.4
+    nc_min: int = 100
+    nc_max: int = 20_000
+    J_range: tuple = (7, 10)
+    seed: int = 401
+    scale: float = 1.0                 # < 1 shrinks every instance (tests only)
+    instances: list = field(default_factory=list)
+
+    def __post_init__(self):
+        rng = np.random.default_rng(self.seed)
+        freqs = np.linspace(self.f_lo, self.f_hi, self.n_channels)
+        n_bl = CFG2.track.n_baselines
+        out = []
+        i = 0
+        for dec in self.decs:
+            for f in freqs:
+                n_target = int(rng.integers(self.n_min, self.n_max + 1) * self.scale)
+                frac = float(rng.uniform(0.0, self.flag_max))
+                n_t = max(1, math.ceil(n_target / (n_bl * (1.0 - frac))))
+                nc = int(round(math.exp(rng.uniform(math.log(self.nc_min),
+                                                    math.log(self.nc_max)))))
+                J = int(rng.integers(self.J_range[0], self.J_range[1] + 1))
+                out.append(Instance(i, float(f), float(dec), n_target, frac, n_t, nc, J,
+                                    seed=int(self.seed * 1000 + i)))
+                i += 1
+        self.instances = out
+
+    def instance_inputs(self, inst: Instance):
+        """(u, v, w, l, m, flux) of one instance: the cfg2 array tracked for 8 h
+        at the instance's pointing and frequency with n_t samples, rows flagged
+        at random with the instance's fraction."""
+        rng = np.random.default_rng(inst.seed)
+        bxyz = tracks.array_baselines_xyz(CFG2.track.n_ant, CFG2.track.radius_m,
+                                          CFG2.track.seed)
+        Hs = tracks.hour_angles(8 * H, inst.n_t)
+        u, v, w = tracks.uvw_from_baselines(bxyz, Hs, math.radians(inst.dec_deg),
+                                            inst.channel_hz)
+        keep = rng.random(u.shape[0]) >= inst.flag_frac
+        l, m, flux = models.blob_mixture_components(inst.n_comp, 0.7, 5, 0.1, 3.0, 4.0, rng)
+        return (np.ascontiguousarray(u[keep]), np.ascontiguousarray(v[keep]),
+                np.ascontiguousarray(w[keep]), l, m, flux)
