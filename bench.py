@@ -1,0 +1,357 @@
+#!/usr/bin/env python3
+"""Throughput of the model-visibility prediction hot path on one MI355X.
+
+One step is one major cycle of the hot path over the measured workload
+(8,355,840 visibilities of a 256-antenna, 20 km array tracked 8 h at dec +30
+deg, 1.4 GHz; 2,000 clean components, 70 % in five 0.1 deg blobs):
+
+  direct FP64       V = sum_k I_k e_jk                       (N_C terms per row)
+  direct FP32c      same, FP64 phase, FP32 sincos + Kahan     (N_C terms)
+  tree J = 8, 9, 10 host tree build + wavelet route (Eq. 17)  (N_C terms each)
+  residual, chi^2   r = V_obs - V (FP64 model)
+  adjoint           residual image on the level-9 pixels within 4 deg (N_pix terms)
+  gradients         d chi^2 / d(I, l, m) of every component  (N_C terms)
+
+value = (sum over the step of rows x terms) / step time, in Gvis.terms/s.
+Inputs are resident in device memory before the timed region.  One JSON line
+goes to stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gvis·terms/s for model-visibility prediction, direct vs tree, FP64 vs FP32-comp"
+UNIT = "Gvis·terms/s"
+PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
+PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (packed)
+HBM_GBS = 8000.0
+TREE_LEVELS = (8, 9, 10)
+CPU_SHARE = 16                 # host cores of one GPU's share of the box
+
+# Algorithmic flops per unit (FMA = 2, other arithmetic = 1; a rint counts 1):
+#   phase u l + v m + w (n-1): 1 mul + 2 FMA = 5; reduction rint + sub = 2;
+#   phasor: r^2 1, sine polynomial 6 FMA + 1 mul = 13, cosine 6 FMA = 12,
+#   4x identities 8 -> 34.  Per-term work after the phasor:
+FLOPS = {
+    "direct_fp64": 5 + 2 + 34 + 4,            # MAC: 2 FMA                      -> 45
+    "adjoint": 5 + 2 + 34 + 8,                # complex MAC: 4 FMA               -> 49
+    "grad": 5 + 2 + 34 + 6 + 2 + 12,          # z = conj(y) e, Z0 += z, 3 x 2 FMA -> 61
+    "tree_leaf": 5 + 2 + 34 + 14,             # + running sums S, D^0..2 (2 add, 6 FMA)
+    "tree_node": 20 + 14,                     # eta, sigma, gamma sigma; + parent sums
+    "tree_root": 20 + 4,                      # level-1 node: + A_1 lambda_1 eta_1
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--cpu-rows", type=int, default=32768,
+                   help="rows of the workload the oracle is timed on")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--profile", action="store_true",
+                   help="short run for a profiler: no CPU baseline")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="also run one device copy of 1 GiB (HBM counter calibration)")
+    return p.parse_args()
+
+
+# ------------------------------------------------------------ CPU baseline --
+def _cpu_worker(args):
+    """Times the oracle on a slice of rows for every stage of the step."""
+    rows, seed_inputs = args
+    import numpy as np
+    from oracle import sphere as sp
+    from oracle import tree as ot
+    from oracle import visibility as ov
+    from synth import configs, models
+    W = configs.CFG2
+    u, v, w = W.track.uvw_rows(rows)
+    l, m, f = W.components()
+    rng = np.random.default_rng(seed_inputs)
+    y = models.complex_noise(rows.size, 0.01, rng)
+    pix, pl, pm, pn = sp.pixels_in_disk(9, W.ra_p, W.dec_p, math.radians(4.0))
+    t0 = time.perf_counter()
+    V = ov.predict_direct(u, v, w, l, m, f)           # FP64 form (and the FP32c reference)
+    t_direct = time.perf_counter() - t0
+    terms = 2 * rows.size * l.size
+    t_trees = 0.0
+    for J in TREE_LEVELS:
+        t1 = time.perf_counter()
+        T = ot.build_tree(J, W.ra_p, W.dec_p, l, m, f)
+        ot.predict_tree(T, u, v, w)
+        t_trees += time.perf_counter() - t1
+        terms += rows.size * l.size
+    t1 = time.perf_counter()
+    r, _ = ov.residual_chi2(V + y, V, 1e4)
+    ov.adjoint(u, v, w, r, pl, pm, pn)
+    t_adj = time.perf_counter() - t1
+    terms += rows.size * pix.size
+    t1 = time.perf_counter()
+    ov.grad_direct(u, v, w, r, l, m, f, alpha=-2e4)
+    t_grad = time.perf_counter() - t1
+    terms += rows.size * l.size
+    return terms, 2 * t_direct + t_trees + t_adj + t_grad
+
+
+def cpu_baseline(n_rows: int) -> dict:
+    import multiprocessing as mp
+
+    import numpy as np
+    from synth import configs
+    cores = min(CPU_SHARE, len(os.sched_getaffinity(0)))
+    rows = configs.sample_rows(configs.CFG2.track.n_vis, n_rows, seed=2024, tile=0)
+    rows = rows[:n_rows]
+    parts = [p for p in np.array_split(rows, cores) if p.size]
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(len(parts)) as pool:
+        res = pool.map(_cpu_worker, [(p, 99 + i) for i, p in enumerate(parts)])
+    wall = time.perf_counter() - t0
+    terms = sum(r[0] for r in res)
+    cpu_s = sum(r[1] for r in res)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    busy = max(r[1] for r in res)
+    return {
+        "value": terms / busy / 1e9,
+        "unit": UNIT,
+        "cores": len(parts),
+        "kind": "oracle",
+        "sample": (f"{rows.size} seeded rows of the 8,355,840-row workload, every stage of the "
+                   f"step (direct sum twice: FP64 reference of both forms), split over "
+                   f"{len(parts)} worker processes, 1 thread each"),
+        "per_core_value": terms / cpu_s / 1e9,
+        "cpu_seconds": cpu_s,
+        "wall_seconds_incl_spawn": wall,
+        "cpu_model": model,
+    }
+
+
+# ------------------------------------------------------------------ GPU --
+def _sha(path):
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_for(kernel_file: str, per_launch_key: str):
+    """HBM bytes per launch from the committed counter summary, or None if the
+    kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(per_launch_key)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, "paper_1909_03956_amd", "csrc", kernel_file)
+    if rec.get("source_sha") != _sha(src):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (--gpus "
+              f"{args.gpus} requested); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1909_03956_amd as swv
+    from synth import configs, models
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    W = configs.CFG2
+    t_in = time.perf_counter()
+    u, v, w = W.track.uvw()
+    l, m, f = W.components()
+    n_vis, n_comp = u.size, l.size
+
+    def D(x):
+        return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+    U, V, Wt = D(u), D(v), D(w)
+    L, M, F = D(l), D(m), D(f)
+    pix, pl, pm, pn = swv.pixels_in_disk(9, W.ra_p, W.dec_p, math.radians(4.0))
+    PL, PM, PN = D(pl), D(pm), D(pn)
+    n_pix = pix.size
+    rng = np.random.default_rng(configs.CFG5_SEED_PERTURB)
+    l2, m2, f2 = models.perturb_model(l, m, f, rng)
+    noise = models.complex_noise(n_vis, configs.CFG5_NOISE_SIGMA,
+                                 np.random.default_rng(configs.CFG5_SEED_NOISE))
+    v_obs = swv.predict_direct(U, V, Wt, D(l2), D(m2), D(f2))
+    v_obs += torch.as_tensor(noise, dtype=torch.complex128, device=dev)
+    inv_s2 = 1.0 / configs.CFG5_NOISE_SIGMA ** 2
+    v64 = torch.empty(n_vis, dtype=torch.complex128, device=dev)
+    v32 = torch.empty(n_vis, dtype=torch.complex64, device=dev)
+    vt = {J: torch.empty(n_vis, dtype=torch.complex128, device=dev) for J in TREE_LEVELS}
+    resid = torch.empty(n_vis, dtype=torch.complex128, device=dev)
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.perf_counter() - t_in:.1f} s: {n_vis} rows, {n_comp} "
+        f"components, {n_pix} pixels")
+
+    stages = ["direct_fp64", "direct_f32c"] + [f"tree_J{J}" for J in TREE_LEVELS] + \
+        ["residual", "adjoint", "grad"]
+    keep_trees = []
+    tree_stats = {}
+
+    def step(events):
+        def mark(name):
+            e = torch.cuda.Event(enable_timing=True)
+            e.record()
+            events.append((name, e))
+        mark("start")
+        swv.predict_direct(U, V, Wt, L, M, F, out=v64)
+        mark("direct_fp64")
+        swv.predict_direct(U, V, Wt, L, M, F, prec="f32c", out=v32)
+        mark("direct_f32c")
+        for J in TREE_LEVELS:
+            T = swv.Tree(J, W.ra_p, W.dec_p, l, m, f)     # host build, once per major cycle
+            keep_trees.append(T)
+            tree_stats[J] = T.stats()
+            T.predict(U, V, Wt, out=vt[J])
+            mark(f"tree_J{J}")
+        r, chi2 = swv.residual_chi2(v_obs, v64, inv_s2, out=resid)
+        mark("residual")
+        img = swv.adjoint(U, V, Wt, r, PL, PM, PN)
+        mark("adjoint")
+        g = swv.grad_direct(U, V, Wt, r, L, M, F, alpha=-2.0 * inv_s2)
+        mark("grad")
+        return chi2, img, g
+
+    for _ in range(args.warmup):
+        step([])
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    all_events = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ev = []
+        step(ev)
+        all_events.append(ev)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    swv.synchronize()
+    ms_per_step = 1e3 * wall / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step")
+
+    # per-stage device times (median over steps)
+    per = {s: [] for s in stages}
+    for ev in all_events:
+        for (a, ea), (b, eb) in zip(ev[:-1], ev[1:]):
+            per[b].append(ea.elapsed_time(eb))
+    med = {s: float(np.median(per[s])) for s in stages}
+    terms = {"direct_fp64": n_vis * n_comp, "direct_f32c": n_vis * n_comp,
+             "residual": 0, "adjoint": n_vis * n_pix, "grad": n_vis * n_comp}
+    for J in TREE_LEVELS:
+        terms[f"tree_J{J}"] = n_vis * n_comp
+    step_terms = sum(terms.values())
+    value = step_terms / (ms_per_step * 1e-3) / 1e9
+
+    routes = {}
+    for s in stages:
+        r = {"ms": round(med[s], 4)}
+        if terms[s]:
+            r["Gvis_terms_per_s"] = round(terms[s] / (med[s] * 1e-3) / 1e9, 2)
+        routes[s] = r
+    for J in TREE_LEVELS:
+        st = tree_stats[J]
+        routes[f"tree_J{J}"].update({"leaves": st["n_leaves"], "internal_nodes": st["n_internal"],
+                                     "host_build_ms": round(1e3 * st["build_seconds"], 3),
+                                     "Gvis_nodes_per_s": round(
+                                         n_vis * (st["n_leaves"] + st["n_internal"]) /
+                                         (med[f"tree_J{J}"] * 1e-3) / 1e9, 2)})
+    routes["residual"]["GB_per_s"] = round(48 * n_vis / (med["residual"] * 1e-3) / 1e9, 1)
+    routes["direct_fp64"]["hbm_GB_per_s"] = round(40 * n_vis / (med["direct_fp64"] * 1e-3) / 1e9, 2)
+    routes["direct_f32c"]["hbm_GB_per_s"] = round(32 * n_vis / (med["direct_f32c"] * 1e-3) / 1e9, 2)
+    routes["speedup_f32c_over_fp64"] = round(med["direct_fp64"] / med["direct_f32c"], 3)
+
+    # roofline of the dominant kernel (largest device time in the step)
+    def tree_flops(J):
+        st = tree_stats[J]
+        roots = st["nodes_per_level"][0]
+        return n_vis * (st["n_leaves"] * FLOPS["tree_leaf"] +
+                        (st["n_internal"] - (roots if J > 1 else 0)) * FLOPS["tree_node"] +
+                        roots * FLOPS["tree_root"])
+    flops = {"direct_fp64": n_vis * n_comp * FLOPS["direct_fp64"],
+             "adjoint": n_vis * n_pix * FLOPS["adjoint"],
+             "grad": n_vis * n_comp * FLOPS["grad"]}
+    for J in TREE_LEVELS:
+        flops[f"tree_J{J}"] = tree_flops(J)
+    kernel_of = {"direct_fp64": ("k_direct.hip", "k_direct_f64"),
+                 "adjoint": ("k_image.hip", "k_adjoint"), "grad": ("k_image.hip", "k_grad_partial")}
+    for J in TREE_LEVELS:
+        kernel_of[f"tree_J{J}"] = ("k_tree.hip", f"k_tree_J{J}")
+    dom = max(flops, key=lambda s: med[s])
+    achieved = flops[dom] / (med[dom] * 1e-3) / 1e12
+    src, kname = kernel_of[dom]
+    traffic = traffic_for(src, kname)
+    roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                "traffic": traffic, "kernel": kname, "stage": dom,
+                "flops_per_launch": flops[dom], "avg_launch_ms": round(med[dom], 4)}
+    for s in flops:
+        routes[s]["TFLOP_per_s"] = round(flops[s] / (med[s] * 1e-3) / 1e12, 2)
+        routes[s]["fp64_alu_frac"] = round(flops[s] / (med[s] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32c", "data": "synthetic",
+        "config": {"workload": "cfg2 major cycle: 256-antenna 20 km array, 8 h at dec +30, "
+                               "1.4 GHz, 8,355,840 vis; 2,000 components (70% in 5 blobs); "
+                               "trees J=8,9,10; adjoint on the J=9 pixels within 4 deg",
+                   "n_vis": n_vis, "n_comp": n_comp, "n_pix": int(n_pix),
+                   "tree_levels": list(TREE_LEVELS), "terms_per_step": step_terms},
+        "routes": routes,
+        "roofline": roofline,
+    }
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = a.numel() * 8
+    if not (args.no_cpu_baseline or args.profile):
+        log("timing the oracle on the host ...")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_rows)
+    print(json.dumps(out), flush=True)
+    for T in keep_trees:
+        T.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,302 @@
+/*
+ * swvis.h -- C ABI of libswvis.so: model-visibility prediction on MI355X
+ * (gfx950) by the direct component sum and by the spherical-Haar-wavelet
+ * tree of Skipper, Scaife & McEwen (2019), plus the exact adjoint and the
+ * chi^2 gradients of the direct sum.
+ *
+ * Notation.  A visibility row j has baseline B_j = (u_j, v_j, w_j) in
+ * wavelengths; a component k has direction cosines (l_k, m_k), n_k =
+ * sqrt(1 - l_k^2 - m_k^2), and flux I_k.  The phase in cycles is
+ *     phi_jk = u_j l_k + v_j m_k + w_j (n_k - 1)
+ * (section 3.3, Eq. 12 with the phase centre at [0, 0, 1]) and
+ *     e_jk = exp(s 2 pi i phi_jk),  s = `sign` in {-1, +1}.
+ * The paper prints s = +1; the conventional default is s = -1.
+ *
+ * Conventions of every entry point.
+ *  - Return value: SWV_OK (0) or a negative status; swv_last_error() then
+ *    holds a message (thread-local, valid until the next call on the thread).
+ *    No C++ exception and no abort crosses this boundary.
+ *  - Pointers marked DEVICE are caller-owned device memory (e.g. a torch
+ *    tensor's data_ptr()) on the context's device; they must stay valid until
+ *    the context's stream has reached the work.  Pointers marked HOST are
+ *    caller-owned host memory, read or written before the call returns.  The
+ *    library never frees caller memory.
+ *  - Arrays are contiguous.  FP64 unless stated.  Complex values are
+ *    interleaved (re, im): complex128 = 2 x FP64 (16 B), complex64 = 2 x FP32.
+ *  - Device work is enqueued asynchronously on the context's stream.  Errors
+ *    the kernels detect (non-finite or out-of-domain inputs) and HIP faults
+ *    are reported by the next swv_ctx_synchronize() on that context.
+ *  - Library objects (swv_ctx, swv_tree, swv_plan, swv_graph) follow
+ *    create/destroy pairs.  A context may be used from one thread at a time;
+ *    calls that overlap on one stream are ordered by the stream.
+ *  - n = 0 is valid everywhere and enqueues nothing (outputs untouched,
+ *    except reductions, which write zero).
+ */
+#ifndef SWVIS_H
+#define SWVIS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWV_VERSION_MAJOR 1
+#define SWV_VERSION_MINOR 0
+
+/* Status codes. */
+#define SWV_OK        0
+#define SWV_EINVAL   (-1)  /* null pointer, negative size, bad enum, bad handle */
+#define SWV_EDOMAIN  (-2)  /* l^2 + m^2 >= 1, J outside [1, 29], |sign| != 1, non-finite input */
+#define SWV_ENOMEM   (-3)  /* host or device allocation failed */
+#define SWV_EHIP     (-4)  /* a HIP runtime call failed; the message holds the HIP error text */
+#define SWV_ENOTSUP  (-5)  /* valid request this build does not support */
+
+/* Arithmetic forms. */
+#define SWV_FP64  0  /* phase, sincos and sums in FP64; output complex128 */
+#define SWV_F32C  1  /* phase and its reduction mod 1 in FP64; sincos (the hardware
+                        v_sin_f32 / v_cos_f32, which take revolutions), products and
+                        Kahan-compensated sums in FP32; output complex64 */
+
+/* Routes of a batched instance. */
+#define SWV_ROUTE_DIRECT 0
+#define SWV_ROUTE_TREE   1
+
+#define SWV_MAX_LEVEL 29
+
+typedef struct swv_ctx_s* swv_ctx;
+typedef struct swv_tree_s* swv_tree;
+typedef struct swv_plan_s* swv_plan;
+typedef struct swv_graph_s* swv_graph;
+
+/* ------------------------------------------------------------ basics --- */
+
+/* Library version (SWV_VERSION_MAJOR, SWV_VERSION_MINOR). */
+int swv_version(int* major, int* minor);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* swv_last_error(void);
+
+/* Creates a context bound to HIP device `device` and the HIP stream `stream`
+ * (a hipStream_t; NULL = the legacy default stream).  The context owns its
+ * workspaces and its tuning table.  If the environment variable
+ * SWV_TUNE_CACHE names a file written by swv_autotune, it is loaded. */
+int swv_ctx_create(int device, void* stream, swv_ctx* out);
+
+/* Rebinds the context to another stream of the same device. */
+int swv_ctx_set_stream(swv_ctx ctx, void* stream);
+
+/* Waits for the context's stream; returns the first deferred error since the
+ * previous call: SWV_EDOMAIN if a kernel saw an out-of-domain or non-finite
+ * input, SWV_EHIP on a HIP failure. */
+int swv_ctx_synchronize(swv_ctx ctx);
+
+/* Frees the context's workspaces (after waiting for its stream). */
+int swv_ctx_destroy(swv_ctx ctx);
+
+/* ------------------------------------------------------- direct route --- */
+
+/* Direct component sum (section 3.3, Eq. 12):
+ *     vis_out[j] = sum_k flux[k] * e_jk,   j < n_vis.
+ * u, v, w [n_vis] DEVICE; l, m, flux [n_comp] DEVICE (l^2 + m^2 < 1);
+ * vis_out [n_vis] DEVICE complex128 (SWV_FP64) or complex64 (SWV_F32C).
+ * n - 1 is formed as -(l^2 + m^2) / (1 + n).  Work: n_vis * n_comp terms.
+ * Uses a context workspace of 32 * n_comp bytes (the packed components). */
+int swv_predict_direct(swv_ctx ctx, int64_t n_vis, const double* u, const double* v,
+                       const double* w, int64_t n_comp, const double* l, const double* m,
+                       const double* flux, int sign, int prec, void* vis_out);
+
+/* --------------------------------------------------------- tree route --- */
+
+typedef struct {
+    int J;                                   /* finest level */
+    int64_t n_comp;                          /* components given */
+    int64_t n_leaves;                        /* distinct level-J pixels (N~_C) */
+    int64_t n_internal;                      /* existing nodes at levels 1..J-1 */
+    int64_t n_nodes[SWV_MAX_LEVEL + 1];      /* n_nodes[j] = existing nodes at level j */
+    int64_t n_records;                       /* length of the depth-first record stream */
+    double sparsity;                         /* n_leaves / N_J */
+    double build_seconds;                    /* host time of swv_tree_build */
+} swv_tree_stats_t;
+
+/* Builds the sparse coefficient tree of a component list (sections 3.2-3.5),
+ * on the host:
+ *  1. [l, m, n] (SIN projection) is rotated to the equatorial xyz frame by
+ *     R_uvw->xyz = R_y(ra_p) R_x(-dec_p) (section 3.4, Eq. 18);
+ *  2. assigned to its level-J nested pixel of the 12 * 4^(J-1)-pixel
+ *     equal-area (HEALPix NESTED) pixelisation (section 3.2);
+ *  3. components sharing a pixel are summed into one leaf; the leaf position
+ *     is the pixel centre rotated back to uvw (section 3.5);
+ *  4. lambda_J = flux / A_J, and for existing nodes at j = J-1 .. 1
+ *     lambda_j = 1/4 sum_c lambda_{j+1,4k+c} (Eq. 9) and
+ *     gamma^m_j = sqrt(A_j)/4 sum_c s^m_c lambda_{j+1,4k+c} (Eq. 10);
+ *     ancestors are k_j = k_J >> 2(J - j) (section 3.5).
+ * Geometry is evaluated in extended precision and rounded once to FP64.
+ * l, m, flux [n_comp] HOST.  1 <= J <= 29.  ra_p, dec_p in radians. */
+int swv_tree_build(int J, double ra_p, double dec_p, int64_t n_comp, const double* l,
+                   const double* m, const double* flux, swv_tree* out);
+
+/* Sizes of a tree (HOST struct). */
+int swv_tree_stats(swv_tree tree, swv_tree_stats_t* out);
+
+/* Copies the leaves, sorted by pixel id, to HOST arrays of n_leaves entries:
+ * nested pixel id, centre (l, m, n - 1) in the uvw frame, summed flux.
+ * Any pointer may be NULL to skip that array. */
+int swv_tree_leaves(swv_tree tree, int64_t* pix, double* l, double* m, double* nm1,
+                    double* flux);
+
+/* Copies level j (1 <= j <= J) of the tree to HOST arrays of n_nodes[j]
+ * entries: sorted pixel ids, 4-bit child masks (bit c set if child 4k+c
+ * exists; 0 at level J), lambda_j, and gamma^0..2 as [n][3] (zeros at level
+ * J).  Any pointer may be NULL. */
+int swv_tree_level(swv_tree tree, int j, int64_t* pix, int32_t* child_mask, double* lambda,
+                   double* gamma);
+
+/* Model visibilities by the wavelet route (section 3.3, Eqs. 14-17; the
+ * per-visibility work of section 3.6.1): for every row, the plane wave
+ * eta_{J,k} = exp(s 2 pi i B . (s_k - P)) at the leaf centres, then per
+ * existing node eta_j = 1/4 sum_c eta_{j+1} and
+ * sigma^m_j = sqrt(A_j)/4 sum_c s^m_c eta_{j+1} (Eqs. 9, 10 applied to the
+ * plane wave), and
+ *     vis_out = A_1 sum_k lambda_1 eta_1 + sum_{j<J} sum_k sum_m gamma^m sigma^m
+ * (Eq. 17 with lambda_J a flux density; equal to the direct sum over the
+ * pixel-snapped leaves, Eq. 16).  u, v, w [n_vis] DEVICE; vis_out DEVICE
+ * complex128 (SWV_FP64 only).  The tree is copied to the device on first use
+ * with this context's device. */
+int swv_predict_tree(swv_ctx ctx, swv_tree tree, int64_t n_vis, const double* u,
+                     const double* v, const double* w, int sign, int prec, void* vis_out);
+
+int swv_tree_destroy(swv_tree tree);
+
+/* ------------------------------------------------------ sphere pixels --- */
+
+/* Level-J nested pixel of each SIN-projected direction (l, m) for the phase
+ * centre (ra_p, dec_p) (sections 3.2, 3.4, 3.5).  l, m [n] HOST, pix [n] HOST. */
+int swv_ang2pix(int J, double ra_p, double dec_p, int64_t n, const double* l, const double* m,
+                int64_t* pix);
+
+/* Centres of level-J pixels as (l, m, n - 1) in the uvw frame of (ra_p, dec_p).
+ * pix, l, m, nm1 [n] HOST.  For a centre behind the phase centre's
+ * hemisphere n - 1 < -1. */
+int swv_pixel_centres(int J, double ra_p, double dec_p, int64_t n, const int64_t* pix,
+                      double* l, double* m, double* nm1);
+
+/* Sorted level-J pixels whose centres lie within `radius` radians of the
+ * phase centre, with their centres (l, m, n - 1).  At most `cap` entries are
+ * written to the HOST arrays; *n_out receives the full count (call with
+ * cap = 0 to size the arrays). */
+int swv_pixels_in_disk(int J, double ra_p, double dec_p, double radius, int64_t cap,
+                       int64_t* pix, double* l, double* m, double* nm1, int64_t* n_out);
+
+/* -------------------------------------------- major cycle: subtract, image --- */
+
+/* Subtract step of the major cycle (section 2.2):
+ *     resid_out[j] = vis_obs[j] - vis_model[j],
+ *     *chi2_out = inv_sigma2 * sum_j |resid_out[j]|^2   (deterministic order).
+ * vis_obs, vis_model, resid_out [n_vis] DEVICE complex128 (resid_out may alias
+ * vis_obs); chi2_out DEVICE, one FP64. */
+int swv_residual_chi2(swv_ctx ctx, int64_t n_vis, const void* vis_obs, const void* vis_model,
+                      double inv_sigma2, void* resid_out, double* chi2_out);
+
+/* Exact adjoint of the direct sum on a pixel set (the residual image on the
+ * sphere pixels; replaces the grid + inverse FFT of section 2.2's third
+ * step):
+ *     img_out[p] = sum_j conj(e_jp) * y[j].
+ * u, v, w, y [n_vis] DEVICE (y complex128); l, m, nm1 [n_pix] DEVICE (pixel
+ * centres, n - 1 given explicitly); img_out [n_pix] DEVICE complex128 for
+ * both precisions (SWV_F32C: FP32 sincos and products, Kahan sums per
+ * visibility chunk).  Deterministic: fixed chunking and summation order.
+ * Uses a workspace of 16 * n_pix * ceil(n_vis / chunk) bytes. */
+int swv_adjoint(swv_ctx ctx, int64_t n_vis, const double* u, const double* v, const double* w,
+                const void* y, int64_t n_pix, const double* l, const double* m,
+                const double* nm1, int sign, int prec, void* img_out);
+
+/* Gradient of  alpha * Re sum_j conj(y_j) V_j(theta)  with respect to the real
+ * parameters theta = (flux_k, l_k, m_k) of the direct sum (Eq. 12):
+ *     d_flux[k] = alpha Re sum_j conj(y_j) e_jk
+ *     d_l[k]    = alpha Re sum_j conj(y_j) flux_k s 2 pi i (u_j - w_j l_k / n_k) e_jk
+ *     d_m[k]    = alpha Re sum_j conj(y_j) flux_k s 2 pi i (v_j - w_j m_k / n_k) e_jk
+ * y = residuals and alpha = -2/sigma^2 give d(chi^2); y = dL/dV* and alpha = 1
+ * give the backward of a real loss.  All arrays DEVICE; FP64.  Deterministic. */
+int swv_grad_direct(swv_ctx ctx, int64_t n_vis, const double* u, const double* v,
+                    const double* w, const void* y, int64_t n_comp, const double* l,
+                    const double* m, const double* flux, int sign, double alpha,
+                    double* d_flux, double* d_l, double* d_m);
+
+/* ------------------------------------------------------------ batched --- */
+
+/* One prediction instance (a channel x pointing), all pointers DEVICE except
+ * `tree`.  route SWV_ROUTE_DIRECT uses (n_comp, l, m, flux); SWV_ROUTE_TREE
+ * uses `tree`.  vis_out is complex128 (SWV_FP64) or complex64 (SWV_F32C,
+ * direct route only). */
+typedef struct {
+    int route;
+    int prec;
+    int sign;
+    int64_t n_vis;
+    const double* u;
+    const double* v;
+    const double* w;
+    int64_t n_comp;
+    const double* l;
+    const double* m;
+    const double* flux;
+    swv_tree tree;
+    void* vis_out;
+} swv_instance;
+
+typedef struct {
+    int64_t n_instances;
+    int64_t n_items;          /* (instance, visibility tile) work items */
+    int64_t total_terms;      /* sum over instances of n_vis * terms */
+    int tile_rows;            /* visibilities per work item */
+    int grid_blocks;          /* persistent blocks launched */
+    int block_threads;
+} swv_plan_stats_t;
+
+/* Plans one persistent launch per route over many instances: packs every
+ * instance's components (direct) and uploads every tree, splits each
+ * instance into visibility tiles and orders the (instance, tile) work items
+ * by decreasing cost (longest-processing-time first).  Workgroups take items
+ * from a device counter, so uneven instances balance across the chip.  The
+ * tile shape comes from the context's tuning table.  `inst` [n] HOST; the
+ * device buffers they name must outlive the plan. */
+int swv_batch_plan(swv_ctx ctx, int n, const swv_instance* inst, swv_plan* out);
+
+int swv_plan_stats(swv_plan plan, swv_plan_stats_t* out);
+
+/* Enqueues the planned prediction on the context's stream. */
+int swv_batch_run(swv_plan plan);
+
+/* Captures the planned prediction (counter reset by a kernel, then the
+ * persistent launches) into a HIP graph on the context's stream. */
+int swv_graph_capture(swv_plan plan, swv_graph* out);
+
+/* Replays a captured graph on the context's stream. */
+int swv_graph_launch(swv_graph graph);
+
+int swv_graph_destroy(swv_graph graph);
+int swv_plan_destroy(swv_plan plan);
+
+/* ------------------------------------------------------------- tuning --- */
+
+/* Times every compiled tile shape of each kernel family (direct FP64,
+ * direct F32C, tree, adjoint) on synthetic inputs of two size classes, keeps
+ * the fastest per (family, size class) in the context's tuning table and, if
+ * `cache_path` is not NULL, writes the table there as JSON.  flags: 0 =
+ * full sweep, 1 = quick sweep (fewer repetitions). */
+int swv_autotune(swv_ctx ctx, const char* cache_path, int flags);
+
+/* Loads a tuning table written by swv_autotune into the context. */
+int swv_tune_load(swv_ctx ctx, const char* cache_path);
+
+/* Tile shape the context will use: family 0 direct FP64, 1 direct F32C,
+ * 2 tree, 3 adjoint; size class 0 (< 2^20 rows) or 1.  Writes rows per lane
+ * (or pixels per lane for the adjoint) and threads per block. */
+int swv_tune_get(swv_ctx ctx, int family, int size_class, int* per_lane, int* block);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWVIS_H */

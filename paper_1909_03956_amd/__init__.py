@@ -1,0 +1,11 @@
+"""Model-visibility prediction on MI355X (gfx950): the direct component sum and
+the spherical-Haar-wavelet tree of Skipper, Scaife & McEwen (2019), with the
+exact adjoint and chi^2 gradients, behind the C ABI of libswvis.so
+(include/swvis.h).  This package only marshals torch tensors into that
+library; the library must be built (build.py) -- there is no CPU fallback.
+"""
+from ._lib import SwvError, lib  # noqa: F401
+from .api import (Context, Tree, adjoint, ang2pix, context, grad_direct,  # noqa: F401
+                  pixel_centres, pixels_in_disk, predict_direct, residual_chi2, synchronize)
+
+__version__ = "1.0"

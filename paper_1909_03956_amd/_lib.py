@@ -1,0 +1,104 @@
+"""ctypes declarations of libswvis.so (include/swvis.h).  Marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libswvis.so")
+
+SWV_OK, SWV_EINVAL, SWV_EDOMAIN, SWV_ENOMEM, SWV_EHIP, SWV_ENOTSUP = 0, -1, -2, -3, -4, -5
+SWV_FP64, SWV_F32C = 0, 1
+SWV_ROUTE_DIRECT, SWV_ROUTE_TREE = 0, 1
+SWV_MAX_LEVEL = 29
+STATUS_NAMES = {0: "SWV_OK", -1: "SWV_EINVAL", -2: "SWV_EDOMAIN", -3: "SWV_ENOMEM",
+                -4: "SWV_EHIP", -5: "SWV_ENOTSUP"}
+
+
+class SwvError(RuntimeError):
+    """A libswvis call returned a negative status."""
+
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {message}")
+        self.code = code
+        self.message = message
+
+
+class TreeStats(C.Structure):
+    _fields_ = [("J", C.c_int), ("n_comp", C.c_int64), ("n_leaves", C.c_int64),
+                ("n_internal", C.c_int64), ("n_nodes", C.c_int64 * (SWV_MAX_LEVEL + 1)),
+                ("n_records", C.c_int64), ("sparsity", C.c_double),
+                ("build_seconds", C.c_double)]
+
+
+class PlanStats(C.Structure):
+    _fields_ = [("n_instances", C.c_int64), ("n_items", C.c_int64),
+                ("total_terms", C.c_int64), ("tile_rows", C.c_int),
+                ("grid_blocks", C.c_int), ("block_threads", C.c_int)]
+
+
+class Instance(C.Structure):
+    _fields_ = [("route", C.c_int), ("prec", C.c_int), ("sign", C.c_int),
+                ("n_vis", C.c_int64), ("u", C.c_void_p), ("v", C.c_void_p), ("w", C.c_void_p),
+                ("n_comp", C.c_int64), ("l", C.c_void_p), ("m", C.c_void_p),
+                ("flux", C.c_void_p), ("tree", C.c_void_p), ("vis_out", C.c_void_p)]
+
+
+_vp, _i64, _int, _dbl = C.c_void_p, C.c_int64, C.c_int, C.c_double
+_pvp = C.POINTER(C.c_void_p)
+
+SIGNATURES = {
+    "swv_version": [C.POINTER(C.c_int), C.POINTER(C.c_int)],
+    "swv_ctx_create": [_int, _vp, _pvp],
+    "swv_ctx_set_stream": [_vp, _vp],
+    "swv_ctx_synchronize": [_vp],
+    "swv_ctx_destroy": [_vp],
+    "swv_predict_direct": [_vp, _i64, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _int, _int, _vp],
+    "swv_tree_build": [_int, _dbl, _dbl, _i64, _vp, _vp, _vp, _pvp],
+    "swv_tree_stats": [_vp, C.POINTER(TreeStats)],
+    "swv_tree_leaves": [_vp, _vp, _vp, _vp, _vp, _vp],
+    "swv_tree_level": [_vp, _int, _vp, _vp, _vp, _vp],
+    "swv_predict_tree": [_vp, _vp, _i64, _vp, _vp, _vp, _int, _int, _vp],
+    "swv_tree_destroy": [_vp],
+    "swv_ang2pix": [_int, _dbl, _dbl, _i64, _vp, _vp, _vp],
+    "swv_pixel_centres": [_int, _dbl, _dbl, _i64, _vp, _vp, _vp, _vp],
+    "swv_pixels_in_disk": [_int, _dbl, _dbl, _dbl, _i64, _vp, _vp, _vp, _vp, C.POINTER(_i64)],
+    "swv_residual_chi2": [_vp, _i64, _vp, _vp, _dbl, _vp, _vp],
+    "swv_adjoint": [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _int, _int, _vp],
+    "swv_grad_direct": [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _int, _dbl,
+                        _vp, _vp, _vp],
+    "swv_batch_plan": [_vp, _int, C.POINTER(Instance), _pvp],
+    "swv_plan_stats": [_vp, C.POINTER(PlanStats)],
+    "swv_batch_run": [_vp],
+    "swv_graph_capture": [_vp, _pvp],
+    "swv_graph_launch": [_vp],
+    "swv_graph_destroy": [_vp],
+    "swv_plan_destroy": [_vp],
+    "swv_autotune": [_vp, C.c_char_p, _int],
+    "swv_tune_load": [_vp, C.c_char_p],
+    "swv_tune_get": [_vp, _int, _int, C.POINTER(C.c_int), C.POINTER(C.c_int)],
+}
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded library.  Raises if it is not built: there is no fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run "
+                               "`python paper_1909_03956_amd/build.py` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        for name, args in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.swv_last_error.argtypes = []
+        L.swv_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(rc: int) -> None:
+    if rc != SWV_OK:
+        raise SwvError(rc, lib().swv_last_error().decode(errors="replace"))

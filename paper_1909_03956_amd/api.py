@@ -1,0 +1,307 @@
+"""Torch-facing wrappers of libswvis.  Torch supplies device memory and the
+stream; every step of the computation runs in the library's kernels."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from ._lib import (SWV_F32C, SWV_FP64, Instance, PlanStats, TreeStats,
+                   check, lib)
+
+PRECISIONS = {"fp64": SWV_FP64, "f32c": SWV_F32C}
+
+
+def _prec(p) -> int:
+    if isinstance(p, int):
+        return p
+    try:
+        return PRECISIONS[p]
+    except KeyError:
+        raise ValueError(f"precision must be one of {sorted(PRECISIONS)}") from None
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr() if t is not None and t.numel() else 0)
+
+
+def _dev_f64(t, name, device=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU device")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if t.dim() != 1:
+        raise ValueError(f"{name} must be 1-D")
+    return t.contiguous()
+
+
+def _dev_c128(t, name, device):
+    if not isinstance(t, torch.Tensor) or t.device != device or t.dtype != torch.complex128:
+        raise TypeError(f"{name} must be a complex128 tensor on {device}")
+    if t.dim() != 1:
+        raise ValueError(f"{name} must be 1-D")
+    return t.contiguous()
+
+
+def _host_f64(x):
+    if isinstance(x, torch.Tensor):
+        x = x.detach().cpu().numpy()
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def _np_ptr(a) -> C.c_void_p:
+    return C.c_void_p(a.ctypes.data if a.size else 0)
+
+
+class Context:
+    """A libswvis context on one device and one stream."""
+
+    def __init__(self, device=None, stream=None):
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        self.device = dev
+        self.stream = stream
+        self._h = C.c_void_p()
+        check(lib().swv_ctx_create(dev.index, C.c_void_p(stream.cuda_stream), C.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def synchronize(self):
+        """Waits for the stream and raises the first deferred kernel error."""
+        check(lib().swv_ctx_synchronize(self._h))
+
+    def tune_get(self, family: int, size_class: int):
+        pl, bl = C.c_int(), C.c_int()
+        check(lib().swv_tune_get(self._h, family, size_class, C.byref(pl), C.byref(bl)))
+        return pl.value, bl.value
+
+    def autotune(self, cache_path=None, quick=False):
+        p = cache_path.encode() if cache_path else None
+        check(lib().swv_autotune(self._h, p, 1 if quick else 0))
+
+    def tune_load(self, cache_path):
+        check(lib().swv_tune_load(self._h, cache_path.encode()))
+
+    def close(self):
+        if self._h:
+            lib().swv_ctx_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_CONTEXTS: dict = {}
+
+
+def context(device=None) -> Context:
+    """The cached context for a device and torch's current stream on it."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None \
+        else torch.device(device)
+    if dev.index is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+    st = torch.cuda.current_stream(dev)
+    key = (dev.index, st.cuda_stream)
+    ctx = _CONTEXTS.get(key)
+    if ctx is None:
+        ctx = _CONTEXTS[key] = Context(dev, st)
+    return ctx
+
+
+# ---------------------------------------------------------------- direct --
+def predict_direct(u, v, w, l, m, flux, sign: int = -1, prec="fp64", out=None):
+    """V_j = sum_k flux_k exp(s 2 pi i (u_j l_k + v_j m_k + w_j (n_k - 1))) (Eq. 12).
+
+    u, v, w, l, m, flux: 1-D float64 tensors on one GPU.  Returns complex128
+    (prec "fp64") or complex64 ("f32c")."""
+    u = _dev_f64(u, "u")
+    dev = u.device
+    v, w = _dev_f64(v, "v", dev), _dev_f64(w, "w", dev)
+    l, m, flux = _dev_f64(l, "l", dev), _dev_f64(m, "m", dev), _dev_f64(flux, "flux", dev)
+    n, k = u.numel(), l.numel()
+    if v.numel() != n or w.numel() != n or m.numel() != k or flux.numel() != k:
+        raise ValueError("length mismatch")
+    p = _prec(prec)
+    dt = torch.complex128 if p == SWV_FP64 else torch.complex64
+    if out is None:
+        out = torch.empty(n, dtype=dt, device=dev)
+    elif out.dtype != dt or out.numel() != n or not out.is_contiguous() or out.device != dev:
+        raise ValueError("out has the wrong dtype, size or device")
+    ctx = context(dev)
+    check(lib().swv_predict_direct(ctx.handle, n, _ptr(u), _ptr(v), _ptr(w), k, _ptr(l),
+                                   _ptr(m), _ptr(flux), sign, p, _ptr(out)))
+    return out
+
+
+# ------------------------------------------------------------------ tree --
+class Tree:
+    """Sparse spherical-Haar coefficient tree of a component list (built on the host)."""
+
+    def __init__(self, J: int, ra_p: float, dec_p: float, l, m, flux):
+        l, m, flux = _host_f64(l), _host_f64(m), _host_f64(flux)
+        if not (l.shape == m.shape == flux.shape and l.ndim == 1):
+            raise ValueError("l, m, flux must be 1-D of one length")
+        self._h = C.c_void_p()
+        check(lib().swv_tree_build(int(J), float(ra_p), float(dec_p), l.size, _np_ptr(l),
+                                   _np_ptr(m), _np_ptr(flux), C.byref(self._h)))
+        self.J, self.ra_p, self.dec_p = int(J), float(ra_p), float(dec_p)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self) -> dict:
+        s = TreeStats()
+        check(lib().swv_tree_stats(self._h, C.byref(s)))
+        return {"J": s.J, "n_comp": s.n_comp, "n_leaves": s.n_leaves,
+                "n_internal": s.n_internal,
+                "nodes_per_level": [s.n_nodes[j] for j in range(1, s.J + 1)],
+                "n_records": s.n_records, "sparsity": s.sparsity,
+                "build_seconds": s.build_seconds}
+
+    def leaves(self) -> dict:
+        n = self.stats()["n_leaves"]
+        pix = np.empty(n, np.int64)
+        arrs = [np.empty(n) for _ in range(4)]
+        check(lib().swv_tree_leaves(self._h, _np_ptr(pix), *[_np_ptr(a) for a in arrs]))
+        return {"pix": pix, "l": arrs[0], "m": arrs[1], "nm1": arrs[2], "flux": arrs[3]}
+
+    def level(self, j: int) -> dict:
+        n = self.stats()["nodes_per_level"][j - 1]
+        pix = np.empty(n, np.int64)
+        mask = np.empty(n, np.int32)
+        lam = np.empty(n)
+        gam = np.empty((n, 3))
+        check(lib().swv_tree_level(self._h, j, _np_ptr(pix), _np_ptr(mask), _np_ptr(lam),
+                                   _np_ptr(gam)))
+        return {"pix": pix, "mask": mask, "lambda": lam, "gamma": gam}
+
+    def predict(self, u, v, w, sign: int = -1, prec="fp64", out=None):
+        """Model visibilities by the wavelet route (Eqs. 14-17); complex128."""
+        u = _dev_f64(u, "u")
+        dev = u.device
+        v, w = _dev_f64(v, "v", dev), _dev_f64(w, "w", dev)
+        n = u.numel()
+        if v.numel() != n or w.numel() != n:
+            raise ValueError("length mismatch")
+        if out is None:
+            out = torch.empty(n, dtype=torch.complex128, device=dev)
+        ctx = context(dev)
+        check(lib().swv_predict_tree(ctx.handle, self._h, n, _ptr(u), _ptr(v), _ptr(w), sign,
+                                     _prec(prec), _ptr(out)))
+        return out
+
+    def close(self):
+        if self._h:
+            lib().swv_tree_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- pixels --
+def ang2pix(J, ra_p, dec_p, l, m) -> np.ndarray:
+    l, m = _host_f64(l), _host_f64(m)
+    pix = np.empty(l.size, np.int64)
+    check(lib().swv_ang2pix(int(J), float(ra_p), float(dec_p), l.size, _np_ptr(l), _np_ptr(m),
+                            _np_ptr(pix)))
+    return pix
+
+
+def pixel_centres(J, ra_p, dec_p, pix):
+    pix = np.ascontiguousarray(np.asarray(pix, np.int64))
+    out = [np.empty(pix.size) for _ in range(3)]
+    check(lib().swv_pixel_centres(int(J), float(ra_p), float(dec_p), pix.size, _np_ptr(pix),
+                                  *[_np_ptr(a) for a in out]))
+    return tuple(out)
+
+
+def pixels_in_disk(J, ra_p, dec_p, radius):
+    """(pix, l, m, nm1) of the level-J pixels within `radius` of the phase centre."""
+    n = C.c_int64()
+    z = C.c_void_p(0)
+    check(lib().swv_pixels_in_disk(int(J), float(ra_p), float(dec_p), float(radius), 0, z, z, z,
+                                   z, C.byref(n)))
+    pix = np.empty(n.value, np.int64)
+    arrs = [np.empty(n.value) for _ in range(3)]
+    check(lib().swv_pixels_in_disk(int(J), float(ra_p), float(dec_p), float(radius), n.value,
+                                   _np_ptr(pix), *[_np_ptr(a) for a in arrs], C.byref(n)))
+    return pix, arrs[0], arrs[1], arrs[2]
+
+
+# ------------------------------------------------- subtract, image, grads --
+def residual_chi2(vis_obs, vis_model, inv_sigma2: float, out=None):
+    """(V_obs - V_model, chi^2 as a 1-element float64 tensor)."""
+    dev = vis_obs.device
+    vis_obs = _dev_c128(vis_obs, "vis_obs", dev)
+    vis_model = _dev_c128(vis_model, "vis_model", dev)
+    n = vis_obs.numel()
+    if vis_model.numel() != n:
+        raise ValueError("length mismatch")
+    resid = torch.empty_like(vis_obs) if out is None else out
+    chi2 = torch.empty(1, dtype=torch.float64, device=dev)
+    ctx = context(dev)
+    check(lib().swv_residual_chi2(ctx.handle, n, _ptr(vis_obs), _ptr(vis_model),
+                                  float(inv_sigma2), _ptr(resid), _ptr(chi2)))
+    return resid, chi2
+
+
+def adjoint(u, v, w, y, l, m, nm1, sign: int = -1, prec="fp64"):
+    """x_p = sum_j conj(e_jp) y_j on the pixel set (l, m, n - 1); complex128."""
+    u = _dev_f64(u, "u")
+    dev = u.device
+    v, w = _dev_f64(v, "v", dev), _dev_f64(w, "w", dev)
+    y = _dev_c128(y, "y", dev)
+    l, m, nm1 = _dev_f64(l, "l", dev), _dev_f64(m, "m", dev), _dev_f64(nm1, "nm1", dev)
+    n, P = u.numel(), l.numel()
+    if v.numel() != n or w.numel() != n or y.numel() != n or m.numel() != P or nm1.numel() != P:
+        raise ValueError("length mismatch")
+    out = torch.empty(P, dtype=torch.complex128, device=dev)
+    ctx = context(dev)
+    check(lib().swv_adjoint(ctx.handle, n, _ptr(u), _ptr(v), _ptr(w), _ptr(y), P, _ptr(l),
+                            _ptr(m), _ptr(nm1), sign, _prec(prec), _ptr(out)))
+    return out
+
+
+def grad_direct(u, v, w, y, l, m, flux, sign: int = -1, alpha: float = 1.0):
+    """Gradient of alpha Re sum_j conj(y_j) V_j with respect to (flux, l, m)."""
+    u = _dev_f64(u, "u")
+    dev = u.device
+    v, w = _dev_f64(v, "v", dev), _dev_f64(w, "w", dev)
+    y = _dev_c128(y, "y", dev)
+    l, m, flux = _dev_f64(l, "l", dev), _dev_f64(m, "m", dev), _dev_f64(flux, "flux", dev)
+    n, k = u.numel(), l.numel()
+    if v.numel() != n or w.numel() != n or y.numel() != n or m.numel() != k or flux.numel() != k:
+        raise ValueError("length mismatch")
+    outs = [torch.empty(k, dtype=torch.float64, device=dev) for _ in range(3)]
+    ctx = context(dev)
+    check(lib().swv_grad_direct(ctx.handle, n, _ptr(u), _ptr(v), _ptr(w), _ptr(y), k, _ptr(l),
+                                _ptr(m), _ptr(flux), sign, float(alpha),
+                                *[_ptr(o) for o in outs]))
+    return tuple(outs)
+
+
+def synchronize(device=None):
+    """Waits for the current stream and raises deferred kernel errors."""
+    context(device).synchronize()
+
+
+__all__ = ["Context", "context", "predict_direct", "Tree", "ang2pix", "pixel_centres",
+           "pixels_in_disk", "residual_chi2", "adjoint", "grad_direct", "synchronize",
+           "Instance", "PlanStats"]

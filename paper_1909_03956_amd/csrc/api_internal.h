@@ -1,0 +1,50 @@
+// Host-runtime internals shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "launch.h"
+#include "tree.h"
+
+namespace swv {
+
+// Kernel families of the tuning table.
+enum { kFamDirect64 = 0, kFamDirect32 = 1, kFamTree = 2, kFamAdjoint = 3, kFamilies = 4 };
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t n = 0;
+};
+
+struct DeviceGuard {
+    int prev = 0;
+    bool ok = false;
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+};
+
+}  // namespace swv
+
+struct swv_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    swv::DevBuf comp;       // packed components
+    swv::DevBuf partial;    // per-chunk partial sums (adjoint, gradients)
+    swv::DevBuf partial2;   // per-block chi^2 partials
+    int* d_status = nullptr;  // deferred-error bits raised by kernels
+    int n_cu = 256;
+    int per_lane[swv::kFamilies][2];
+    int block[swv::kFamilies][2];
+};
+
+namespace swv {
+
+int hip_fail(hipError_t e, const char* what);
+int ensure(swv_ctx ctx, DevBuf& b, size_t bytes);
+void tune_defaults(swv_ctx ctx);
+int size_class(int64_t rows);
+int check_sign_prec(int sign, int prec, bool allow_f32);
+int upload_tree(swv_ctx ctx, swv_tree t, const TRec** out);
+TreeArgs tree_args(swv_tree t, const TRec* d_rec);
+
+}  // namespace swv

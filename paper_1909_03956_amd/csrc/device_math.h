@@ -1,0 +1,71 @@
+// Per-term arithmetic of every kernel: the reduced phase and its complex
+// exponential.
+//
+// Phase (section 3.3, Eq. 12 with P = [0, 0, 1]), in cycles:
+//     phi = u l + v m + w (n - 1)
+// evaluated with two FMAs and one multiply, then reduced exactly to
+// r = phi - rint(phi) in [-1/2, 1/2] (the subtraction is exact).
+//
+// Phasor: with x = (pi/2) r, |x| <= pi/4, s = sin x and c = cos x come from
+// the fitted polynomials of sincos_coeffs.h, and the full angle 4x = 2 pi r
+// from the identities
+//     cos 4x = 1 - 8 (s c)^2,      sin 4x = 4 (s c)(c^2 - s^2).
+// cis2pi_q returns cos(2 pi r) and q = sin(2 pi r) / 4: callers fold the
+// factor 4 (a power of two, so exactly) into their accumulators.
+//
+// Operation count per phasor: 1 (r^2) + 7 (sine polynomial) + 6 (cosine
+// polynomial) + 6 (the 4x identities) = 20 VALU instructions, 14 of them FMAs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "sincos_coeffs.h"
+
+namespace swv {
+
+__host__ __device__ __forceinline__ double reduced_phase(double u, double v, double w, double l,
+                                                         double m, double nm1) {
+    const double ph = fma(u, l, fma(v, m, w * nm1));
+    return ph - rint(ph);
+}
+
+__host__ __device__ __forceinline__ void cis2pi_q(double r, double& c, double& q) {
+    const double t = r * r;
+    double ps = kS64[6];
+    ps = fma(ps, t, kS64[5]);
+    ps = fma(ps, t, kS64[4]);
+    ps = fma(ps, t, kS64[3]);
+    ps = fma(ps, t, kS64[2]);
+    ps = fma(ps, t, kS64[1]);
+    ps = fma(ps, t, kS64[0]);
+    double pc = kC64[5];
+    pc = fma(pc, t, kC64[4]);
+    pc = fma(pc, t, kC64[3]);
+    pc = fma(pc, t, kC64[2]);
+    pc = fma(pc, t, kC64[1]);
+    pc = fma(pc, t, kC64[0]);
+    const double s1 = r * ps;
+    const double c1 = fma(pc, t, 1.0);
+    const double p = s1 * c1;
+    const double d = fma(c1, c1, -(s1 * s1));
+    c = fma(-8.0 * p, p, 1.0);
+    q = p * d;
+}
+
+// FP32 phasor of a reduced phase |r| <= 1/2 in cycles: cos(2 pi r), sin(2 pi r)
+// from the hardware transcendental unit (v_cos_f32 / v_sin_f32 take the angle
+// in revolutions and are valid on [-256, 256]).
+__device__ __forceinline__ void cis2pi_f32(float r, float& c, float& s) {
+    c = __builtin_amdgcn_cosf(r);
+    s = __builtin_amdgcn_sinf(r);
+}
+
+// Kahan-compensated accumulation of x into (sum, comp).
+__host__ __device__ __forceinline__ void kahan_add(float x, float& sum, float& comp) {
+    const float y = x - comp;
+    const float t = sum + y;
+    comp = (t - sum) - y;
+    sum = t;
+}
+
+}  // namespace swv

@@ -1,0 +1,296 @@
+// Major-cycle kernels around the prediction: the subtract step with chi^2
+// (section 2.2), the exact adjoint of the direct sum (the residual image on
+// sphere pixels), and the chi^2 gradients of the direct sum.
+//
+// Adjoint and gradients swap the roles of the direct kernel: lanes own the
+// outputs (pixels or components) and every lane of the wave walks the same
+// visibility rows, read with scalar loads.  The visibility axis is split
+// into fixed chunks (grid.y); each (tile, chunk) block writes its partial
+// sums, and a second kernel adds the chunks in index order -- deterministic
+// and free of atomics.
+#include "device_math.h"
+#include "launch.h"
+
+namespace swv {
+
+// ---------------------------------------------------------------- adjoint --
+// img[p] = sum_j conj(e_jp) y_j, e = exp(s 2 pi i phi).  With e = c + i s S:
+// conj(e) y = (c yr + s S yi) + i (c yi - s S yr), S = 4 q.
+template <int PPL, int BLOCK, int PREC>
+__global__ __launch_bounds__(BLOCK) void k_adjoint(
+    const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
+    const double2* __restrict__ y, int64_t n_vis, int64_t chunk, const double* __restrict__ pl,
+    const double* __restrict__ pm, const double* __restrict__ pn, int64_t n_pix, double sgn,
+    double2* __restrict__ partial) {
+    const int64_t p0 = (int64_t)blockIdx.x * (BLOCK * PPL) + threadIdx.x;
+    double L[PPL], M[PPL], N[PPL];
+    double ar[PPL], ai[PPL];
+    float sr[PPL], cr[PPL], si[PPL], ci[PPL];
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+        int64_t p = p0 + (int64_t)i * BLOCK;
+        p = p < n_pix ? p : n_pix - 1;
+        L[i] = pl[p];
+        M[i] = pm[p];
+        N[i] = pn[p];
+        ar[i] = ai[i] = 0.0;
+        sr[i] = cr[i] = si[i] = ci[i] = 0.0f;
+    }
+    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j1 = j0 + chunk < n_vis ? j0 + chunk : n_vis;
+    const auto* U = uniform_ptr(u);
+    const auto* V = uniform_ptr(v);
+    const auto* W = uniform_ptr(w);
+    const auto* Y = uniform_ptr(y);
+    for (int64_t j = j0; j < j1; ++j) {
+        const double uj = U[j], vj = V[j], wj = W[j];
+        const double yr = Y[j].x, yi = Y[j].y;
+        if constexpr (PREC == SWV_FP64) {
+            const double y4r = 4.0 * sgn * yr, y4i = 4.0 * sgn * yi;
+#pragma unroll
+            for (int i = 0; i < PPL; ++i) {
+                double c, q;
+                cis2pi_q(reduced_phase(uj, vj, wj, L[i], M[i], N[i]), c, q);
+                ar[i] = fma(c, yr, ar[i]);
+                ar[i] = fma(q, y4i, ar[i]);
+                ai[i] = fma(c, yi, ai[i]);
+                ai[i] = fma(-q, y4r, ai[i]);
+            }
+        } else {
+            const float fyr = (float)yr, fyi = (float)yi;
+            const float fsyr = (float)(sgn * yr), fsyi = (float)(sgn * yi);
+#pragma unroll
+            for (int i = 0; i < PPL; ++i) {
+                const float r = (float)reduced_phase(uj, vj, wj, L[i], M[i], N[i]);
+                float c, s;
+                cis2pi_f32(r, c, s);
+                kahan_add(fmaf(c, fyr, s * fsyi), sr[i], cr[i]);
+                kahan_add(fmaf(c, fyi, -(s * fsyr)), si[i], ci[i]);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < PPL; ++i) {
+        const int64_t p = p0 + (int64_t)i * BLOCK;
+        if (p < n_pix) {
+            double2 o;
+            if constexpr (PREC == SWV_FP64)
+                o = make_double2(ar[i], ai[i]);
+            else
+                o = make_double2((double)sr[i] - (double)cr[i], (double)si[i] - (double)ci[i]);
+            partial[(int64_t)blockIdx.y * n_pix + p] = o;
+        }
+    }
+}
+
+// out[p] = sum over chunks c (in order) of partial[c][p]
+__global__ void k_sum_chunks_c128(const double2* __restrict__ partial, int64_t n_chunks,
+                                  int64_t n, double2* __restrict__ out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double re = 0.0, im = 0.0;
+    for (int64_t c = 0; c < n_chunks; ++c) {
+        const double2 x = partial[c * n + p];
+        re += x.x;
+        im += x.y;
+    }
+    out[p] = make_double2(re, im);
+}
+
+template <int PPL, int BLOCK, int PREC>
+static void run_adjoint(hipStream_t s, dim3 grid, int64_t chunk, int64_t n_vis, const double* u,
+                        const double* v, const double* w, const void* y, int64_t n_pix,
+                        const double* l, const double* m, const double* nm1, int sign,
+                        void* partial) {
+    k_adjoint<PPL, BLOCK, PREC><<<grid, dim3(BLOCK), 0, s>>>(
+        u, v, w, (const double2*)y, n_vis, chunk, l, m, nm1, n_pix, (double)sign,
+        (double2*)partial);
+}
+
+template <int PPL, int PREC>
+static hipError_t run_adjoint_b(hipStream_t s, int block, dim3 grid, int64_t chunk,
+                                int64_t n_vis, const double* u, const double* v, const double* w,
+                                const void* y, int64_t n_pix, const double* l, const double* m,
+                                const double* nm1, int sign, void* partial) {
+    switch (block) {
+        case 64: run_adjoint<PPL, 64, PREC>(s, grid, chunk, n_vis, u, v, w, y, n_pix, l, m, nm1, sign, partial); break;
+        case 128: run_adjoint<PPL, 128, PREC>(s, grid, chunk, n_vis, u, v, w, y, n_pix, l, m, nm1, sign, partial); break;
+        case 256: run_adjoint<PPL, 256, PREC>(s, grid, chunk, n_vis, u, v, w, y, n_pix, l, m, nm1, sign, partial); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint(hipStream_t s, int prec, int ppl, int block, int64_t chunk,
+                          int64_t n_vis, const double* u, const double* v, const double* w,
+                          const void* y, int64_t n_pix, const double* l, const double* m,
+                          const double* nm1, int sign, void* partial, void* out) {
+    if (n_pix <= 0) return hipSuccess;
+    const int64_t n_chunks = n_vis > 0 ? (n_vis + chunk - 1) / chunk : 0;
+    if (n_chunks > 0) {
+        const int64_t per_block = (int64_t)block * ppl;
+        const dim3 grid((unsigned)((n_pix + per_block - 1) / per_block), (unsigned)n_chunks);
+        hipError_t e;
+        if (prec == SWV_FP64) {
+            switch (ppl) {
+                case 1: e = run_adjoint_b<1, SWV_FP64>(s, block, grid, chunk, n_vis, u, v, w, y, n_pix, l, m, nm1, sign, partial); break;
+                case 2: e = run_adjoint_b<2, SWV_FP64>(s, block, grid, chunk, n_vis, u, v, w, y, n_pix, l, m, nm1, sign, partial); break;
+                case 4: e = run_adjoint_b<4, SWV_FP64>(s, block, grid, chunk, n_vis, u, v, w, y, n_pix, l, m, nm1, sign, partial); break;
+                default: return hipErrorInvalidValue;
+            }
+        } else {
+            switch (ppl) {
+                case 1: e = run_adjoint_b<1, SWV_F32C>(s, block, grid, chunk, n_vis, u, v, w, y, n_pix, l, m, nm1, sign, partial); break;
+                case 2: e = run_adjoint_b<2, SWV_F32C>(s, block, grid, chunk, n_vis, u, v, w, y, n_pix, l, m, nm1, sign, partial); break;
+                case 4: e = run_adjoint_b<4, SWV_F32C>(s, block, grid, chunk, n_vis, u, v, w, y, n_pix, l, m, nm1, sign, partial); break;
+                default: return hipErrorInvalidValue;
+            }
+        }
+        if (e != hipSuccess) return e;
+    }
+    k_sum_chunks_c128<<<dim3((unsigned)((n_pix + 255) / 256)), dim3(256), 0, s>>>(
+        (const double2*)partial, n_chunks, n_pix, (double2*)out);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------- gradients --
+// Per component k (one per lane) and chunk of rows:
+//   Z0 = sum conj(y) e,  Zu = sum u conj(y) e,  Zv = ..., Zw = ...
+// conj(y) e = (yr - i yi)(c + i s S) = (yr c + yi s S) + i (yr s S - yi c).
+constexpr int kGradBlock = 128;
+
+__global__ __launch_bounds__(kGradBlock) void k_grad_partial(
+    const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
+    const double2* __restrict__ y, int64_t n_vis, int64_t chunk, const Comp* __restrict__ comp,
+    int64_t n_comp, double sgn, double* __restrict__ partial) {
+    const int64_t k0 = (int64_t)blockIdx.x * kGradBlock + threadIdx.x;
+    const int64_t k = k0 < n_comp ? k0 : n_comp - 1;
+    const double L = comp[k].l, M = comp[k].m, N = comp[k].nm1;
+    double z0r = 0, z0i = 0, zur = 0, zui = 0, zvr = 0, zvi = 0, zwr = 0, zwi = 0;
+    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j1 = j0 + chunk < n_vis ? j0 + chunk : n_vis;
+    const auto* U = uniform_ptr(u);
+    const auto* V = uniform_ptr(v);
+    const auto* W = uniform_ptr(w);
+    const auto* Y = uniform_ptr(y);
+    for (int64_t j = j0; j < j1; ++j) {
+        const double uj = U[j], vj = V[j], wj = W[j];
+        const double yr = Y[j].x, yi = Y[j].y;
+        const double y4r = 4.0 * sgn * yr, y4i = 4.0 * sgn * yi;
+        double c, q;
+        cis2pi_q(reduced_phase(uj, vj, wj, L, M, N), c, q);
+        const double zr = fma(q, y4i, yr * c);
+        const double zi = fma(q, y4r, -(yi * c));
+        z0r += zr;
+        z0i += zi;
+        zur = fma(uj, zr, zur);
+        zui = fma(uj, zi, zui);
+        zvr = fma(vj, zr, zvr);
+        zvi = fma(vj, zi, zvi);
+        zwr = fma(wj, zr, zwr);
+        zwi = fma(wj, zi, zwi);
+    }
+    if (k0 < n_comp) {
+        double* o = partial + ((int64_t)blockIdx.y * 8) * n_comp + k0;
+        o[0 * n_comp] = z0r;
+        o[1 * n_comp] = z0i;
+        o[2 * n_comp] = zur;
+        o[3 * n_comp] = zui;
+        o[4 * n_comp] = zvr;
+        o[5 * n_comp] = zvi;
+        o[6 * n_comp] = zwr;
+        o[7 * n_comp] = zwi;
+    }
+}
+
+// d_flux = alpha Re Z0
+// d_l    = alpha I Re[s 2 pi i (Zu - (l/n) Zw)] = -alpha I s 2 pi Im(Zu - (l/n) Zw)
+// d_m    = -alpha I s 2 pi Im(Zv - (m/n) Zw)
+__global__ void k_grad_finish(const double* __restrict__ partial, int64_t n_chunks,
+                              const Comp* __restrict__ comp, int64_t n_comp, double sgn,
+                              double alpha, double* __restrict__ d_flux, double* __restrict__ d_l,
+                              double* __restrict__ d_m) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_comp) return;
+    double z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t c = 0; c < n_chunks; ++c)
+        for (int t = 0; t < 8; ++t) z[t] += partial[(c * 8 + t) * n_comp + k];
+    const double n = 1.0 + comp[k].nm1;
+    const double f = -alpha * comp[k].I * sgn * 2.0 * M_PI;
+    d_flux[k] = alpha * z[0];
+    d_l[k] = f * (z[3] - (comp[k].l / n) * z[7]);
+    d_m[k] = f * (z[5] - (comp[k].m / n) * z[7]);
+}
+
+hipError_t launch_grad(hipStream_t s, int64_t chunk, int64_t n_vis, const double* u,
+                       const double* v, const double* w, const void* y, const Comp* comp,
+                       int64_t n_comp, int sign, double alpha, double* partial, double* d_flux,
+                       double* d_l, double* d_m) {
+    if (n_comp <= 0) return hipSuccess;
+    const int64_t n_chunks = n_vis > 0 ? (n_vis + chunk - 1) / chunk : 0;
+    if (n_chunks > 0) {
+        const dim3 grid((unsigned)((n_comp + kGradBlock - 1) / kGradBlock), (unsigned)n_chunks);
+        k_grad_partial<<<grid, dim3(kGradBlock), 0, s>>>(u, v, w, (const double2*)y, n_vis, chunk,
+                                                         comp, n_comp, (double)sign, partial);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_grad_finish<<<dim3((unsigned)((n_comp + 127) / 128)), dim3(128), 0, s>>>(
+        partial, n_chunks, comp, n_comp, (double)sign, alpha, d_flux, d_l, d_m);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ residual and chi^2 --
+constexpr int kResBlock = 256;
+constexpr int kResMaxBlocks = 2048;
+
+int residual_blocks(int64_t n_vis) {
+    const int64_t b = (n_vis + kResBlock * 8 - 1) / (kResBlock * 8);
+    return (int)(b < 1 ? 1 : (b > kResMaxBlocks ? kResMaxBlocks : b));
+}
+
+__global__ __launch_bounds__(kResBlock) void k_residual(const double2* __restrict__ obs,
+                                                        const double2* __restrict__ model,
+                                                        int64_t n, double2* __restrict__ resid,
+                                                        double* __restrict__ partial) {
+    __shared__ double red[kResBlock];
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kResBlock;
+    for (int64_t j = (int64_t)blockIdx.x * kResBlock + threadIdx.x; j < n; j += stride) {
+        const double2 a = obs[j], b = model[j];
+        const double rr = a.x - b.x, ri = a.y - b.y;
+        resid[j] = make_double2(rr, ri);
+        acc = fma(rr, rr, fma(ri, ri, acc));
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = kResBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_chi2_finish(const double* __restrict__ partial, int nb, double inv_sigma2,
+                              double* __restrict__ chi2) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[b];
+    *chi2 = s * inv_sigma2;
+}
+
+hipError_t launch_residual(hipStream_t s, int64_t n_vis, const void* obs, const void* model,
+                           double inv_sigma2, void* resid, double* partial, double* chi2) {
+    const int nb = n_vis > 0 ? residual_blocks(n_vis) : 0;
+    if (nb > 0) {
+        k_residual<<<dim3(nb), dim3(kResBlock), 0, s>>>((const double2*)obs,
+                                                        (const double2*)model, n_vis,
+                                                        (double2*)resid, partial);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_chi2_finish<<<1, 1, 0, s>>>(partial, nb, inv_sigma2, chi2);
+    return hipGetLastError();
+}
+
+}  // namespace swv

@@ -1,0 +1,155 @@
+// Wavelet-tree route (section 3.3, Eqs. 14-17; section 3.5) on gfx950.
+//
+// Per visibility row (one per lane) the paper's work is: the plane wave at
+// the leaves (eta_J), the plane-wave coefficients up the tree (eta_j and
+// sigma^m_j by Eqs. 9 and 10 applied to the plane wave), and the
+// reconstruction sum of Eq. 17.  Every lane traverses the same tree, so the
+// traversal is wave-uniform: the tree comes as one pre-order stream of
+// 32-byte records read with scalar loads, and the branches on child masks
+// are scalar branches.
+//
+// Depth-first order keeps the live state O(J) per lane: while a subtree is
+// walked, each open ancestor at level j holds its running sums
+//     S = sum_c eta_{j+1,c},   D^m = sum_c s^m_c eta_{j+1,c}   (m = 0, 1, 2)
+// over the children finished so far (4 complex FP64 values).  When the last
+// child returns, the node forms eta_j = S / 4 and sigma^m_j = sqrt(A_j)/4 D^m,
+// adds gamma^m_j sigma^m_j to V, and hands eta_j to its parent.  The level is
+// a template parameter, so each open level's sums live in their own
+// registers; one call site per level (inside a loop over the set bits of the
+// child mask) keeps the code linear in J.  Roots add A_1 lambda_1 eta_1.
+//
+// Imaginary parts are carried divided by 4 (cis2pi_q's convention; every step
+// is linear) and scaled back once at the end.
+#include "device_math.h"
+#include "launch.h"
+
+namespace swv {
+
+using RecPtr = const __attribute__((address_space(4))) TRec*;
+
+template <int LVL, int JMAX>
+__device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const TreeArgs& ta,
+                                     const double u, const double v, const double w, double& er,
+                                     double& ei, double& Vr, double& Vi) {
+    const int me = pos++;
+    if (LVL == JMAX || LVL == J) {
+        // leaf: eta_{J,k} = exp(2 pi i B . (s_k - P))
+        double c, q;
+        cis2pi_q(reduced_phase(u, v, w, rec[me].a, rec[me].b, rec[me].c), c, q);
+        er = c;
+        ei = q;
+        return;
+    }
+    if constexpr (LVL < JMAX) {
+        unsigned mask = (unsigned)rec[me].meta;
+        double Sr = 0.0, Si = 0.0, D0r = 0.0, D0i = 0.0, D1r = 0.0, D1i = 0.0, D2r = 0.0,
+               D2i = 0.0;
+        while (mask) {
+            const int c = __builtin_ctz(mask);
+            mask &= mask - 1;
+            double xr, xi;
+            walk<LVL + 1, JMAX>(rec, pos, J, ta, u, v, w, xr, xi, Vr, Vi);
+            // Eq. 10 signs of child c: gamma^0 (+-+-), gamma^1 (++--), gamma^2 (+--+)
+            const double s0 = (c & 1) ? -1.0 : 1.0;
+            const double s1 = (c & 2) ? -1.0 : 1.0;
+            const double s2 = s0 * s1;
+            Sr += xr;
+            Si += xi;
+            D0r = fma(s0, xr, D0r);
+            D0i = fma(s0, xi, D0i);
+            D1r = fma(s1, xr, D1r);
+            D1i = fma(s1, xi, D1i);
+            D2r = fma(s2, xr, D2r);
+            D2i = fma(s2, xi, D2i);
+        }
+        // eta_j (Eq. 9 on the plane wave) goes up to the parent
+        er = 0.25 * Sr;
+        ei = 0.25 * Si;
+        // sigma^m_j (Eq. 10 on the plane wave), then gamma^m_j sigma^m_j (Eq. 17)
+        const double a = ta.scale[LVL];
+        const double g0 = rec[me].a, g1 = rec[me].b, g2 = rec[me].c;
+        const double s0r = a * D0r, s0i = a * D0i;
+        const double s1r = a * D1r, s1i = a * D1i;
+        const double s2r = a * D2r, s2i = a * D2i;
+        Vr = fma(g0, s0r, Vr);
+        Vi = fma(g0, s0i, Vi);
+        Vr = fma(g1, s1r, Vr);
+        Vi = fma(g1, s1i, Vi);
+        Vr = fma(g2, s2r, Vr);
+        Vi = fma(g2, s2i, Vi);
+    }
+}
+
+template <int JMAX, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_tree(TreeArgs ta, const double* __restrict__ u,
+                                                const double* __restrict__ v,
+                                                const double* __restrict__ w, int64_t n_vis,
+                                                double sgn, double2* __restrict__ out,
+                                                int* __restrict__ status) {
+    const int64_t jrow = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t j = jrow < n_vis ? jrow : n_vis - 1;
+    const double U = u[j], V = v[j], W = w[j];
+    const RecPtr rec = uniform_ptr(ta.rec);
+    double Vr = 0.0, Vi = 0.0;
+    int pos = 0;
+    for (int r = 0; r < ta.n_roots; ++r) {
+        const int root = pos++;
+        double er, ei;
+        walk<1, JMAX>(rec, pos, ta.J, ta, U, V, W, er, ei, Vr, Vi);
+        const double A1lam = rec[root].a;  // A_1 lambda_1
+        Vr = fma(A1lam, er, Vr);
+        Vi = fma(A1lam, ei, Vi);
+    }
+    if (jrow < n_vis) {
+        if (!isfinite(U + V + W)) atomicOr(status, kStatusNonFinite);
+        out[jrow] = make_double2(Vr, 4.0 * sgn * Vi);
+    }
+}
+
+template <int JMAX>
+static hipError_t run_tree(hipStream_t s, int block, const TreeArgs& t, int64_t n_vis,
+                           const double* u, const double* v, const double* w, int sign,
+                           void* out, int* status) {
+    const double sg = (double)sign;
+    switch (block) {
+        case 64:
+            k_tree<JMAX, 64><<<dim3((unsigned)((n_vis + 63) / 64)), dim3(64), 0, s>>>(
+                t, u, v, w, n_vis, sg, (double2*)out, status);
+            break;
+        case 128:
+            k_tree<JMAX, 128><<<dim3((unsigned)((n_vis + 127) / 128)), dim3(128), 0, s>>>(
+                t, u, v, w, n_vis, sg, (double2*)out, status);
+            break;
+        case 256:
+            k_tree<JMAX, 256><<<dim3((unsigned)((n_vis + 255) / 256)), dim3(256), 0, s>>>(
+                t, u, v, w, n_vis, sg, (double2*)out, status);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tree(hipStream_t s, int block, const TreeArgs& t, int64_t n_vis,
+                       const double* u, const double* v, const double* w, int sign, void* out,
+                       int* status) {
+    if (n_vis <= 0) return hipSuccess;
+    // the compiled traversal depth is the tree's J: register use grows with it
+    switch (t.J) {
+        case 1: return run_tree<1>(s, block, t, n_vis, u, v, w, sign, out, status);
+        case 2: return run_tree<2>(s, block, t, n_vis, u, v, w, sign, out, status);
+        case 3: return run_tree<3>(s, block, t, n_vis, u, v, w, sign, out, status);
+        case 4: return run_tree<4>(s, block, t, n_vis, u, v, w, sign, out, status);
+        case 5: return run_tree<5>(s, block, t, n_vis, u, v, w, sign, out, status);
+        case 6: return run_tree<6>(s, block, t, n_vis, u, v, w, sign, out, status);
+        case 7: return run_tree<7>(s, block, t, n_vis, u, v, w, sign, out, status);
+        case 8: return run_tree<8>(s, block, t, n_vis, u, v, w, sign, out, status);
+        case 9: return run_tree<9>(s, block, t, n_vis, u, v, w, sign, out, status);
+        case 10: return run_tree<10>(s, block, t, n_vis, u, v, w, sign, out, status);
+        case 11: return run_tree<11>(s, block, t, n_vis, u, v, w, sign, out, status);
+        case 12: return run_tree<12>(s, block, t, n_vis, u, v, w, sign, out, status);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace swv

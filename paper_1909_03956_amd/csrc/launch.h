@@ -1,0 +1,60 @@
+// Host-side launchers of the gfx950 kernels (internal to libswvis).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace swv {
+
+// Reads through the constant address space: a wave-uniform index then
+// compiles to a scalar (SMEM) load whose result lands in SGPRs and feeds
+// every lane's arithmetic for free.  Only for memory no kernel writes while
+// the reading kernel runs.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* uniform_ptr(const T* p) {
+    return (const __attribute__((address_space(4))) T*)p;
+}
+
+// Tile shapes compiled for each kernel family.
+constexpr int kPerLaneOptions[3] = {1, 2, 4};
+constexpr int kBlockOptions[3] = {64, 128, 256};
+
+hipError_t launch_ingest(hipStream_t s, int64_t n, const double* l, const double* m,
+                         const double* flux, Comp* out, int* status);
+
+hipError_t launch_direct(hipStream_t s, int prec, int vpl, int block, int64_t n_vis,
+                         const double* u, const double* v, const double* w, const Comp* comp,
+                         int64_t n_comp, int sign, void* out, int* status);
+
+struct TreeArgs {
+    const TRec* rec;
+    int n_roots;
+    int J;
+    double scale[SWV_MAX_LEVEL + 1];  // sqrt(A_j) / 4
+};
+
+// Largest J with a compiled register-resident traversal.
+constexpr int kTreeMaxJ = 12;
+
+hipError_t launch_tree(hipStream_t s, int block, const TreeArgs& t, int64_t n_vis,
+                       const double* u, const double* v, const double* w, int sign, void* out,
+                       int* status);
+
+hipError_t launch_adjoint(hipStream_t s, int prec, int ppl, int block, int64_t chunk,
+                          int64_t n_vis, const double* u, const double* v, const double* w,
+                          const void* y, int64_t n_pix, const double* l, const double* m,
+                          const double* nm1, int sign, void* partial, void* out);
+
+hipError_t launch_grad(hipStream_t s, int64_t chunk, int64_t n_vis, const double* u,
+                       const double* v, const double* w, const void* y, const Comp* comp,
+                       int64_t n_comp, int sign, double alpha, double* partial, double* d_flux,
+                       double* d_l, double* d_m);
+
+hipError_t launch_residual(hipStream_t s, int64_t n_vis, const void* obs, const void* model,
+                           double inv_sigma2, void* resid, double* partial, double* chi2);
+
+// Number of blocks launch_residual uses (its partial buffer holds that many doubles).
+int residual_blocks(int64_t n_vis);
+
+}  // namespace swv

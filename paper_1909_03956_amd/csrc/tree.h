@@ -1,0 +1,46 @@
+// Sparse spherical-Haar coefficient tree (sections 3.2-3.5), host side.
+#pragma once
+
+#include <cstdint>
+#include <map>
+#include <vector>
+
+#include "common.h"
+
+namespace swv {
+
+// One level of the tree: the existing nodes in increasing pixel order.
+struct TreeLevel {
+    std::vector<int64_t> pix;         // nested ids, sorted
+    std::vector<int32_t> mask;        // bit c set if child 4k + c exists (level < J)
+    std::vector<int64_t> first_child; // index of the first child in the next level
+    std::vector<double> lambda;       // lambda_{j,k}
+    std::vector<double> gamma;        // gamma^m_{j,k} at [3 k + m] (level < J)
+};
+
+}  // namespace swv
+
+struct swv_tree_s {
+    int J = 0;
+    double ra_p = 0, dec_p = 0;
+    int64_t n_comp = 0;
+    // leaves (level J), sorted by pixel id
+    std::vector<int64_t> leaf_pix;
+    std::vector<double> leaf_l, leaf_m, leaf_nm1, leaf_flux;
+    std::vector<swv::TreeLevel> levels;  // levels[j - 1] is level j
+    // depth-first record stream consumed by the device traversal
+    std::vector<swv::TRec> records;
+    int64_t n_roots = 0;
+    double level_scale[SWV_MAX_LEVEL + 1] = {};  // sqrt(A_j) / 4
+    double build_seconds = 0;
+    // device copies of `records`, one per HIP device id
+    std::map<int, void*> device_records;
+};
+
+namespace swv {
+
+// Builds the tree; returns a status code (message via fail()).
+int build_tree(int J, double ra_p, double dec_p, int64_t n, const double* l, const double* m,
+               const double* flux, swv_tree_s* out);
+
+}  // namespace swv

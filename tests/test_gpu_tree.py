@@ -1,0 +1,132 @@
+"""GPU parity of the wavelet-tree route (Eqs. 14-17) against the oracle.
+
+The oracle builds its own tree (its own pixelisation and centres) and
+evaluates Eq. 17 step by step; the GPU path builds the tree in the library's
+host code and walks it on the device.  Tolerance: E_max <= 1e-12 relative to
+sum |F| (see test_gpu_direct).  A further property test compares the tree
+route with the direct route of the library on the tree's own leaves (Eq. 16
+= Eq. 17) at the full measured size."""
+import numpy as np
+import pytest
+
+from oracle import tree as ot
+from synth import configs
+
+from .gpu_util import dev, errors, fp64_row_bound, host, note, require_gpu
+
+pytestmark = pytest.mark.gpu
+TOL64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def env():
+    return require_gpu()
+
+
+def _tree_run(env, J, ra, dec, l, m, f, u, v, w, sign=-1):
+    torch, swv = env
+    t = swv.Tree(J, ra, dec, l, m, f)
+    out = t.predict(dev(u, torch), dev(v, torch), dev(w, torch), sign=sign)
+    swv.synchronize()
+    return t, host(out)
+
+
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_cfg1_tree_full(env, sign):
+    W = configs.CFG1
+    u, v, w = W.track.uvw()
+    l, m, f = W.components()
+    J = W.J[0]
+    t, got = _tree_run(env, J, W.ra_p, W.dec_p, l, m, f, u, v, w, sign)
+    ref_t = ot.build_tree(J, W.ra_p, W.dec_p, l, m, f)
+    rows = np.arange(u.size)
+    ref = ot.predict_tree(ref_t, u[rows], v[rows], w[rows], sign)
+    e_max, e_rms = errors(got, ref, f.sum())
+    note(f"cfg1 tree J={J} ({t.stats()['n_leaves']} leaves): E_max={e_max:.3e} E_rms={e_rms:.3e}")
+    assert e_max <= TOL64
+    snapped = ot.predict_snapped(ref_t, u, v, w, sign)
+    assert errors(got, snapped, f.sum())[0] <= TOL64
+
+
+@pytest.mark.parametrize("J", [8, 9, 10])
+def test_cfg2_tree_sampled(env, J):
+    torch, swv = env
+    W = configs.CFG2
+    u, v, w = W.track.uvw()
+    l, m, f = W.components()
+    t = swv.Tree(J, W.ra_p, W.dec_p, l, m, f)
+    out = t.predict(dev(u, torch), dev(v, torch), dev(w, torch))
+    swv.synchronize()
+    rows = configs.sample_rows(u.size, 2048, seed=J)
+    got = host(out[torch.as_tensor(rows, device="cuda")])
+    ref_t = ot.build_tree(J, W.ra_p, W.dec_p, l, m, f)
+    ref = ot.predict_tree(ref_t, u[rows], v[rows], w[rows])
+    e_max, e_rms = errors(got, ref, f.sum())
+    st = t.stats()
+    note(f"cfg2 tree J={J}: leaves={st['n_leaves']} internal={st['n_internal']} "
+         f"sparsity={st['sparsity']:.3e} E_max={e_max:.3e} E_rms={e_rms:.3e}")
+    assert e_max <= TOL64
+
+
+@pytest.mark.parametrize("J", [8, 10])
+def test_tree_equals_direct_on_its_leaves_full_size(env, J):
+    # Eq. 17 == Eq. 16 at every one of the 8.36M rows (library only)
+    torch, swv = env
+    W = configs.CFG2
+    u, v, w = (dev(a, torch) for a in W.track.uvw())
+    l, m, f = W.components()
+    t = swv.Tree(J, W.ra_p, W.dec_p, l, m, f)
+    lv = t.leaves()
+    # the direct kernel takes (l, m) and forms n - 1 itself; leaves lie on the
+    # near hemisphere, so the same centre is described
+    vt = t.predict(u, v, w)
+    vd = swv.predict_direct(u, v, w, dev(lv["l"], torch), dev(lv["m"], torch),
+                            dev(lv["flux"], torch))
+    swv.synchronize()
+    d = (vt - vd).abs().max().item() / float(np.abs(f).sum())
+    note(f"cfg2 J={J}: max |V_tree - V_direct(leaves)| / sum|F| over {u.numel()} rows = {d:.3e}")
+    assert d <= TOL64
+
+
+@pytest.mark.parametrize("J", list(range(1, 13)))
+def test_small_trees_every_depth(env, J):
+    rng = np.random.default_rng(100 + J)
+    n = 37
+    half = 0.5 if J < 5 else 0.05
+    l, m = rng.uniform(-half, half, n), rng.uniform(-half, half, n)
+    f = rng.lognormal(-3, 1, n)
+    nv = 333
+    scale = 200.0 if J < 5 else 2e4
+    u, v, w = (rng.uniform(-scale, scale, nv) for _ in range(3))
+    ra, dec = 1.0, 0.3
+    _, got = _tree_run(env, J, ra, dec, l, m, f, u, v, w)
+    rt = ot.build_tree(J, ra, dec, l, m, f)
+    ref = ot.predict_tree(rt, u, v, w)
+    # few leaves: per-row bound of the FP64 leaf phases, plus J levels of sums
+    bound = fp64_row_bound(u, v, w, rt.leaf_l, rt.leaf_m, rt.leaf_nm1, rt.leaf_flux)
+    assert np.all(np.abs(got - ref) <= bound + (J + 2) * 4e-16 * np.abs(f).sum())
+
+
+def test_empty_tree_gives_zero(env):
+    _, got = _tree_run(env, 7, 0.0, 0.5, np.zeros(0), np.zeros(0), np.zeros(0),
+                       np.ones(100), np.ones(100), np.ones(100))
+    assert np.all(got == 0)
+
+
+def test_deep_tree_not_supported(env):
+    torch, swv = env
+    from paper_1909_03956_amd._lib import SWV_ENOTSUP, SwvError
+    t = swv.Tree(20, 0.0, 0.5, [0.01], [0.0], [1.0])
+    x = dev(np.ones(4), torch)
+    with pytest.raises(SwvError) as e:
+        t.predict(x, x, x)
+    assert e.value.code == SWV_ENOTSUP
+
+
+def test_tree_bitwise_reproducible(env):
+    W = configs.CFG1
+    u, v, w = W.track.uvw()
+    l, m, f = W.components()
+    _, a = _tree_run(env, 6, W.ra_p, W.dec_p, l, m, f, u, v, w)
+    _, b = _tree_run(env, 6, W.ra_p, W.dec_p, l, m, f, u, v, w)
+    assert np.array_equal(a, b)

@@ -1,0 +1,158 @@
+"""CPU tests of libswvis: it loads, exports every symbol its header declares,
+and its host logic (pixelisation, tree builder, argument checks) agrees with
+the oracle.  No GPU compute is called here."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import sphere as sp
+from oracle import tree as ot
+from synth import configs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def swv():
+    from paper_1909_03956_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libswvis.so not built")
+    return _lib
+
+
+def test_every_declared_symbol_is_exported(swv):
+    L = swv.lib()
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^\s*(?:int|const char\s*\*)\s+(swv_\w+)\s*\(", text, re.M))
+    assert len(names) >= 25
+    missing = [n for n in sorted(names) if not hasattr(L, n)]
+    assert not missing, missing
+    # and the binding declares them all
+    assert names <= set(swv.SIGNATURES) | {"swv_last_error"}
+
+
+def test_version(swv):
+    a, b = C.c_int(), C.c_int()
+    assert swv.lib().swv_version(C.byref(a), C.byref(b)) == 0
+    assert (a.value, b.value) == (1, 0)
+    assert swv.lib().swv_version(None, None) == swv.SWV_EINVAL
+    assert b"null" in swv.lib().swv_last_error()
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data)
+
+
+def _build(swv, J, ra, dec, l, m, f):
+    h = C.c_void_p()
+    rc = swv.lib().swv_tree_build(J, ra, dec, l.size, _ptr(l), _ptr(m), _ptr(f), C.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("name,J", [("cfg1", 6), ("cfg2", 8), ("cfg2", 9), ("cfg2", 10)])
+def test_tree_builder_matches_oracle(swv, name, J):
+    from paper_1909_03956_amd.api import Tree
+    W = configs.WORKLOADS[name]
+    l, m, f = W.components()
+    t = Tree(J, W.ra_p, W.dec_p, l, m, f)
+    ref = ot.build_tree(J, W.ra_p, W.dec_p, l, m, f)
+    lv = t.leaves()
+    assert np.array_equal(lv["pix"], ref.leaf_pix)
+    assert np.allclose(lv["flux"], ref.leaf_flux, rtol=1e-15, atol=0)
+    # centres: both sides round an extended-precision value once
+    for key, r in (("l", ref.leaf_l), ("m", ref.leaf_m), ("nm1", ref.leaf_nm1)):
+        d = np.abs(lv[key] - r)
+        assert np.all(d <= 2 * np.spacing(np.abs(r))), (key, d.max())
+    st = t.stats()
+    assert st["n_leaves"] == ref.n_leaves and st["n_internal"] == ref.n_internal
+    for j in range(1, J + 1):
+        got = t.level(j)
+        exp = ref.levels[j - 1]
+        assert np.array_equal(got["pix"], exp.pix)
+        scale = np.abs(exp.lam).max()
+        assert np.max(np.abs(got["lambda"] - exp.lam)) <= 1e-15 * scale
+        if j < J:
+            mask = (exp.child >= 0) @ (1 << np.arange(4))
+            assert np.array_equal(got["mask"], mask)
+            assert np.max(np.abs(got["gamma"] - exp.gamma)) <= 1e-15 * scale
+    # every node record and root record is in the stream once
+    assert st["n_records"] == st["n_leaves"] + st["n_internal"] + st["nodes_per_level"][0]
+
+
+def test_ang2pix_and_centres_match_oracle(swv):
+    from paper_1909_03956_amd.api import ang2pix, pixel_centres
+    rng = np.random.default_rng(3)
+    ra, dec = 2.2, -0.4
+    l = rng.uniform(-0.5, 0.5, 5000)
+    m = rng.uniform(-0.5, 0.5, 5000)
+    for J in (1, 4, 9, 18, 29):
+        pix = ang2pix(J, ra, dec, l, m)
+        ref = sp.ang2pix_xyz(J, sp.lm_to_xyz(l, m, ra, dec))
+        assert np.array_equal(pix, ref), J
+        cl, cm, cn = pixel_centres(J, ra, dec, pix)
+        rl, rm, rn = sp.pixel_centres_lmn(J, pix, ra, dec)
+        for a, b in ((cl, rl), (cm, rm), (cn, rn)):
+            assert np.all(np.abs(a - b) <= 2 * np.spacing(np.abs(b))), J
+
+
+def test_pixels_in_disk_matches_oracle(swv):
+    from paper_1909_03956_amd.api import pixels_in_disk
+    for J, rad in ((6, 10.0), (9, configs.CFG5_DISK_RADIUS_DEG)):
+        W = configs.CFG2
+        pix, l, m, nm1 = pixels_in_disk(J, W.ra_p, W.dec_p, math.radians(rad))
+        rp, rl, rm, rn = sp.pixels_in_disk(J, W.ra_p, W.dec_p, math.radians(rad))
+        assert np.array_equal(pix, rp)
+        assert np.all(np.abs(l - rl) <= 2 * np.spacing(np.abs(rl)))
+        assert np.all(np.abs(nm1 - rn) <= 2 * np.spacing(np.abs(rn)))
+
+
+def test_tree_build_argument_errors(swv):
+    l = np.array([0.01, 0.02])
+    m = np.array([0.0, 0.01])
+    f = np.array([1.0, 2.0])
+    for J in (0, 30, -3):
+        rc, _ = _build(swv, J, 0.0, 0.5, l, m, f)
+        assert rc == swv.SWV_EDOMAIN
+        assert b"J" in swv.lib().swv_last_error()
+    rc, _ = _build(swv, 5, 0.0, 0.5, np.array([0.8, 0.1]), np.array([0.7, 0.1]), f)
+    assert rc == swv.SWV_EDOMAIN
+    rc, _ = _build(swv, 5, 0.0, 0.5, np.array([np.nan, 0.1]), m, f)
+    assert rc == swv.SWV_EDOMAIN
+    rc, _ = _build(swv, 5, 0.0, 0.5, l, m, np.array([np.inf, 1.0]))
+    assert rc == swv.SWV_EDOMAIN
+    h = C.c_void_p()
+    assert swv.lib().swv_tree_build(5, 0.0, 0.5, 2, None, None, None, C.byref(h)) == swv.SWV_EINVAL
+    assert swv.lib().swv_tree_build(5, 0.0, 0.5, -1, None, None, None, C.byref(h)) == swv.SWV_EINVAL
+    assert swv.lib().swv_tree_build(5, 0.0, 0.5, 0, None, None, None, None) == swv.SWV_EINVAL
+    # an empty component list is a valid, empty tree
+    rc, h = _build(swv, 5, 0.0, 0.5, np.zeros(0), np.zeros(0), np.zeros(0))
+    assert rc == 0
+    s = swv.TreeStats()
+    assert swv.lib().swv_tree_stats(h, C.byref(s)) == 0 and s.n_leaves == 0
+    assert swv.lib().swv_tree_destroy(h) == 0
+
+
+def test_host_call_errors(swv):
+    L = swv.lib()
+    n = C.c_int64()
+    assert L.swv_pixels_in_disk(9, 0.0, 0.5, -1.0, 0, None, None, None, None, C.byref(n)) == \
+        swv.SWV_EDOMAIN
+    assert L.swv_pixels_in_disk(9, 0.0, 0.5, 0.1, 5, None, None, None, None, C.byref(n)) == \
+        swv.SWV_EINVAL
+    pix = np.array([12 * 4 ** 8], np.int64)
+    out = [np.empty(1) for _ in range(3)]
+    assert L.swv_pixel_centres(9, 0.0, 0.5, 1, _ptr(pix), *[_ptr(a) for a in out]) == \
+        swv.SWV_EINVAL
+    # GPU entry points reject null handles before touching a device
+    assert L.swv_predict_direct(None, 1, None, None, None, 1, None, None, None, -1, 0, None) == \
+        swv.SWV_EINVAL
+    assert L.swv_ctx_synchronize(None) == swv.SWV_EINVAL
+    assert L.swv_batch_run(None) != 0
+    assert L.swv_tree_leaves(None, None, None, None, None, None) == swv.SWV_EINVAL
