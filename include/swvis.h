@@ -27,8 +27,10 @@
  *    the kernels detect (non-finite or out-of-domain inputs) and HIP faults
  *    are reported by the next swv_ctx_synchronize() on that context.
  *  - Library objects (swv_ctx, swv_tree, swv_plan, swv_graph) follow
- *    create/destroy pairs.  A context may be used from one thread at a time;
- *    calls that overlap on one stream are ordered by the stream.
+ *    create/destroy pairs.  A plan keeps its context alive and a graph its
+ *    plan, so they may be destroyed in any order (memory is released with the
+ *    last of them).  A context may be used from one thread at a time; calls
+ *    that overlap on one stream are ordered by the stream.
  *  - n = 0 is valid everywhere and enqueues nothing (outputs untouched,
  *    except reductions, which write zero).
  */
@@ -281,7 +283,8 @@ int swv_plan_destroy(swv_plan plan);
 /* ------------------------------------------------------------- tuning --- */
 
 /* Times every compiled tile shape of each kernel family (direct FP64,
- * direct F32C, tree, adjoint) on synthetic inputs of two size classes, keeps
+ * direct F32C, tree, adjoint, gradients) on synthetic inputs of the two size
+ * classes (2^18 and 2^22 rows), keeps
  * the fastest per (family, size class) in the context's tuning table and, if
  * `cache_path` is not NULL, writes the table there as JSON.  flags: 0 =
  * full sweep, 1 = quick sweep (fewer repetitions). */
@@ -290,10 +293,18 @@ int swv_autotune(swv_ctx ctx, const char* cache_path, int flags);
 /* Loads a tuning table written by swv_autotune into the context. */
 int swv_tune_load(swv_ctx ctx, const char* cache_path);
 
-/* Tile shape the context will use: family 0 direct FP64, 1 direct F32C,
- * 2 tree, 3 adjoint; size class 0 (< 2^20 rows) or 1.  Writes rows per lane
- * (or pixels per lane for the adjoint) and threads per block. */
+/* Tile shape the context uses per kernel family and size class.  Families:
+ * 0 direct FP64, 1 direct F32C, 2 tree, 3 adjoint, 4 gradients.  Size class
+ * 0 is fewer than 2^20 visibility rows, 1 the rest.  per_lane is rows per lane
+ * (direct), pixels per lane (adjoint) or components per lane (gradients), in
+ * {1, 2, 4} (1 for the tree); block is threads per block in {64, 128, 256}
+ * (128 for the gradients).  Results do not depend on the shape except for
+ * the summation order of the adjoint and gradients. */
 int swv_tune_get(swv_ctx ctx, int family, int size_class, int* per_lane, int* block);
+
+/* Sets one entry of the context's tuning table (SWV_EINVAL for a shape that is
+ * not compiled). */
+int swv_tune_set(swv_ctx ctx, int family, int size_class, int per_lane, int block);
 
 #ifdef __cplusplus
 }

@@ -5,7 +5,8 @@ exact adjoint and chi^2 gradients, behind the C ABI of libswvis.so
 library; the library must be built (build.py) -- there is no CPU fallback.
 """
 from ._lib import SwvError, lib  # noqa: F401
-from .api import (Context, Tree, adjoint, ang2pix, context, grad_direct,  # noqa: F401
-                  pixel_centres, pixels_in_disk, predict_direct, residual_chi2, synchronize)
+from .api import (BatchPlan, Context, Graph, Tree, adjoint, ang2pix, context,  # noqa: F401
+                  grad_direct, pixel_centres, pixels_in_disk, predict_direct, residual_chi2,
+                  synchronize)
 
 __version__ = "1.0"

@@ -76,6 +76,7 @@ SIGNATURES = {
     "swv_autotune": [_vp, C.c_char_p, _int],
     "swv_tune_load": [_vp, C.c_char_p],
     "swv_tune_get": [_vp, _int, _int, C.POINTER(C.c_int), C.POINTER(C.c_int)],
+    "swv_tune_set": [_vp, _int, _int, _int, _int],
 }
 
 _lib = None

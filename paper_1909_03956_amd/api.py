@@ -2,6 +2,7 @@
 stream; every step of the computation runs in the library's kernels."""
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 
 import numpy as np
@@ -11,6 +12,11 @@ from ._lib import (SWV_F32C, SWV_FP64, Instance, PlanStats, TreeStats,
                    check, lib)
 
 PRECISIONS = {"fp64": SWV_FP64, "f32c": SWV_F32C}
+
+# At interpreter exit, objects are collected in no useful order; the process
+# end releases device memory anyway, so finalizers then do nothing.
+_EXITING = [False]
+atexit.register(lambda: _EXITING.__setitem__(0, True))
 
 
 def _prec(p) -> int:
@@ -84,6 +90,9 @@ class Context:
         check(lib().swv_tune_get(self._h, family, size_class, C.byref(pl), C.byref(bl)))
         return pl.value, bl.value
 
+    def tune_set(self, family: int, size_class: int, per_lane: int, block: int):
+        check(lib().swv_tune_set(self._h, family, size_class, per_lane, block))
+
     def autotune(self, cache_path=None, quick=False):
         p = cache_path.encode() if cache_path else None
         check(lib().swv_autotune(self._h, p, 1 if quick else 0))
@@ -97,6 +106,8 @@ class Context:
             self._h = C.c_void_p()
 
     def __del__(self):
+        if _EXITING[0]:
+            return
         try:
             self.close()
         except Exception:
@@ -209,6 +220,8 @@ class Tree:
             self._h = C.c_void_p()
 
     def __del__(self):
+        if _EXITING[0]:
+            return
         try:
             self.close()
         except Exception:
@@ -297,6 +310,108 @@ def grad_direct(u, v, w, y, l, m, flux, sign: int = -1, alpha: float = 1.0):
     return tuple(outs)
 
 
+# --------------------------------------------------------------- batched --
+ROUTES = {"direct": 0, "tree": 1}
+
+
+class Graph:
+    """A captured batched prediction; launch() replays it on the plan's stream."""
+
+    def __init__(self, plan):
+        self.plan = plan
+        self._h = C.c_void_p()
+        check(lib().swv_graph_capture(plan.handle, C.byref(self._h)))
+
+    def launch(self):
+        check(lib().swv_graph_launch(self._h))
+
+    def close(self):
+        if self._h:
+            lib().swv_graph_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        if _EXITING[0]:
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchPlan:
+    """One persistent launch per route over many prediction instances.
+
+    instances: dicts with keys route ("direct" | "tree"), u, v, w (float64 GPU
+    tensors), out (complex128, or complex64 for a "f32c" direct instance),
+    sign (default -1), prec (default "fp64"), and l, m, flux (float64 GPU
+    tensors, direct) or tree (a Tree).  The tensors and trees must outlive the
+    plan; the plan keeps references to them."""
+
+    def __init__(self, instances, device=None):
+        self._keep = []
+        arr = (Instance * max(1, len(instances)))()
+        dev = None
+        for k, d in enumerate(instances):
+            u = _dev_f64(d["u"], "u")
+            dev = dev or u.device
+            v, w = _dev_f64(d["v"], "v", u.device), _dev_f64(d["w"], "w", u.device)
+            out = d["out"]
+            n = u.numel()
+            if v.numel() != n or w.numel() != n or out.numel() != n or not out.is_contiguous():
+                raise ValueError(f"instance {k}: length mismatch")
+            I = arr[k]
+            I.route = ROUTES[d.get("route", "direct")]
+            I.prec = _prec(d.get("prec", "fp64"))
+            I.sign = int(d.get("sign", -1))
+            I.n_vis = n
+            I.u, I.v, I.w = _ptr(u).value, _ptr(v).value, _ptr(w).value
+            I.vis_out = _ptr(out).value
+            self._keep += [u, v, w, out]
+            if I.route == 0:
+                l = _dev_f64(d["l"], "l", u.device)
+                m = _dev_f64(d["m"], "m", u.device)
+                f = _dev_f64(d["flux"], "flux", u.device)
+                I.n_comp = l.numel()
+                I.l, I.m, I.flux = _ptr(l).value, _ptr(m).value, _ptr(f).value
+                self._keep += [l, m, f]
+            else:
+                t = d["tree"]
+                I.tree = t.handle.value
+                self._keep.append(t)
+        self.ctx = context(dev if device is None else device)
+        self._h = C.c_void_p()
+        check(lib().swv_batch_plan(self.ctx.handle, len(instances), arr, C.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self) -> dict:
+        s = PlanStats()
+        check(lib().swv_plan_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in PlanStats._fields_}
+
+    def run(self):
+        check(lib().swv_batch_run(self._h))
+
+    def capture(self) -> Graph:
+        return Graph(self)
+
+    def close(self):
+        if self._h:
+            lib().swv_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        if _EXITING[0]:
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def synchronize(device=None):
     """Waits for the current stream and raises deferred kernel errors."""
     context(device).synchronize()
@@ -304,4 +419,4 @@ def synchronize(device=None):
 
 __all__ = ["Context", "context", "predict_direct", "Tree", "ang2pix", "pixel_centres",
            "pixels_in_disk", "residual_chi2", "adjoint", "grad_direct", "synchronize",
-           "Instance", "PlanStats"]
+           "BatchPlan", "Graph"]

@@ -22,6 +22,9 @@ ARCH = "gfx950"
 
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # arithmetic exactly as written: every intended FMA is an explicit fma(),
+    # so results do not depend on how a device function was inlined
+    "-ffp-contract=off",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-warning-option",

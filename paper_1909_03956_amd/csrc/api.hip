@@ -48,7 +48,7 @@ int ensure(swv_ctx ctx, DevBuf& b, size_t bytes) {
 
 void tune_defaults(swv_ctx ctx) {
     // (per_lane, block) for family x size class; see swv_tune_get.
-    const int pl[kFamilies][2] = {{2, 256}, {2, 256}, {1, 64}, {2, 256}};
+    const int pl[kFamilies][2] = {{2, 256}, {2, 256}, {1, 64}, {2, 256}, {2, 128}};
     for (int f = 0; f < kFamilies; ++f)
         for (int c = 0; c < 2; ++c) {
             ctx->per_lane[f][c] = pl[f][0];
@@ -57,6 +57,15 @@ void tune_defaults(swv_ctx ctx) {
 }
 
 int size_class(int64_t rows) { return rows < (int64_t(1) << 20) ? 0 : 1; }
+
+bool tune_valid(int family, int per_lane, int block) {
+    if (family < 0 || family >= kFamilies) return false;
+    const bool pl_ok = per_lane == 1 || per_lane == 2 || per_lane == 4;
+    const bool bl_ok = block == 64 || block == 128 || block == 256;
+    if (family == kFamTree) return per_lane == 1 && bl_ok;
+    if (family == kFamGrad) return pl_ok && block == 128;
+    return pl_ok && bl_ok;
+}
 
 int check_sign_prec(int sign, int prec, bool allow_f32) {
     if (sign != 1 && sign != -1) return fail(SWV_EDOMAIN, "sign must be +1 or -1 (got %d)", sign);
@@ -97,6 +106,18 @@ TreeArgs tree_args(swv_tree t, const TRec* d_rec) {
     a.J = t->J;
     for (int j = 0; j <= SWV_MAX_LEVEL; ++j) a.scale[j] = t->level_scale[j];
     return a;
+}
+
+void ctx_release(swv_ctx ctx) {
+    if (--ctx->refs > 0) return;
+    {
+        DeviceGuard g(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        for (DevBuf* b : {&ctx->comp, &ctx->partial, &ctx->partial2})
+            if (b->p) (void)hipFree(b->p);
+        if (ctx->d_status) (void)hipFree(ctx->d_status);
+    }
+    delete ctx;
 }
 
 }  // namespace swv
@@ -195,14 +216,7 @@ int swv_ctx_synchronize(swv_ctx ctx) {
 
 int swv_ctx_destroy(swv_ctx ctx) {
     if (!ctx) return SWV_OK;
-    {
-        DeviceGuard g(ctx->device);
-        (void)hipStreamSynchronize(ctx->stream);
-        for (DevBuf* b : {&ctx->comp, &ctx->partial, &ctx->partial2})
-            if (b->p) (void)hipFree(b->p);
-        if (ctx->d_status) (void)hipFree(ctx->d_status);
-    }
-    delete ctx;
+    ctx_release(ctx);
     return SWV_OK;
 }
 
@@ -459,6 +473,7 @@ static int64_t choose_chunk(int64_t n_rows, int64_t tiles, int n_cu, int blocks_
     if (want < 1) want = 1;
     int64_t chunk = (n_rows + want - 1) / want;
     if (chunk < 64) chunk = 64;
+    if (chunk > (int64_t(1) << 30)) chunk = int64_t(1) << 30;  // rows per chunk fit an int
     return chunk;
 }
 
@@ -508,12 +523,13 @@ int swv_grad_direct(swv_ctx ctx, int64_t n_vis, const double* u, const double* v
     if (rc) return rc;
     Comp* comp = (Comp*)ctx->comp.p;
     HIPCALL(launch_ingest(ctx->stream, n_comp, l, m, flux, comp, ctx->d_status));
-    const int64_t tiles = (n_comp + 127) / 128;
+    const int cpl = ctx->per_lane[kFamGrad][size_class(n_vis)];
+    const int64_t tiles = (n_comp + 128 * cpl - 1) / (128 * cpl);
     const int64_t chunk = choose_chunk(n_vis, tiles, ctx->n_cu, 16);
     const int64_t n_chunks = n_vis > 0 ? (n_vis + chunk - 1) / chunk : 0;
     rc = ensure(ctx, ctx->partial, 64 * (size_t)n_comp * (size_t)(n_chunks > 0 ? n_chunks : 1));
     if (rc) return rc;
-    HIPCALL(launch_grad(ctx->stream, chunk, n_vis, u, v, w, y, comp, n_comp, sign, alpha,
+    HIPCALL(launch_grad(ctx->stream, cpl, chunk, n_vis, u, v, w, y, comp, n_comp, sign, alpha,
                         (double*)ctx->partial.p, d_flux, d_l, d_m));
     return SWV_OK;
     TRY_END
@@ -527,6 +543,16 @@ int swv_tune_get(swv_ctx ctx, int family, int size_class_, int* per_lane, int* b
         return fail(SWV_EINVAL, "swv_tune_get: bad argument");
     *per_lane = ctx->per_lane[family][size_class_];
     *block = ctx->block[family][size_class_];
+    return SWV_OK;
+}
+
+int swv_tune_set(swv_ctx ctx, int family, int size_class_, int per_lane, int block) {
+    CHECK_CTX(ctx);
+    if (size_class_ < 0 || size_class_ > 1 || !tune_valid(family, per_lane, block))
+        return fail(SWV_EINVAL, "swv_tune_set: no compiled shape (%d, %d) for family %d",
+                    per_lane, block, family);
+    ctx->per_lane[family][size_class_] = per_lane;
+    ctx->block[family][size_class_] = block;
     return SWV_OK;
 }
 

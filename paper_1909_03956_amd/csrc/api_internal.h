@@ -9,7 +9,7 @@
 namespace swv {
 
 // Kernel families of the tuning table.
-enum { kFamDirect64 = 0, kFamDirect32 = 1, kFamTree = 2, kFamAdjoint = 3, kFamilies = 4 };
+enum { kFamDirect64 = 0, kFamDirect32 = 1, kFamTree = 2, kFamAdjoint = 3, kFamGrad = 4, kFamilies = 5 };
 
 struct DevBuf {
     void* p = nullptr;
@@ -35,7 +35,15 @@ struct swv_ctx_s {
     int n_cu = 256;
     int per_lane[swv::kFamilies][2];
     int block[swv::kFamilies][2];
+    // plans that point at this context; the context is freed when it has
+    // been destroyed and the last plan has gone
+    int refs = 1;
 };
+
+namespace swv {
+// Drops one reference to the context and frees it when none is left.
+void ctx_release(swv_ctx ctx);
+}  // namespace swv
 
 namespace swv {
 
@@ -44,6 +52,7 @@ int ensure(swv_ctx ctx, DevBuf& b, size_t bytes);
 void tune_defaults(swv_ctx ctx);
 int size_class(int64_t rows);
 int check_sign_prec(int sign, int prec, bool allow_f32);
+bool tune_valid(int family, int per_lane, int block);
 int upload_tree(swv_ctx ctx, swv_tree t, const TRec** out);
 TreeArgs tree_args(swv_tree t, const TRec* d_rec);
 

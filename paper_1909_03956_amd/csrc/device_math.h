@@ -60,6 +60,16 @@ __device__ __forceinline__ void cis2pi_f32(float r, float& c, float& s) {
     s = __builtin_amdgcn_sinf(r);
 }
 
+// Kahan-compensated accumulation of the product a b into (sum, comp); the
+// product is rounded once, inside the FMA that removes the compensation.
+__host__ __device__ __forceinline__ void kahan_add_prod(float a, float b, float& sum,
+                                                        float& comp) {
+    const float y = fmaf(a, b, -comp);
+    const float t = sum + y;
+    comp = (t - sum) - y;
+    sum = t;
+}
+
 // Kahan-compensated accumulation of x into (sum, comp).
 __host__ __device__ __forceinline__ void kahan_add(float x, float& sum, float& comp) {
     const float y = x - comp;

@@ -1,0 +1,212 @@
+// Persistent batched prediction: many instances (channels x pointings) of
+// uneven size in one launch per route.
+//
+// The host splits every instance into row tiles and orders the (instance,
+// tile) work items by decreasing cost, largest first.  Each wave of a
+// grid sized to stay resident takes the next item from a device counter
+// (one atomic per item, on lane 0), so long and short instances balance
+// across the chip without a second launch; a wave leaves when the counter
+// passes the item count, so every wave exits.  The row arithmetic is the
+// single-instance kernels' (direct_rows.h, tree_walk.h).
+#include "direct_rows.h"
+#include "tree_walk.h"
+
+namespace swv {
+
+// Packs the components of every direct instance: block row y is instance y.
+__global__ void k_batch_ingest(const BatchInst* __restrict__ inst, Comp* __restrict__ pack,
+                               int* __restrict__ status) {
+    const BatchInst I = inst[blockIdx.y];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= I.n_comp) return;
+    int bad;
+    pack[I.comp_offset + k] = pack_component(I.l[k], I.m[k], I.flux[k], bad);
+    if (bad) atomicOr(status, bad);
+}
+
+hipError_t launch_batch_ingest(hipStream_t s, const BatchInst* inst, int n_inst, int max_comp,
+                               Comp* pack, int* status) {
+    if (n_inst <= 0 || max_comp <= 0) return hipSuccess;
+    k_batch_ingest<<<dim3((unsigned)((max_comp + 255) / 256), (unsigned)n_inst), dim3(256), 0,
+                     s>>>(inst, pack, status);
+    return hipGetLastError();
+}
+
+// Work-counter reset as a kernel, so a captured graph re-arms itself on
+// every replay without a memset node.
+__global__ void k_reset_counters(unsigned* counters, int n) {
+    if ((int)threadIdx.x < n) counters[threadIdx.x] = 0u;
+}
+
+hipError_t launch_reset_counters(hipStream_t s, unsigned* counters, int n) {
+    k_reset_counters<<<1, 64, 0, s>>>(counters, n);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ unsigned next_item(unsigned* counter) {
+    unsigned it = 0;
+    if ((threadIdx.x & 63) == 0) it = atomicAdd(counter, 1u);
+    return __builtin_amdgcn_readfirstlane(it);
+}
+
+template <int VPL, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_batch_direct(const BatchInst* __restrict__ inst,
+                                                        const Comp* __restrict__ pack,
+                                                        const WorkItem* __restrict__ items,
+                                                        unsigned n_items,
+                                                        unsigned* __restrict__ counter,
+                                                        int* __restrict__ status) {
+    const int lane = threadIdx.x & 63;
+    const auto* IT = uniform_ptr(items);
+    const auto* IN = uniform_ptr(inst);
+    for (;;) {
+        const unsigned it = next_item(counter);
+        if (it >= n_items) break;
+        const int64_t row0 = IT[it].row0;
+        const int nrows = IT[it].nrows;
+        const int ii = IT[it].inst;
+        const int64_t n_vis = IN[ii].n_vis;
+        const int64_t limit = row0 + nrows < n_vis ? row0 + nrows : n_vis;
+        const double* u = IN[ii].u;
+        const double* v = IN[ii].v;
+        const double* w = IN[ii].w;
+        void* out = IN[ii].out;
+        const Comp* comp = pack + IN[ii].comp_offset;
+        const int n_comp = IN[ii].n_comp;
+        const double sgn = IN[ii].sgn;
+        const bool f64 = IN[ii].prec == SWV_FP64;
+        for (int sub = 0; sub < nrows; sub += 64 * VPL) {
+            int64_t j[VPL];
+#pragma unroll
+            for (int i = 0; i < VPL; ++i) j[i] = row0 + sub + i * 64 + lane;
+            if (f64)
+                direct_rows_f64<VPL>(j, limit, u, v, w, comp, n_comp, sgn, (double2*)out, status);
+            else
+                direct_rows_f32c<VPL>(j, limit, u, v, w, comp, n_comp, (float)sgn, (float2*)out,
+                                      status);
+        }
+    }
+}
+
+template <int JMAX>
+__global__ __launch_bounds__(kBatchTreeBlock) void k_batch_tree(
+    TreeArgs scales, const BatchInst* __restrict__ inst, const WorkItem* __restrict__ items,
+    unsigned n_items, unsigned* __restrict__ counter, int* __restrict__ status) {
+    const int lane = threadIdx.x & 63;
+    const auto* IT = uniform_ptr(items);
+    const auto* IN = uniform_ptr(inst);
+    for (;;) {
+        const unsigned it = next_item(counter);
+        if (it >= n_items) break;
+        const int64_t row0 = IT[it].row0;
+        const int nrows = IT[it].nrows;
+        const int ii = IT[it].inst;
+        const int64_t n_vis = IN[ii].n_vis;
+        const int64_t limit = row0 + nrows < n_vis ? row0 + nrows : n_vis;
+        const double* u = IN[ii].u;
+        const double* v = IN[ii].v;
+        const double* w = IN[ii].w;
+        double2* out = (double2*)IN[ii].out;
+        const TRec* rec = IN[ii].rec;
+        const int n_roots = IN[ii].n_roots, J = IN[ii].J;
+        const double s4 = 4.0 * IN[ii].sgn;
+        for (int sub = 0; sub < nrows; sub += 64) {
+            const int64_t jr = row0 + sub + lane;
+            const int64_t j = jr < limit ? jr : limit - 1;
+            const double U = u[j], V = v[j], W = w[j];
+            double Vr, Vi;
+            tree_row<JMAX>(rec, n_roots, J, scales, U, V, W, Vr, Vi);
+            if (jr < limit) {
+                if (!isfinite(U + V + W)) atomicOr(status, kStatusNonFinite);
+                out[jr] = make_double2(Vr, s4 * Vi);
+            }
+        }
+    }
+}
+
+template <int VPL, int BLOCK>
+static int direct_occupancy() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_direct<VPL, BLOCK>, BLOCK, 0) !=
+        hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+int batch_direct_blocks_per_cu(int vpl, int block) {
+#define SWV_OCC(V, B) if (vpl == V && block == B) return direct_occupancy<V, B>();
+    SWV_OCC(1, 64) SWV_OCC(1, 128) SWV_OCC(1, 256)
+    SWV_OCC(2, 64) SWV_OCC(2, 128) SWV_OCC(2, 256)
+    SWV_OCC(4, 64) SWV_OCC(4, 128) SWV_OCC(4, 256)
+#undef SWV_OCC
+    return 1;
+}
+
+template <int JMAX>
+static int tree_occupancy() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_tree<JMAX>, kBatchTreeBlock,
+                                                     0) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+int batch_tree_blocks_per_cu(int jmax) {
+    switch (jmax) {
+        case 1: return tree_occupancy<1>();
+        case 2: return tree_occupancy<2>();
+        case 3: return tree_occupancy<3>();
+        case 4: return tree_occupancy<4>();
+        case 5: return tree_occupancy<5>();
+        case 6: return tree_occupancy<6>();
+        case 7: return tree_occupancy<7>();
+        case 8: return tree_occupancy<8>();
+        case 9: return tree_occupancy<9>();
+        case 10: return tree_occupancy<10>();
+        case 11: return tree_occupancy<11>();
+        case 12: return tree_occupancy<12>();
+        default: return 1;
+    }
+}
+
+hipError_t launch_batch_direct(hipStream_t s, int vpl, int block, int grid,
+                               const BatchInst* inst, const Comp* pack, const WorkItem* items,
+                               unsigned n_items, unsigned* counter, int* status) {
+    if (n_items == 0) return hipSuccess;
+#define SWV_RUN(V, B)                                                                     \
+    if (vpl == V && block == B) {                                                         \
+        k_batch_direct<V, B><<<dim3(grid), dim3(B), 0, s>>>(inst, pack, items, n_items,    \
+                                                            counter, status);             \
+        return hipGetLastError();                                                         \
+    }
+    SWV_RUN(1, 64) SWV_RUN(1, 128) SWV_RUN(1, 256)
+    SWV_RUN(2, 64) SWV_RUN(2, 128) SWV_RUN(2, 256)
+    SWV_RUN(4, 64) SWV_RUN(4, 128) SWV_RUN(4, 256)
+#undef SWV_RUN
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_tree(hipStream_t s, int jmax, int grid, const TreeArgs& scales,
+                             const BatchInst* inst, const WorkItem* items, unsigned n_items,
+                             unsigned* counter, int* status) {
+    if (n_items == 0) return hipSuccess;
+    const dim3 g(grid), b(kBatchTreeBlock);
+    switch (jmax) {
+        case 1: k_batch_tree<1><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
+        case 2: k_batch_tree<2><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
+        case 3: k_batch_tree<3><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
+        case 4: k_batch_tree<4><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
+        case 5: k_batch_tree<5><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
+        case 6: k_batch_tree<6><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
+        case 7: k_batch_tree<7><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
+        case 8: k_batch_tree<8><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
+        case 9: k_batch_tree<9><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
+        case 10: k_batch_tree<10><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
+        case 11: k_batch_tree<11><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
+        case 12: k_batch_tree<12><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace swv

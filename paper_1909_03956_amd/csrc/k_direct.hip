@@ -1,15 +1,7 @@
-// Direct component sum (section 3.3, Eq. 12) on gfx950.
-//
-// Mapping: each lane owns VPL visibility rows (coalesced FP64 loads of u, v,
-// w); every lane of a wave walks the same component list, so a component
-// record (l, m, n-1, I; 32 B) is one scalar load into SGPRs and enters the
-// FMAs as the instruction's scalar operand.  The sum over components is a
-// per-lane running sum: no cross-lane reduction, no atomics, a fixed order,
-// bit-reproducible.  VPL independent rows give the FP64 pipeline ILP.
-//
-// Work per (row, component): phase 3 ops, reduction 2, phasor 20, MAC 2.
-#include "device_math.h"
-#include "launch.h"
+// Direct component sum (section 3.3, Eq. 12) on gfx950: the component
+// ingest and the single-instance kernels.  Rows of a block are strided by
+// the block size so each of a lane's VPL loads is coalesced.
+#include "direct_rows.h"
 
 namespace swv {
 
@@ -18,18 +10,9 @@ __global__ void k_ingest(int64_t n, const double* __restrict__ l, const double* 
                          int* __restrict__ status) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const double L = l[k], M = m[k], I = flux[k];
-    const double r2 = L * L + M * M;
-    int bad = 0;
-    if (!(r2 < 1.0)) bad |= kStatusDomain;
-    if (!isfinite(L) || !isfinite(M) || !isfinite(I)) bad |= kStatusNonFinite;
-    if (bad) {
-        atomicOr(status, bad);
-        out[k] = Comp{0.0, 0.0, 0.0, 0.0};
-        return;
-    }
-    // n - 1 = -(l^2 + m^2) / (1 + n), free of cancellation
-    out[k] = Comp{L, M, -r2 / (1.0 + sqrt(1.0 - r2)), I};
+    int bad;
+    out[k] = pack_component(l[k], m[k], flux[k], bad);
+    if (bad) atomicOr(status, bad);
 }
 
 hipError_t launch_ingest(hipStream_t s, int64_t n, const double* l, const double* m,
@@ -48,40 +31,12 @@ __global__ __launch_bounds__(BLOCK) void k_direct_f64(const double* __restrict__
                                                       double sgn, double2* __restrict__ out,
                                                       int* __restrict__ status) {
     const int64_t base = (int64_t)blockIdx.x * (BLOCK * VPL) + threadIdx.x;
-    double U[VPL], V[VPL], W[VPL], re[VPL], iq[VPL];
+    int64_t j[VPL];
 #pragma unroll
-    for (int i = 0; i < VPL; ++i) {
-        int64_t j = base + (int64_t)i * BLOCK;
-        j = j < n_vis ? j : n_vis - 1;
-        U[i] = u[j];
-        V[i] = v[j];
-        W[i] = w[j];
-        re[i] = 0.0;
-        iq[i] = 0.0;
-    }
-    const auto* cp = uniform_ptr(comp);
-    for (int k = 0; k < n_comp; ++k) {
-        const Comp cur{cp[k].l, cp[k].m, cp[k].nm1, cp[k].I};
-#pragma unroll
-        for (int i = 0; i < VPL; ++i) {
-            double c, q;
-            cis2pi_q(reduced_phase(U[i], V[i], W[i], cur.l, cur.m, cur.nm1), c, q);
-            re[i] = fma(cur.I, c, re[i]);
-            iq[i] = fma(cur.I, q, iq[i]);
-        }
-    }
-    const double s4 = 4.0 * sgn;
-#pragma unroll
-    for (int i = 0; i < VPL; ++i) {
-        const int64_t j = base + (int64_t)i * BLOCK;
-        if (j < n_vis) {
-            if (!isfinite(U[i] + V[i] + W[i])) atomicOr(status, kStatusNonFinite);
-            out[j] = make_double2(re[i], s4 * iq[i]);
-        }
-    }
+    for (int i = 0; i < VPL; ++i) j[i] = base + (int64_t)i * BLOCK;
+    direct_rows_f64<VPL>(j, n_vis, u, v, w, comp, n_comp, sgn, out, status);
 }
 
-// FP64 phase and reduction; FP32 phasor, products and Kahan-compensated sums.
 template <int VPL, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_direct_f32c(const double* __restrict__ u,
                                                        const double* __restrict__ v,
@@ -91,38 +46,10 @@ __global__ __launch_bounds__(BLOCK) void k_direct_f32c(const double* __restrict_
                                                        float sgn, float2* __restrict__ out,
                                                        int* __restrict__ status) {
     const int64_t base = (int64_t)blockIdx.x * (BLOCK * VPL) + threadIdx.x;
-    double U[VPL], V[VPL], W[VPL];
-    float sr[VPL], cr[VPL], si[VPL], ci[VPL];
+    int64_t j[VPL];
 #pragma unroll
-    for (int i = 0; i < VPL; ++i) {
-        int64_t j = base + (int64_t)i * BLOCK;
-        j = j < n_vis ? j : n_vis - 1;
-        U[i] = u[j];
-        V[i] = v[j];
-        W[i] = w[j];
-        sr[i] = cr[i] = si[i] = ci[i] = 0.0f;
-    }
-    const auto* cp = uniform_ptr(comp);
-    for (int k = 0; k < n_comp; ++k) {
-        const Comp cur{cp[k].l, cp[k].m, cp[k].nm1, cp[k].I};
-        const float cI = (float)cur.I;
-#pragma unroll
-        for (int i = 0; i < VPL; ++i) {
-            const float r = (float)reduced_phase(U[i], V[i], W[i], cur.l, cur.m, cur.nm1);
-            float c, s;
-            cis2pi_f32(r, c, s);
-            kahan_add(cI * c, sr[i], cr[i]);
-            kahan_add(cI * s, si[i], ci[i]);
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < VPL; ++i) {
-        const int64_t j = base + (int64_t)i * BLOCK;
-        if (j < n_vis) {
-            if (!isfinite(U[i] + V[i] + W[i])) atomicOr(status, kStatusNonFinite);
-            out[j] = make_float2(sr[i], sgn * si[i]);
-        }
-    }
+    for (int i = 0; i < VPL; ++i) j[i] = base + (int64_t)i * BLOCK;
+    direct_rows_f32c<VPL>(j, n_vis, u, v, w, comp, n_comp, sgn, out, status);
 }
 
 template <int VPL, int BLOCK>

@@ -38,11 +38,14 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
     }
     const int64_t j0 = (int64_t)blockIdx.y * chunk;
     const int64_t j1 = j0 + chunk < n_vis ? j0 + chunk : n_vis;
-    const auto* U = uniform_ptr(u);
-    const auto* V = uniform_ptr(v);
-    const auto* W = uniform_ptr(w);
-    const auto* Y = uniform_ptr(y);
-    for (int64_t j = j0; j < j1; ++j) {
+    // wave-uniform trip count, kept in scalar registers
+    const int nrow = __builtin_amdgcn_readfirstlane((int)(j1 - j0));
+    const auto* U = uniform_ptr(u + j0);
+    const auto* V = uniform_ptr(v + j0);
+    const auto* W = uniform_ptr(w + j0);
+    const auto* Y = uniform_ptr(y + j0);
+#pragma unroll 2
+    for (int j = 0; j < nrow; ++j) {
         const double uj = U[j], vj = V[j], wj = W[j];
         const double yr = Y[j].x, yi = Y[j].y;
         if constexpr (PREC == SWV_FP64) {
@@ -154,52 +157,73 @@ hipError_t launch_adjoint(hipStream_t s, int prec, int ppl, int block, int64_t c
 }
 
 // -------------------------------------------------------------- gradients --
-// Per component k (one per lane) and chunk of rows:
+// Per component k (CPL per lane) and chunk of rows:
 //   Z0 = sum conj(y) e,  Zu = sum u conj(y) e,  Zv = ..., Zw = ...
-// conj(y) e = (yr - i yi)(c + i s S) = (yr c + yi s S) + i (yr s S - yi c).
+// conj(y) e = (yr - i yi)(c + i s S) = (yr c + yi s S) + i (yr s S - yi c),
+// S = 4 q; the products 4 s y are formed once per row for all CPL components.
 constexpr int kGradBlock = 128;
 
+template <int CPL>
 __global__ __launch_bounds__(kGradBlock) void k_grad_partial(
     const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
     const double2* __restrict__ y, int64_t n_vis, int64_t chunk, const Comp* __restrict__ comp,
     int64_t n_comp, double sgn, double* __restrict__ partial) {
-    const int64_t k0 = (int64_t)blockIdx.x * kGradBlock + threadIdx.x;
-    const int64_t k = k0 < n_comp ? k0 : n_comp - 1;
-    const double L = comp[k].l, M = comp[k].m, N = comp[k].nm1;
-    double z0r = 0, z0i = 0, zur = 0, zui = 0, zvr = 0, zvi = 0, zwr = 0, zwi = 0;
+    const int64_t k0 = (int64_t)blockIdx.x * (kGradBlock * CPL) + threadIdx.x;
+    double L[CPL], M[CPL], N[CPL];
+    double z0r[CPL], z0i[CPL], zur[CPL], zui[CPL], zvr[CPL], zvi[CPL], zwr[CPL], zwi[CPL];
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+        int64_t k = k0 + (int64_t)i * kGradBlock;
+        k = k < n_comp ? k : n_comp - 1;
+        L[i] = comp[k].l;
+        M[i] = comp[k].m;
+        N[i] = comp[k].nm1;
+        z0r[i] = z0i[i] = zur[i] = zui[i] = zvr[i] = zvi[i] = zwr[i] = zwi[i] = 0.0;
+    }
     const int64_t j0 = (int64_t)blockIdx.y * chunk;
     const int64_t j1 = j0 + chunk < n_vis ? j0 + chunk : n_vis;
-    const auto* U = uniform_ptr(u);
-    const auto* V = uniform_ptr(v);
-    const auto* W = uniform_ptr(w);
-    const auto* Y = uniform_ptr(y);
-    for (int64_t j = j0; j < j1; ++j) {
+    // wave-uniform trip count, kept in scalar registers
+    const int nrow = __builtin_amdgcn_readfirstlane((int)(j1 - j0));
+    const auto* U = uniform_ptr(u + j0);
+    const auto* V = uniform_ptr(v + j0);
+    const auto* W = uniform_ptr(w + j0);
+    const auto* Y = uniform_ptr(y + j0);
+    const double s4 = 4.0 * sgn;
+#pragma unroll 2
+    for (int j = 0; j < nrow; ++j) {
         const double uj = U[j], vj = V[j], wj = W[j];
         const double yr = Y[j].x, yi = Y[j].y;
-        const double y4r = 4.0 * sgn * yr, y4i = 4.0 * sgn * yi;
-        double c, q;
-        cis2pi_q(reduced_phase(uj, vj, wj, L, M, N), c, q);
-        const double zr = fma(q, y4i, yr * c);
-        const double zi = fma(q, y4r, -(yi * c));
-        z0r += zr;
-        z0i += zi;
-        zur = fma(uj, zr, zur);
-        zui = fma(uj, zi, zui);
-        zvr = fma(vj, zr, zvr);
-        zvi = fma(vj, zi, zvi);
-        zwr = fma(wj, zr, zwr);
-        zwi = fma(wj, zi, zwi);
+        const double y4r = s4 * yr, y4i = s4 * yi;
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) {
+            double c, q;
+            cis2pi_q(reduced_phase(uj, vj, wj, L[i], M[i], N[i]), c, q);
+            const double zr = fma(q, y4i, yr * c);
+            const double zi = fma(q, y4r, -(yi * c));
+            z0r[i] += zr;
+            z0i[i] += zi;
+            zur[i] = fma(uj, zr, zur[i]);
+            zui[i] = fma(uj, zi, zui[i]);
+            zvr[i] = fma(vj, zr, zvr[i]);
+            zvi[i] = fma(vj, zi, zvi[i]);
+            zwr[i] = fma(wj, zr, zwr[i]);
+            zwi[i] = fma(wj, zi, zwi[i]);
+        }
     }
-    if (k0 < n_comp) {
-        double* o = partial + ((int64_t)blockIdx.y * 8) * n_comp + k0;
-        o[0 * n_comp] = z0r;
-        o[1 * n_comp] = z0i;
-        o[2 * n_comp] = zur;
-        o[3 * n_comp] = zui;
-        o[4 * n_comp] = zvr;
-        o[5 * n_comp] = zvi;
-        o[6 * n_comp] = zwr;
-        o[7 * n_comp] = zwi;
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+        const int64_t k = k0 + (int64_t)i * kGradBlock;
+        if (k < n_comp) {
+            double* o = partial + ((int64_t)blockIdx.y * 8) * n_comp + k;
+            o[0 * n_comp] = z0r[i];
+            o[1 * n_comp] = z0i[i];
+            o[2 * n_comp] = zur[i];
+            o[3 * n_comp] = zui[i];
+            o[4 * n_comp] = zvr[i];
+            o[5 * n_comp] = zvi[i];
+            o[6 * n_comp] = zwr[i];
+            o[7 * n_comp] = zwi[i];
+        }
     }
 }
 
@@ -222,16 +246,23 @@ __global__ void k_grad_finish(const double* __restrict__ partial, int64_t n_chun
     d_m[k] = f * (z[5] - (comp[k].m / n) * z[7]);
 }
 
-hipError_t launch_grad(hipStream_t s, int64_t chunk, int64_t n_vis, const double* u,
+hipError_t launch_grad(hipStream_t s, int cpl, int64_t chunk, int64_t n_vis, const double* u,
                        const double* v, const double* w, const void* y, const Comp* comp,
                        int64_t n_comp, int sign, double alpha, double* partial, double* d_flux,
                        double* d_l, double* d_m) {
     if (n_comp <= 0) return hipSuccess;
     const int64_t n_chunks = n_vis > 0 ? (n_vis + chunk - 1) / chunk : 0;
     if (n_chunks > 0) {
-        const dim3 grid((unsigned)((n_comp + kGradBlock - 1) / kGradBlock), (unsigned)n_chunks);
-        k_grad_partial<<<grid, dim3(kGradBlock), 0, s>>>(u, v, w, (const double2*)y, n_vis, chunk,
-                                                         comp, n_comp, (double)sign, partial);
+        const int64_t per_block = (int64_t)kGradBlock * cpl;
+        const dim3 grid((unsigned)((n_comp + per_block - 1) / per_block), (unsigned)n_chunks);
+        const double sg = (double)sign;
+        const double2* yy = (const double2*)y;
+        switch (cpl) {
+            case 1: k_grad_partial<1><<<grid, dim3(kGradBlock), 0, s>>>(u, v, w, yy, n_vis, chunk, comp, n_comp, sg, partial); break;
+            case 2: k_grad_partial<2><<<grid, dim3(kGradBlock), 0, s>>>(u, v, w, yy, n_vis, chunk, comp, n_comp, sg, partial); break;
+            case 4: k_grad_partial<4><<<grid, dim3(kGradBlock), 0, s>>>(u, v, w, yy, n_vis, chunk, comp, n_comp, sg, partial); break;
+            default: return hipErrorInvalidValue;
+        }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

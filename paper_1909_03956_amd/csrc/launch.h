@@ -46,7 +46,7 @@ hipError_t launch_adjoint(hipStream_t s, int prec, int ppl, int block, int64_t c
                           const void* y, int64_t n_pix, const double* l, const double* m,
                           const double* nm1, int sign, void* partial, void* out);
 
-hipError_t launch_grad(hipStream_t s, int64_t chunk, int64_t n_vis, const double* u,
+hipError_t launch_grad(hipStream_t s, int cpl, int64_t chunk, int64_t n_vis, const double* u,
                        const double* v, const double* w, const void* y, const Comp* comp,
                        int64_t n_comp, int sign, double alpha, double* partial, double* d_flux,
                        double* d_l, double* d_m);
@@ -56,5 +56,46 @@ hipError_t launch_residual(hipStream_t s, int64_t n_vis, const void* obs, const 
 
 // Number of blocks launch_residual uses (its partial buffer holds that many doubles).
 int residual_blocks(int64_t n_vis);
+
+// ------------------------------------------------------------ batched --
+// One prediction instance as the persistent kernels read it.
+struct BatchInst {
+    const double* u;
+    const double* v;
+    const double* w;
+    void* out;
+    const double* l;      // direct: caller's components, packed by the batched ingest
+    const double* m;
+    const double* flux;
+    const TRec* rec;      // tree: record stream on the device
+    int64_t n_vis;
+    int64_t comp_offset;  // direct: first packed component of this instance
+    int n_comp;
+    int n_roots;
+    int J;
+    int prec;
+    double sgn;
+};
+
+// A tile of rows [row0, row0 + nrows) of one instance.
+struct WorkItem {
+    int64_t row0;
+    int inst;
+    int nrows;
+};
+
+hipError_t launch_batch_ingest(hipStream_t s, const BatchInst* inst, int n_inst, int max_comp,
+                               Comp* pack, int* status);
+hipError_t launch_reset_counters(hipStream_t s, unsigned* counters, int n);
+// Blocks per CU that stay resident for the persistent kernels.
+int batch_direct_blocks_per_cu(int vpl, int block);
+int batch_tree_blocks_per_cu(int jmax);
+hipError_t launch_batch_direct(hipStream_t s, int vpl, int block, int grid,
+                               const BatchInst* inst, const Comp* pack, const WorkItem* items,
+                               unsigned n_items, unsigned* counter, int* status);
+hipError_t launch_batch_tree(hipStream_t s, int jmax, int grid, const TreeArgs& scales,
+                             const BatchInst* inst, const WorkItem* items, unsigned n_items,
+                             unsigned* counter, int* status);
+constexpr int kBatchTreeBlock = 64;
 
 }  // namespace swv

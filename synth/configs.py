@@ -179,3 +179,48 @@ class BatchedWorkload:
         l, m, flux = models.blob_mixture_components(inst.n_comp, 0.7, 5, 0.1, 3.0, 4.0, rng)
         return (np.ascontiguousarray(u[keep]), np.ascontiguousarray(v[keep]),
                 np.ascontiguousarray(w[keep]), l, m, flux)
+
+    def instance_rows_kept(self, inst: Instance):
+        """Original (time-major) row index of every unflagged row, and the
+        instance's components, drawn exactly as instance_inputs draws them."""
+        rng = np.random.default_rng(inst.seed)
+        n_rows = CFG2.track.n_baselines * inst.n_t
+        keep = rng.random(n_rows) >= inst.flag_frac
+        l, m, flux = models.blob_mixture_components(inst.n_comp, 0.7, 5, 0.1, 3.0, 4.0, rng)
+        return np.nonzero(keep)[0].astype(np.int64), l, m, flux
+
+    def instance_uvw_rows(self, inst: Instance, rows):
+        """(u, v, w) of selected original rows, element by element on the host."""
+        bxyz = tracks.array_baselines_xyz(CFG2.track.n_ant, CFG2.track.radius_m,
+                                          CFG2.track.seed)
+        return tracks.uvw_rows(bxyz, inst.n_t, 8 * H, inst.dec_deg, inst.channel_hz, rows)
+
+    def instance_uvw_torch(self, inst: Instance, kept, device):
+        """(u, v, w) of the kept rows as float64 tensors on `device`.  The same
+        expressions as tracks.uvw_from_baselines in the same order, evaluated
+        with torch element by element (sin and cos of the hour angles on the
+        host), so each row equals the host generator's."""
+        import torch
+        bxyz = tracks.array_baselines_xyz(CFG2.track.n_ant, CFG2.track.radius_m,
+                                          CFG2.track.seed)
+        Hs = tracks.hour_angles(8 * H, inst.n_t)
+        lam = tracks.C_LIGHT / inst.channel_hz
+        dec = math.radians(inst.dec_deg)
+        sd, cd = np.sin(dec), np.cos(dec)
+        T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64,  # noqa
+                                      device=device)
+        X, Y, Z = (T(bxyz[:, i])[None, :] for i in range(3))
+        sH, cH = T(np.sin(Hs))[:, None], T(np.cos(Hs))[:, None]
+        idx = torch.as_tensor(kept, device=device)
+        out = []
+        for expr in ("u", "v", "w"):
+            if expr == "u":
+                a = sH * X + cH * Y
+            elif expr == "v":
+                a = (-sd) * cH * X + (sd * sH) * Y + cd * Z
+            else:
+                a = (cd * cH) * X - (cd * sH) * Y + sd * Z
+            a = a.reshape(-1).index_select(0, idx)
+            out.append((a / torch.full_like(a, lam)).contiguous())
+            del a
+        return tuple(out)
