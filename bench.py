@@ -65,6 +65,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--profile", action="store_true",
                    help="short run for a profiler: no CPU baseline")
+    p.add_argument("--no-tune", action="store_true",
+                   help="keep the default tile shapes instead of autotuning first")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run one device copy of 1 GiB (HBM counter calibration)")
     return p.parse_args()
@@ -219,6 +221,13 @@ def main():
     torch.cuda.synchronize()
     log(f"inputs ready in {time.perf_counter() - t_in:.1f} s: {n_vis} rows, {n_comp} "
         f"components, {n_pix} pixels")
+    ctx = swv.context(dev)
+    families = ("direct_fp64", "direct_f32c", "tree", "adjoint", "grad")
+    if not args.no_tune:
+        t_tune = time.perf_counter()
+        ctx.autotune(quick=True)                  # untimed: picks the tile shapes
+        log(f"autotuned in {time.perf_counter() - t_tune:.2f} s")
+    tuning = {f: ctx.tune_get(i, 1) for i, f in enumerate(families)}
 
     stages = ["direct_fp64", "direct_f32c"] + [f"tree_J{J}" for J in TREE_LEVELS] + \
         ["residual", "adjoint", "grad"]
@@ -338,11 +347,14 @@ def main():
                    "tree_levels": list(TREE_LEVELS), "terms_per_step": step_terms},
         "routes": routes,
         "roofline": roofline,
+        "tile_shapes": {f: {"per_lane": pl, "block": bl} for f, (pl, bl) in tuning.items()},
     }
     if args.copy_calibration:
-        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        # an elementwise kernel that reads 1 GiB and writes 1 GiB (a memcpy
+        # would run on the copy engine, outside the counters' view)
+        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = a.numel() * 8
     if not (args.no_cpu_baseline or args.profile):

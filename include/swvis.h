@@ -154,6 +154,12 @@ int swv_tree_leaves(swv_tree tree, int64_t* pix, double* l, double* m, double* n
 int swv_tree_level(swv_tree tree, int j, int64_t* pix, int32_t* child_mask, double* lambda,
                    double* gamma);
 
+/* Replaces the flux of every leaf (HOST array of n_leaves entries, in leaf
+ * order) and recomputes lambda and gamma on the same pixel set; the tree's
+ * device copies are refreshed in place, so plans and captured graphs that use
+ * the tree predict the new model.  Waits for the devices holding copies. */
+int swv_tree_set_flux(swv_tree tree, const double* leaf_flux);
+
 /* Model visibilities by the wavelet route (section 3.3, Eqs. 14-17; the
  * per-visibility work of section 3.6.1): for every row, the plane wave
  * eta_{J,k} = exp(s 2 pi i B . (s_k - P)) at the leaf centres, then per

@@ -9,4 +9,6 @@ from .api import (BatchPlan, Context, Graph, Tree, adjoint, ang2pix, context,  #
                   grad_direct, pixel_centres, pixels_in_disk, predict_direct, residual_chi2,
                   synchronize)
 
+from . import autograd  # noqa: F401,E402
+
 __version__ = "1.0"

@@ -43,7 +43,7 @@ def _dev_f64(t, name, device=None):
         raise TypeError(f"{name} must be float64")
     if t.dim() != 1:
         raise ValueError(f"{name} must be 1-D")
-    return t.contiguous()
+    return t.resolve_neg().contiguous()
 
 
 def _dev_c128(t, name, device):
@@ -51,7 +51,9 @@ def _dev_c128(t, name, device):
         raise TypeError(f"{name} must be a complex128 tensor on {device}")
     if t.dim() != 1:
         raise ValueError(f"{name} must be 1-D")
-    return t.contiguous()
+    # a lazily conjugated (or negated) view keeps the original values in
+    # memory: materialise it before its pointer is handed to the library
+    return t.resolve_conj().resolve_neg().contiguous()
 
 
 def _host_f64(x):
@@ -198,6 +200,13 @@ class Tree:
         check(lib().swv_tree_level(self._h, j, _np_ptr(pix), _np_ptr(mask), _np_ptr(lam),
                                    _np_ptr(gam)))
         return {"pix": pix, "mask": mask, "lambda": lam, "gamma": gam}
+
+    def set_leaf_flux(self, flux):
+        """New flux per leaf (leaf order), same pixel set; coefficients recomputed."""
+        f = _host_f64(flux)
+        if f.size != self.stats()["n_leaves"]:
+            raise ValueError("one flux per leaf is needed")
+        check(lib().swv_tree_set_flux(self._h, _np_ptr(f)))
 
     def predict(self, u, v, w, sign: int = -1, prec="fp64", out=None):
         """Model visibilities by the wavelet route (Eqs. 14-17); complex128."""

@@ -1,5 +1,6 @@
 // C ABI of libswvis: argument checks, context and workspace management, tree
 // upload and kernel dispatch.  No exception crosses this file's functions.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -57,6 +58,17 @@ void tune_defaults(swv_ctx ctx) {
 }
 
 int size_class(int64_t rows) { return rows < (int64_t(1) << 20) ? 0 : 1; }
+
+// Rows per chunk so that tiles x chunks gives every CU several blocks.
+int64_t choose_chunk(int64_t n_rows, int64_t tiles, int n_cu, int blocks_per_cu) {
+    if (n_rows <= 0) return 1;
+    int64_t want = ((int64_t)n_cu * blocks_per_cu + tiles - 1) / tiles;
+    if (want < 1) want = 1;
+    int64_t chunk = (n_rows + want - 1) / want;
+    if (chunk < 64) chunk = 64;
+    if (chunk > (int64_t(1) << 30)) chunk = int64_t(1) << 30;  // rows per chunk fit an int
+    return chunk;
+}
 
 bool tune_valid(int family, int per_lane, int block) {
     if (family < 0 || family >= kFamilies) return false;
@@ -327,6 +339,33 @@ int swv_tree_level(swv_tree t, int j, int64_t* pix, int32_t* child_mask, double*
     return SWV_OK;
 }
 
+int swv_tree_set_flux(swv_tree t, const double* leaf_flux) {
+    if (!t) return fail(SWV_EINVAL, "swv_tree_set_flux: null tree");
+    const size_t n = t->leaf_pix.size();
+    if (n > 0 && !leaf_flux) return fail(SWV_EINVAL, "swv_tree_set_flux: null leaf_flux");
+    for (size_t k = 0; k < n; ++k)
+        if (!std::isfinite(leaf_flux[k]))
+            return fail(SWV_EDOMAIN, "swv_tree_set_flux: flux %zu is not finite", k);
+    TRY_BEGIN
+    for (auto& kv : t->device_records) {   // device copies may still be read
+        DeviceGuard g(kv.first);
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    }
+    const size_t n_rec = t->records.size();
+    std::copy(leaf_flux, leaf_flux + n, t->leaf_flux.begin());
+    build_coefficients(t);
+    if (t->records.size() != n_rec) return fail(SWV_EINVAL, "swv_tree_set_flux: internal error");
+    for (auto& kv : t->device_records) {   // same structure: refresh in place
+        DeviceGuard g(kv.first);
+        hipError_t e = hipMemcpy(kv.second, t->records.data(), n_rec * sizeof(TRec),
+                                 hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "swv_tree_set_flux upload");
+    }
+    return SWV_OK;
+    TRY_END
+}
+
 int swv_predict_tree(swv_ctx ctx, swv_tree t, int64_t n_vis, const double* u, const double* v,
                      const double* w, int sign, int prec, void* vis_out) {
     CHECK_CTX(ctx);
@@ -466,16 +505,6 @@ int swv_residual_chi2(swv_ctx ctx, int64_t n_vis, const void* vis_obs, const voi
     TRY_END
 }
 
-// Rows per chunk so that tiles x chunks gives every CU several blocks.
-static int64_t choose_chunk(int64_t n_rows, int64_t tiles, int n_cu, int blocks_per_cu) {
-    if (n_rows <= 0) return 1;
-    int64_t want = ((int64_t)n_cu * blocks_per_cu + tiles - 1) / tiles;
-    if (want < 1) want = 1;
-    int64_t chunk = (n_rows + want - 1) / want;
-    if (chunk < 64) chunk = 64;
-    if (chunk > (int64_t(1) << 30)) chunk = int64_t(1) << 30;  // rows per chunk fit an int
-    return chunk;
-}
 
 int swv_adjoint(swv_ctx ctx, int64_t n_vis, const double* u, const double* v, const double* w,
                 const void* y, int64_t n_pix, const double* l, const double* m,
@@ -494,7 +523,7 @@ int swv_adjoint(swv_ctx ctx, int64_t n_vis, const double* u, const double* v, co
     const int sc = size_class(n_vis);
     const int ppl = ctx->per_lane[kFamAdjoint][sc], block = ctx->block[kFamAdjoint][sc];
     const int64_t tiles = (n_pix + (int64_t)ppl * block - 1) / ((int64_t)ppl * block);
-    const int64_t chunk = choose_chunk(n_vis, tiles, ctx->n_cu, 8);
+    const int64_t chunk = choose_chunk(n_vis, tiles, ctx->n_cu, kAdjointBlocksPerCU);
     const int64_t n_chunks = n_vis > 0 ? (n_vis + chunk - 1) / chunk : 0;
     rc = ensure(ctx, ctx->partial, 16 * (size_t)n_pix * (size_t)(n_chunks > 0 ? n_chunks : 1));
     if (rc) return rc;
@@ -525,7 +554,7 @@ int swv_grad_direct(swv_ctx ctx, int64_t n_vis, const double* u, const double* v
     HIPCALL(launch_ingest(ctx->stream, n_comp, l, m, flux, comp, ctx->d_status));
     const int cpl = ctx->per_lane[kFamGrad][size_class(n_vis)];
     const int64_t tiles = (n_comp + 128 * cpl - 1) / (128 * cpl);
-    const int64_t chunk = choose_chunk(n_vis, tiles, ctx->n_cu, 16);
+    const int64_t chunk = choose_chunk(n_vis, tiles, ctx->n_cu, kGradBlocksPerCU);
     const int64_t n_chunks = n_vis > 0 ? (n_vis + chunk - 1) / chunk : 0;
     rc = ensure(ctx, ctx->partial, 64 * (size_t)n_comp * (size_t)(n_chunks > 0 ? n_chunks : 1));
     if (rc) return rc;

@@ -397,31 +397,35 @@ int swv_autotune(swv_ctx ctx, const char* cache_path, int flags) {
     if (!ctx) return fail(SWV_EINVAL, "swv_autotune: null context");
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(SWV_EHIP, "swv_autotune: cannot select device");
-    const int reps = (flags & 1) ? 1 : 3;
+    // timed repetitions after one warm-up launch; the minimum is kept
+    const int reps = (flags & 1) ? 2 : 5;
     const int64_t rows_of[2] = {int64_t(1) << 18, int64_t(1) << 22};
-    const int n_comp = 256, n_pix = 512;
+    // problem sizes of a wide-field major cycle: a few thousand components,
+    // an image of about a thousand pixels
+    const int n_comp = 2048, n_pix = 1024;
+    const int n_par = n_comp > n_pix ? n_comp : n_pix;
     const hipStream_t s = ctx->stream;
     Scratch sc;
     const int64_t nmax = rows_of[1];
     double *u = sc.alloc(nmax), *v = sc.alloc(nmax), *w = sc.alloc(nmax), *y = sc.alloc(2 * nmax);
-    double *l = sc.alloc(n_pix), *m = sc.alloc(n_pix), *f = sc.alloc(n_pix), *nm = sc.alloc(n_pix);
+    double *l = sc.alloc(n_par), *m = sc.alloc(n_par), *f = sc.alloc(n_par), *nm = sc.alloc(n_par);
     double *out = sc.alloc(2 * nmax), *part = nullptr;
-    double *g1 = sc.alloc(n_pix), *g2 = sc.alloc(n_pix), *g3 = sc.alloc(n_pix);
+    double *g1 = sc.alloc(n_comp), *g2 = sc.alloc(n_comp), *g3 = sc.alloc(n_comp);
     if (!u || !v || !w || !y || !l || !m || !f || !nm || !out || !g1 || !g2 || !g3)
         return fail(SWV_ENOMEM, "swv_autotune: scratch allocation failed");
     struct F { double* p; int64_t n; double lo, hi; } fills[] = {
         {u, nmax, -1e5, 1e5}, {v, nmax, -1e5, 1e5}, {w, nmax, -2e4, 2e4}, {y, 2 * nmax, -1, 1},
-        {l, n_pix, -0.03, 0.03}, {m, n_pix, -0.03, 0.03}, {f, n_pix, 0.01, 1.0},
-        {nm, n_pix, -1e-3, -1e-6}};
+        {l, n_par, -0.03, 0.03}, {m, n_par, -0.03, 0.03}, {f, n_par, 0.01, 1.0},
+        {nm, n_par, -1e-3, -1e-6}};
     uint64_t seed = 12345;
     for (const F& x : fills)
         k_fill<<<dim3((unsigned)((x.n + 255) / 256)), dim3(256), 0, s>>>(x.p, x.n, seed++, x.lo, x.hi);
     Comp* comp = nullptr;
     {
-        int rc = ensure(ctx, ctx->comp, sizeof(Comp) * n_pix);
+        int rc = ensure(ctx, ctx->comp, sizeof(Comp) * n_comp);
         if (rc) return rc;
         comp = (Comp*)ctx->comp.p;
-        hipError_t e = launch_ingest(s, n_pix, l, m, f, comp, ctx->d_status);
+        hipError_t e = launch_ingest(s, n_comp, l, m, f, comp, ctx->d_status);
         if (e != hipSuccess) return hip_fail(e, "autotune ingest");
     }
     // a level-9 tree of 1,024 components in a 3 degree field
@@ -473,8 +477,7 @@ int swv_autotune(swv_ctx ctx, const char* cache_path, int flags) {
                             e = launch_tree(s, bl, ta, rows, u, v, w, -1, out, ctx->d_status);
                         } else if (fam == kFamAdjoint) {
                             const int64_t tiles = (n_pix + (int64_t)pl * bl - 1) / ((int64_t)pl * bl);
-                            int64_t want = ((int64_t)ctx->n_cu * 8 + tiles - 1) / tiles;
-                            const int64_t chunk = std::max<int64_t>(64, (rows + want - 1) / want);
+                            const int64_t chunk = choose_chunk(rows, tiles, ctx->n_cu, kAdjointBlocksPerCU);
                             const int64_t nch = (rows + chunk - 1) / chunk;
                             rc = ensure(ctx, ctx->partial, 16 * (size_t)n_pix * nch);
                             if (rc) { result = rc; break; }
@@ -483,8 +486,7 @@ int swv_autotune(swv_ctx ctx, const char* cache_path, int flags) {
                                                l, m, nm, -1, part, out);
                         } else {
                             const int64_t tiles = (n_comp + 128 * pl - 1) / (128 * pl);
-                            int64_t want = ((int64_t)ctx->n_cu * 16 + tiles - 1) / tiles;
-                            const int64_t chunk = std::max<int64_t>(64, (rows + want - 1) / want);
+                            const int64_t chunk = choose_chunk(rows, tiles, ctx->n_cu, kGradBlocksPerCU);
                             const int64_t nch = (rows + chunk - 1) / chunk;
                             rc = ensure(ctx, ctx->partial, 64 * (size_t)n_comp * nch);
                             if (rc) { result = rc; break; }

@@ -5,13 +5,41 @@
 // Adjoint and gradients swap the roles of the direct kernel: lanes own the
 // outputs (pixels or components) and every lane of the wave walks the same
 // visibility rows, read with scalar loads.  The visibility axis is split
-// into fixed chunks (grid.y); each (tile, chunk) block writes its partial
-// sums, and a second kernel adds the chunks in index order -- deterministic
-// and free of atomics.
+// into fixed chunks; each (chunk, tile) block writes its partial sums, and a
+// second kernel adds the chunks in index order -- deterministic and free of
+// atomics.
+//
+// Block order (1-D grid): workgroups are dealt to the 8 XCDs round-robin by
+// linear id, and blocks sharing a chunk read the same rows.  Ids therefore
+// walk groups of 8 chunks -- one per XCD -- and, inside a group, all tiles in
+// consecutive dispatch rounds: every tile of a chunk runs on the same XCD at
+// about the same time and the chunk's rows come from HBM into one L2 once.
 #include "device_math.h"
 #include "launch.h"
 
 namespace swv {
+
+// Chunk count rounded up to a whole number of XCD rounds.
+static int64_t xcd_padded(int64_t n_chunks) { return (n_chunks + 7) / 8 * 8; }
+
+// (chunk, tile) of linear block id `bid` in the order described above.
+__device__ __forceinline__ void chunk_tile(int64_t bid, int64_t tiles, int64_t& chunk,
+                                           int64_t& tile) {
+    const int64_t per_group = 8 * tiles;
+    const int64_t g = bid / per_group;
+    const int64_t r = bid - g * per_group;
+    tile = r >> 3;
+    chunk = g * 8 + (r & 7);
+}
+
+// Launches `total` blocks as 1-D grids of at most 2^30 blocks, passing the
+// first linear id of each.
+template <class F>
+static void launch_slabs(int64_t total, F&& launch) {
+    constexpr int64_t kSlab = int64_t(1) << 30;
+    for (int64_t b0 = 0; b0 < total; b0 += kSlab)
+        launch(b0, (unsigned)(total - b0 < kSlab ? total - b0 : kSlab));
+}
 
 // ---------------------------------------------------------------- adjoint --
 // img[p] = sum_j conj(e_jp) y_j, e = exp(s 2 pi i phi).  With e = c + i s S:
@@ -21,8 +49,11 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
     const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
     const double2* __restrict__ y, int64_t n_vis, int64_t chunk, const double* __restrict__ pl,
     const double* __restrict__ pm, const double* __restrict__ pn, int64_t n_pix, double sgn,
-    double2* __restrict__ partial) {
-    const int64_t p0 = (int64_t)blockIdx.x * (BLOCK * PPL) + threadIdx.x;
+    int64_t n_chunks, int64_t tiles, int64_t bid0, double2* __restrict__ partial) {
+    int64_t chunk_id, tile;
+    chunk_tile(bid0 + blockIdx.x, tiles, chunk_id, tile);
+    if (chunk_id >= n_chunks) return;   // padding of the last XCD group
+    const int64_t p0 = tile * (BLOCK * PPL) + threadIdx.x;
     double L[PPL], M[PPL], N[PPL];
     double ar[PPL], ai[PPL];
     float sr[PPL], cr[PPL], si[PPL], ci[PPL];
@@ -36,7 +67,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
         ar[i] = ai[i] = 0.0;
         sr[i] = cr[i] = si[i] = ci[i] = 0.0f;
     }
-    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j0 = chunk_id * chunk;
     const int64_t j1 = j0 + chunk < n_vis ? j0 + chunk : n_vis;
     // wave-uniform trip count, kept in scalar registers
     const int nrow = __builtin_amdgcn_readfirstlane((int)(j1 - j0));
@@ -81,7 +112,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
                 o = make_double2(ar[i], ai[i]);
             else
                 o = make_double2((double)sr[i] - (double)cr[i], (double)si[i] - (double)ci[i]);
-            partial[(int64_t)blockIdx.y * n_pix + p] = o;
+            partial[chunk_id * n_pix + p] = o;
         }
     }
 }
@@ -101,17 +132,20 @@ __global__ void k_sum_chunks_c128(const double2* __restrict__ partial, int64_t n
 }
 
 template <int PPL, int BLOCK, int PREC>
-static void run_adjoint(hipStream_t s, dim3 grid, int64_t chunk, int64_t n_vis, const double* u,
-                        const double* v, const double* w, const void* y, int64_t n_pix,
-                        const double* l, const double* m, const double* nm1, int sign,
-                        void* partial) {
-    k_adjoint<PPL, BLOCK, PREC><<<grid, dim3(BLOCK), 0, s>>>(
-        u, v, w, (const double2*)y, n_vis, chunk, l, m, nm1, n_pix, (double)sign,
-        (double2*)partial);
+static void run_adjoint(hipStream_t s, int64_t tiles, int64_t chunk, int64_t n_vis,
+                        const double* u, const double* v, const double* w, const void* y,
+                        int64_t n_pix, const double* l, const double* m, const double* nm1,
+                        int sign, void* partial) {
+    const int64_t n_chunks = (n_vis + chunk - 1) / chunk;
+    launch_slabs(xcd_padded(n_chunks) * tiles, [&](int64_t b0, unsigned nb) {
+        k_adjoint<PPL, BLOCK, PREC><<<dim3(nb), dim3(BLOCK), 0, s>>>(
+            u, v, w, (const double2*)y, n_vis, chunk, l, m, nm1, n_pix, (double)sign, n_chunks,
+            tiles, b0, (double2*)partial);
+    });
 }
 
 template <int PPL, int PREC>
-static hipError_t run_adjoint_b(hipStream_t s, int block, dim3 grid, int64_t chunk,
+static hipError_t run_adjoint_b(hipStream_t s, int block, int64_t grid, int64_t chunk,
                                 int64_t n_vis, const double* u, const double* v, const double* w,
                                 const void* y, int64_t n_pix, const double* l, const double* m,
                                 const double* nm1, int sign, void* partial) {
@@ -132,7 +166,7 @@ hipError_t launch_adjoint(hipStream_t s, int prec, int ppl, int block, int64_t c
     const int64_t n_chunks = n_vis > 0 ? (n_vis + chunk - 1) / chunk : 0;
     if (n_chunks > 0) {
         const int64_t per_block = (int64_t)block * ppl;
-        const dim3 grid((unsigned)((n_pix + per_block - 1) / per_block), (unsigned)n_chunks);
+        const int64_t grid = (n_pix + per_block - 1) / per_block;   // pixel tiles
         hipError_t e;
         if (prec == SWV_FP64) {
             switch (ppl) {
@@ -167,8 +201,12 @@ template <int CPL>
 __global__ __launch_bounds__(kGradBlock) void k_grad_partial(
     const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
     const double2* __restrict__ y, int64_t n_vis, int64_t chunk, const Comp* __restrict__ comp,
-    int64_t n_comp, double sgn, double* __restrict__ partial) {
-    const int64_t k0 = (int64_t)blockIdx.x * (kGradBlock * CPL) + threadIdx.x;
+    int64_t n_comp, double sgn, int64_t n_chunks, int64_t tiles, int64_t bid0,
+    double* __restrict__ partial) {
+    int64_t chunk_id, tile;
+    chunk_tile(bid0 + blockIdx.x, tiles, chunk_id, tile);
+    if (chunk_id >= n_chunks) return;   // padding of the last XCD group
+    const int64_t k0 = tile * (kGradBlock * CPL) + threadIdx.x;
     double L[CPL], M[CPL], N[CPL];
     double z0r[CPL], z0i[CPL], zur[CPL], zui[CPL], zvr[CPL], zvi[CPL], zwr[CPL], zwi[CPL];
 #pragma unroll
@@ -180,7 +218,7 @@ __global__ __launch_bounds__(kGradBlock) void k_grad_partial(
         N[i] = comp[k].nm1;
         z0r[i] = z0i[i] = zur[i] = zui[i] = zvr[i] = zvi[i] = zwr[i] = zwi[i] = 0.0;
     }
-    const int64_t j0 = (int64_t)blockIdx.y * chunk;
+    const int64_t j0 = chunk_id * chunk;
     const int64_t j1 = j0 + chunk < n_vis ? j0 + chunk : n_vis;
     // wave-uniform trip count, kept in scalar registers
     const int nrow = __builtin_amdgcn_readfirstlane((int)(j1 - j0));
@@ -214,7 +252,7 @@ __global__ __launch_bounds__(kGradBlock) void k_grad_partial(
     for (int i = 0; i < CPL; ++i) {
         const int64_t k = k0 + (int64_t)i * kGradBlock;
         if (k < n_comp) {
-            double* o = partial + ((int64_t)blockIdx.y * 8) * n_comp + k;
+            double* o = partial + (chunk_id * 8) * n_comp + k;
             o[0 * n_comp] = z0r[i];
             o[1 * n_comp] = z0i[i];
             o[2 * n_comp] = zur[i];
@@ -254,15 +292,19 @@ hipError_t launch_grad(hipStream_t s, int cpl, int64_t chunk, int64_t n_vis, con
     const int64_t n_chunks = n_vis > 0 ? (n_vis + chunk - 1) / chunk : 0;
     if (n_chunks > 0) {
         const int64_t per_block = (int64_t)kGradBlock * cpl;
-        const dim3 grid((unsigned)((n_comp + per_block - 1) / per_block), (unsigned)n_chunks);
+        const int64_t tiles = (n_comp + per_block - 1) / per_block;
         const double sg = (double)sign;
         const double2* yy = (const double2*)y;
-        switch (cpl) {
-            case 1: k_grad_partial<1><<<grid, dim3(kGradBlock), 0, s>>>(u, v, w, yy, n_vis, chunk, comp, n_comp, sg, partial); break;
-            case 2: k_grad_partial<2><<<grid, dim3(kGradBlock), 0, s>>>(u, v, w, yy, n_vis, chunk, comp, n_comp, sg, partial); break;
-            case 4: k_grad_partial<4><<<grid, dim3(kGradBlock), 0, s>>>(u, v, w, yy, n_vis, chunk, comp, n_comp, sg, partial); break;
-            default: return hipErrorInvalidValue;
-        }
+        if (cpl != 1 && cpl != 2 && cpl != 4) return hipErrorInvalidValue;
+        launch_slabs(xcd_padded(n_chunks) * tiles, [&](int64_t b0, unsigned nb) {
+            const dim3 g(nb), b(kGradBlock);
+            if (cpl == 1)
+                k_grad_partial<1><<<g, b, 0, s>>>(u, v, w, yy, n_vis, chunk, comp, n_comp, sg, n_chunks, tiles, b0, partial);
+            else if (cpl == 2)
+                k_grad_partial<2><<<g, b, 0, s>>>(u, v, w, yy, n_vis, chunk, comp, n_comp, sg, n_chunks, tiles, b0, partial);
+            else
+                k_grad_partial<4><<<g, b, 0, s>>>(u, v, w, yy, n_vis, chunk, comp, n_comp, sg, n_chunks, tiles, b0, partial);
+        });
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

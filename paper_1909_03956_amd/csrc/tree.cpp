@@ -40,47 +40,9 @@ static void emit(const swv_tree_s& t, int j, int64_t idx, std::vector<TRec>& out
         if (L.mask[idx] & (1 << c)) emit(t, j + 1, child++, out);
 }
 
-int build_tree(int J, double ra_p, double dec_p, int64_t n, const double* l, const double* m,
-               const double* flux, swv_tree_s* t) {
-    const auto t0 = std::chrono::steady_clock::now();
-    const Frame F = make_frame(ra_p, dec_p);
-
-    // pixel of every component
-    std::vector<int64_t> kJ(n);
-    for (int64_t i = 0; i < n; ++i) {
-        ld xyz[3];
-        lm_to_xyz(F, l[i], m[i], xyz);
-        kJ[i] = ang2pix(J, xyz);
-    }
-    std::vector<int64_t> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int64_t a, int64_t b) { return kJ[a] < kJ[b]; });
-
-    t->J = J;
-    t->ra_p = ra_p;
-    t->dec_p = dec_p;
-    t->n_comp = n;
-    t->leaf_pix.clear();
-    t->leaf_flux.clear();
-    for (int64_t s = 0; s < n;) {
-        int64_t e = s;
-        double f = 0.0;
-        while (e < n && kJ[order[e]] == kJ[order[s]]) f += flux[order[e++]];
-        t->leaf_pix.push_back(kJ[order[s]]);
-        t->leaf_flux.push_back(f);
-        s = e;
-    }
+void build_coefficients(swv_tree_s* t) {
+    const int J = t->J;
     const int64_t nl = (int64_t)t->leaf_pix.size();
-    t->leaf_l.resize(nl);
-    t->leaf_m.resize(nl);
-    t->leaf_nm1.resize(nl);
-    for (int64_t k = 0; k < nl; ++k) {
-        ld xyz[3];
-        pix2xyz(J, t->leaf_pix[k], xyz);
-        xyz_to_lmn(F, xyz, &t->leaf_l[k], &t->leaf_m[k], &t->leaf_nm1[k]);
-    }
-
     // levels J .. 1
     t->levels.assign(J, TreeLevel());
     TreeLevel& top = t->levels[J - 1];
@@ -128,6 +90,50 @@ int build_tree(int J, double ra_p, double dec_p, int64_t n, const double* l, con
         t->records.push_back(TRec{A1 * L1.lambda[r], 0.0, 0.0, 0ull});
         emit(*t, 1, r, t->records);
     }
+}
+
+int build_tree(int J, double ra_p, double dec_p, int64_t n, const double* l, const double* m,
+               const double* flux, swv_tree_s* t) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const Frame F = make_frame(ra_p, dec_p);
+
+    // pixel of every component
+    std::vector<int64_t> kJ(n);
+    for (int64_t i = 0; i < n; ++i) {
+        ld xyz[3];
+        lm_to_xyz(F, l[i], m[i], xyz);
+        kJ[i] = ang2pix(J, xyz);
+    }
+    std::vector<int64_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return kJ[a] < kJ[b]; });
+
+    t->J = J;
+    t->ra_p = ra_p;
+    t->dec_p = dec_p;
+    t->n_comp = n;
+    t->leaf_pix.clear();
+    t->leaf_flux.clear();
+    for (int64_t s = 0; s < n;) {
+        int64_t e = s;
+        double f = 0.0;
+        while (e < n && kJ[order[e]] == kJ[order[s]]) f += flux[order[e++]];
+        t->leaf_pix.push_back(kJ[order[s]]);
+        t->leaf_flux.push_back(f);
+        s = e;
+    }
+    const int64_t nl = (int64_t)t->leaf_pix.size();
+    t->leaf_l.resize(nl);
+    t->leaf_m.resize(nl);
+    t->leaf_nm1.resize(nl);
+    for (int64_t k = 0; k < nl; ++k) {
+        ld xyz[3];
+        pix2xyz(J, t->leaf_pix[k], xyz);
+        xyz_to_lmn(F, xyz, &t->leaf_l[k], &t->leaf_m[k], &t->leaf_nm1[k]);
+    }
+
+    build_coefficients(t);
     t->build_seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return SWV_OK;

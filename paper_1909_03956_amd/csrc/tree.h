@@ -39,6 +39,9 @@ struct swv_tree_s {
 
 namespace swv {
 
+// (Re)computes levels, coefficients and the record stream from the leaves.
+void build_coefficients(swv_tree_s* t);
+
 // Builds the tree; returns a status code (message via fail()).
 int build_tree(int J, double ra_p, double dec_p, int64_t n, const double* l, const double* m,
                const double* flux, swv_tree_s* out);

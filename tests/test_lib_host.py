@@ -156,3 +156,27 @@ def test_host_call_errors(swv):
     assert L.swv_ctx_synchronize(None) == swv.SWV_EINVAL
     assert L.swv_batch_run(None) != 0
     assert L.swv_tree_leaves(None, None, None, None, None, None) == swv.SWV_EINVAL
+
+
+def test_tree_set_flux_recomputes_coefficients(swv):
+    from paper_1909_03956_amd.api import Tree
+    W = configs.CFG2
+    l, m, f = W.components()
+    J = 9
+    t = Tree(J, W.ra_p, W.dec_p, l, m, f)
+    lv = t.leaves()
+    rng = np.random.default_rng(8)
+    F2 = rng.lognormal(-3, 1, lv["flux"].size)
+    t.set_leaf_flux(F2)
+    levels = ot.build_levels(J, lv["pix"], F2)
+    for j in range(1, J + 1):
+        got = t.level(j)
+        exp = levels[j - 1]
+        assert np.array_equal(got["pix"], exp.pix)
+        scale = np.abs(exp.lam).max()
+        assert np.max(np.abs(got["lambda"] - exp.lam)) <= 1e-15 * scale
+        if j < J:
+            assert np.max(np.abs(got["gamma"] - exp.gamma)) <= 1e-15 * scale
+    assert np.array_equal(t.leaves()["flux"], F2)
+    with pytest.raises(ValueError):
+        t.set_leaf_flux(F2[:-1])
