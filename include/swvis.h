@@ -119,6 +119,8 @@ typedef struct {
     int64_t n_records;                       /* length of the depth-first record stream */
     double sparsity;                         /* n_leaves / N_J */
     double build_seconds;                    /* host time of swv_tree_build */
+    int max_branching;                       /* most nodes with >= 2 children on one
+                                                root-to-leaf path */
 } swv_tree_stats_t;
 
 /* Builds the sparse coefficient tree of a component list (sections 3.2-3.5),
@@ -170,7 +172,12 @@ int swv_tree_set_flux(swv_tree tree, const double* leaf_flux);
  * (Eq. 17 with lambda_J a flux density; equal to the direct sum over the
  * pixel-snapped leaves, Eq. 16).  u, v, w [n_vis] DEVICE; vis_out DEVICE
  * complex128 (SWV_FP64 only).  The tree is copied to the device on first use
- * with this context's device. */
+ * with this context's device.
+ * Two traversals compute the same operations in the same order (bitwise equal
+ * results): one keeps a register set per level (J <= 12), the other one per
+ * open node with two or more children (any J, up to 15 such nodes on one
+ * root-to-leaf path, see swv_tree_stats_t.max_branching).  The tuning table
+ * picks between them where both fit; SWV_ENOTSUP if neither does. */
 int swv_predict_tree(swv_ctx ctx, swv_tree tree, int64_t n_vis, const double* u,
                      const double* v, const double* w, int sign, int prec, void* vis_out);
 
@@ -303,8 +310,9 @@ int swv_tune_load(swv_ctx ctx, const char* cache_path);
  * 0 direct FP64, 1 direct F32C, 2 tree, 3 adjoint, 4 gradients.  Size class
  * 0 is fewer than 2^20 visibility rows, 1 the rest.  per_lane is rows per lane
  * (direct), pixels per lane (adjoint) or components per lane (gradients), in
- * {1, 2, 4} (1 for the tree); block is threads per block in {64, 128, 256}
- * (128 for the gradients).  Results do not depend on the shape except for
+ * {1, 2, 4}; for the tree it selects the traversal (1: register set per level,
+ * 2: per branching node; see swv_predict_tree).  block is threads per block
+ * in {64, 128, 256} (128 for the gradients).  Results do not depend on the shape except for
  * the summation order of the adjoint and gradients. */
 int swv_tune_get(swv_ctx ctx, int family, int size_class, int* per_lane, int* block);
 

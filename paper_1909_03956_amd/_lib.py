@@ -10,6 +10,8 @@ SWV_OK, SWV_EINVAL, SWV_EDOMAIN, SWV_ENOMEM, SWV_EHIP, SWV_ENOTSUP = 0, -1, -2, 
 SWV_FP64, SWV_F32C = 0, 1
 SWV_ROUTE_DIRECT, SWV_ROUTE_TREE = 0, 1
 SWV_MAX_LEVEL = 29
+# kernel families of the tuning table (swv_tune_get / swv_tune_set)
+FAM_DIRECT64, FAM_DIRECT32, FAM_TREE, FAM_ADJOINT, FAM_GRAD = 0, 1, 2, 3, 4
 STATUS_NAMES = {0: "SWV_OK", -1: "SWV_EINVAL", -2: "SWV_EDOMAIN", -3: "SWV_ENOMEM",
                 -4: "SWV_EHIP", -5: "SWV_ENOTSUP"}
 
@@ -27,7 +29,7 @@ class TreeStats(C.Structure):
     _fields_ = [("J", C.c_int), ("n_comp", C.c_int64), ("n_leaves", C.c_int64),
                 ("n_internal", C.c_int64), ("n_nodes", C.c_int64 * (SWV_MAX_LEVEL + 1)),
                 ("n_records", C.c_int64), ("sparsity", C.c_double),
-                ("build_seconds", C.c_double)]
+                ("build_seconds", C.c_double), ("max_branching", C.c_int)]
 
 
 class PlanStats(C.Structure):

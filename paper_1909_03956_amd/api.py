@@ -182,7 +182,7 @@ class Tree:
                 "n_internal": s.n_internal,
                 "nodes_per_level": [s.n_nodes[j] for j in range(1, s.J + 1)],
                 "n_records": s.n_records, "sparsity": s.sparsity,
-                "build_seconds": s.build_seconds}
+                "build_seconds": s.build_seconds, "max_branching": s.max_branching}
 
     def leaves(self) -> dict:
         n = self.stats()["n_leaves"]

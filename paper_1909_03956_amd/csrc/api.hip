@@ -74,7 +74,8 @@ bool tune_valid(int family, int per_lane, int block) {
     if (family < 0 || family >= kFamilies) return false;
     const bool pl_ok = per_lane == 1 || per_lane == 2 || per_lane == 4;
     const bool bl_ok = block == 64 || block == 128 || block == 256;
-    if (family == kFamTree) return per_lane == 1 && bl_ok;
+    // tree: per_lane selects the traversal (1 level walker, 2 branch walker)
+    if (family == kFamTree) return (per_lane == 1 || per_lane == 2) && bl_ok;
     if (family == kFamGrad) return pl_ok && block == 128;
     return pl_ok && bl_ok;
 }
@@ -111,11 +112,20 @@ int upload_tree(swv_ctx ctx, swv_tree t, const TRec** out) {
     return SWV_OK;
 }
 
+int tree_walker(swv_tree t, int preferred) {
+    const bool level_ok = t->J <= kTreeMaxJ;
+    const bool branch_ok = t->max_branching + 1 <= kTreeMaxSeg;
+    if (preferred == 2 && branch_ok) return 1;
+    if (level_ok) return 0;
+    return branch_ok ? 1 : -1;
+}
+
 TreeArgs tree_args(swv_tree t, const TRec* d_rec) {
     TreeArgs a;
     a.rec = d_rec;
     a.n_roots = (int)t->n_roots;
     a.J = t->J;
+    a.seg_depth = t->max_branching + 1;
     for (int j = 0; j <= SWV_MAX_LEVEL; ++j) a.scale[j] = t->level_scale[j];
     return a;
 }
@@ -312,6 +322,7 @@ int swv_tree_stats(swv_tree t, swv_tree_stats_t* out) {
     out->n_records = (int64_t)t->records.size();
     out->sparsity = (double)out->n_leaves / (double)n_pixels(t->J);
     out->build_seconds = t->build_seconds;
+    out->max_branching = t->max_branching;
     return SWV_OK;
 }
 
@@ -374,9 +385,13 @@ int swv_predict_tree(swv_ctx ctx, swv_tree t, int64_t n_vis, const double* u, co
     NEED(u, n_vis); NEED(v, n_vis); NEED(w, n_vis); NEED(vis_out, n_vis);
     int rc = check_sign_prec(sign, prec, false);
     if (rc) return rc;
-    if (t->J > kTreeMaxJ)
-        return fail(SWV_ENOTSUP, "swv_predict_tree: J = %d above the compiled maximum %d", t->J,
-                    kTreeMaxJ);
+    const int sc = size_class(n_vis);
+    const int walker = tree_walker(t, ctx->per_lane[kFamTree][sc]);
+    if (walker < 0)
+        return fail(SWV_ENOTSUP,
+                    "swv_predict_tree: J = %d with %d nested branchings on one path: above the "
+                    "compiled maxima (J %d, or %d branchings)",
+                    t->J, t->max_branching, kTreeMaxJ, kTreeMaxSeg - 1);
     if (n_vis == 0) return SWV_OK;
     TRY_BEGIN
     GUARD(ctx);
@@ -384,8 +399,8 @@ int swv_predict_tree(swv_ctx ctx, swv_tree t, int64_t n_vis, const double* u, co
     rc = upload_tree(ctx, t, &rec);
     if (rc) return rc;
     const TreeArgs a = tree_args(t, rec);
-    HIPCALL(launch_tree(ctx->stream, ctx->block[kFamTree][size_class(n_vis)], a, n_vis, u, v, w,
-                        sign, vis_out, ctx->d_status));
+    HIPCALL(launch_tree(ctx->stream, walker, ctx->block[kFamTree][sc], a, n_vis, u, v, w, sign,
+                        vis_out, ctx->d_status));
     return SWV_OK;
     TRY_END
 }

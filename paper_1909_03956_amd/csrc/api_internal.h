@@ -60,5 +60,8 @@ int check_sign_prec(int sign, int prec, bool allow_f32);
 bool tune_valid(int family, int per_lane, int block);
 int upload_tree(swv_ctx ctx, swv_tree t, const TRec** out);
 TreeArgs tree_args(swv_tree t, const TRec* d_rec);
+// Traversal for tree t given the tuned choice (1 level walker, 2 branch
+// walker): 0 level walker, 1 branch walker, -1 if no compiled one fits.
+int tree_walker(swv_tree t, int preferred);
 
 }  // namespace swv

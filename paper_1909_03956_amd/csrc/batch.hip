@@ -25,7 +25,9 @@ struct swv_plan_s {
     unsigned n_items_direct = 0, n_items_tree = 0;
     Comp* d_pack = nullptr;
     unsigned* d_counters = nullptr;  // [0] direct, [1] tree
-    int vpl = 2, block = 256, grid_direct = 0, grid_tree = 0, jmax = 1, max_comp = 0;
+    int vpl = 2, block = 256, grid_direct = 0, grid_tree = 0, max_comp = 0;
+    int jmax = 1, smax = 1;           // largest J and segment depth of the trees
+    int tree_walker = 0, tree_depth = 1;
     int tile_rows = 0;
     int64_t total_terms = 0;
     TreeArgs scales{};
@@ -88,7 +90,7 @@ hipError_t enqueue_plan(swv_plan p, hipStream_t s) {
                             p->d_items_direct, p->n_items_direct, p->d_counters,
                             p->ctx->d_status);
     if (e != hipSuccess) return e;
-    return launch_batch_tree(s, p->jmax, p->grid_tree, p->scales, p->d_tree, p->d_items_tree,
+    return launch_batch_tree(s, p->tree_walker, p->tree_depth, p->grid_tree, p->scales, p->d_tree, p->d_items_tree,
                              p->n_items_tree, p->d_counters + 1, p->ctx->d_status);
 }
 
@@ -111,8 +113,11 @@ int check_instance(const swv_instance& I, int k) {
         if (!I.tree) return fail(SWV_EINVAL, "instance %d: null tree", k);
         if (I.prec != SWV_FP64)
             return fail(SWV_ENOTSUP, "instance %d: the tree route is FP64 only", k);
-        if (I.tree->J > kTreeMaxJ)
-            return fail(SWV_ENOTSUP, "instance %d: J = %d above %d", k, I.tree->J, kTreeMaxJ);
+        if (tree_walker(I.tree, 1) < 0)
+            return fail(SWV_ENOTSUP,
+                        "instance %d: J = %d with %d nested branchings: above the compiled "
+                        "maxima (J %d, or %d branchings)",
+                        k, I.tree->J, I.tree->max_branching, kTreeMaxJ, kTreeMaxSeg - 1);
     }
     return SWV_OK;
 }
@@ -174,6 +179,7 @@ int swv_batch_plan(swv_ctx ctx, int n, const swv_instance* inst, swv_plan* out) 
                 b.n_roots = (int)I.tree->n_roots;
                 b.J = I.tree->J;
                 p->jmax = std::max(p->jmax, b.J);
+                p->smax = std::max(p->smax, I.tree->max_branching + 1);
                 p->tree.push_back(b);
                 cost_per_row_tree.push_back((int64_t)I.tree->records.size() + 1);
                 p->total_terms += I.n_vis * I.tree->n_comp;
@@ -182,10 +188,22 @@ int swv_batch_plan(swv_ctx ctx, int n, const swv_instance* inst, swv_plan* out) 
         for (int j = 0; j <= SWV_MAX_LEVEL; ++j)
             p->scales.scale[j] = j >= 1 ? std::sqrt(pixel_area(j)) / 4.0 : 0.0;
         p->scales.J = p->jmax;
+        // one traversal for all trees of the plan: the tuned one where it fits
+        const bool level_ok = p->jmax <= kTreeMaxJ, branch_ok = p->smax <= kTreeMaxSeg;
+        const bool want_branch = ctx->per_lane[kFamTree][1] == 2;
+        if (!p->tree.empty() && !level_ok && !branch_ok) {
+            delete p;
+            return fail(SWV_ENOTSUP,
+                        "swv_batch_plan: no compiled traversal fits every tree (largest J %d, "
+                        "segment depth %d)",
+                        p->jmax, p->smax);
+        }
+        p->tree_walker = (branch_ok && (want_branch || !level_ok)) ? 1 : 0;
+        p->tree_depth = p->tree_walker ? p->smax : p->jmax;
 
         // persistent grids: as many blocks as stay resident
         p->grid_direct = ctx->n_cu * batch_direct_blocks_per_cu(p->vpl, p->block);
-        p->grid_tree = ctx->n_cu * batch_tree_blocks_per_cu(p->jmax);
+        p->grid_tree = ctx->n_cu * batch_tree_blocks_per_cu(p->tree_walker, p->tree_depth);
         const int64_t waves = (int64_t)p->grid_direct * (p->block / 64);
         // about 16 items per resident wave, in whole wave tiles, at most 64 of them
         const int64_t unit = 64LL * p->vpl;
@@ -474,7 +492,8 @@ int swv_autotune(swv_ctx ctx, const char* cache_path, int flags) {
                             e = launch_direct(s, fam == kFamDirect64 ? SWV_FP64 : SWV_F32C, pl, bl,
                                               rows, u, v, w, comp, n_comp, -1, out, ctx->d_status);
                         } else if (fam == kFamTree) {
-                            e = launch_tree(s, bl, ta, rows, u, v, w, -1, out, ctx->d_status);
+                            e = launch_tree(s, pl == 2 ? 1 : 0, bl, ta, rows, u, v, w, -1, out,
+                                            ctx->d_status);
                         } else if (fam == kFamAdjoint) {
                             const int64_t tiles = (n_pix + (int64_t)pl * bl - 1) / ((int64_t)pl * bl);
                             const int64_t chunk = choose_chunk(rows, tiles, ctx->n_cu, kAdjointBlocksPerCU);

@@ -15,13 +15,27 @@ struct alignas(32) Comp {
 };
 
 // One record of the depth-first tree stream (32 bytes).
-//   root : a = A_1 * lambda_1 of the level-1 node that follows
-//   node : a, b, c = gamma^0, gamma^1, gamma^2; meta = 4-bit child mask
+//   root : a = A_1 * lambda_1 of the level-1 node that follows; meta = 0
+//   node : a, b, c = gamma^0, gamma^1, gamma^2
 //   leaf : a, b, c = l, m, n - 1 of the pixel centre
+// meta of nodes and leaves:
+//   bits 0-3   child mask (bit c set if child 4k + c exists; 0 for a leaf)
+//   bits 8-12  level j
+//   bits 32-63 for a node with exactly one child: the number of consecutive
+//              one-child nodes that start here (this one, its child, ...);
+//              they are contiguous in the stream.  0 otherwise.
 struct alignas(32) TRec {
     double a, b, c;
     unsigned long long meta;
 };
+
+constexpr unsigned meta_mask(unsigned long long meta) { return (unsigned)(meta & 0xFu); }
+constexpr int meta_level(unsigned long long meta) { return (int)((meta >> 8) & 31u); }
+constexpr int meta_chain(unsigned long long meta) { return (int)(meta >> 32); }
+constexpr unsigned long long make_meta(unsigned mask, int level, int chain) {
+    return (unsigned long long)(mask & 0xFu) | ((unsigned long long)level << 8) |
+           ((unsigned long long)(unsigned)chain << 32);
+}
 
 // Deferred-error bits the kernels raise in the context's status word.
 enum : int { kStatusDomain = 1, kStatusNonFinite = 2 };

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_direct(const BatchInst* __restr
     }
 }
 
-template <int JMAX>
+template <int JMAX, int WALKER>
 __global__ __launch_bounds__(kBatchTreeBlock) void k_batch_tree(
     TreeArgs scales, const BatchInst* __restrict__ inst, const WorkItem* __restrict__ items,
     unsigned n_items, unsigned* __restrict__ counter, int* __restrict__ status) {
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kBatchTreeBlock) void k_batch_tree(
             const int64_t j = jr < limit ? jr : limit - 1;
             const double U = u[j], V = v[j], W = w[j];
             double Vr, Vi;
-            tree_row<JMAX>(rec, n_roots, J, scales, U, V, W, Vr, Vi);
+            tree_row<JMAX, WALKER>(rec, n_roots, J, scales, U, V, W, Vr, Vi);
             if (jr < limit) {
                 if (!isfinite(U + V + W)) atomicOr(status, kStatusNonFinite);
                 out[jr] = make_double2(Vr, s4 * Vi);
@@ -142,31 +142,27 @@ int batch_direct_blocks_per_cu(int vpl, int block) {
     return 1;
 }
 
-template <int JMAX>
+template <int JMAX, int WALKER>
 static int tree_occupancy() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_tree<JMAX>, kBatchTreeBlock,
-                                                     0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_tree<JMAX, WALKER>,
+                                                     kBatchTreeBlock, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-int batch_tree_blocks_per_cu(int jmax) {
-    switch (jmax) {
-        case 1: return tree_occupancy<1>();
-        case 2: return tree_occupancy<2>();
-        case 3: return tree_occupancy<3>();
-        case 4: return tree_occupancy<4>();
-        case 5: return tree_occupancy<5>();
-        case 6: return tree_occupancy<6>();
-        case 7: return tree_occupancy<7>();
-        case 8: return tree_occupancy<8>();
-        case 9: return tree_occupancy<9>();
-        case 10: return tree_occupancy<10>();
-        case 11: return tree_occupancy<11>();
-        case 12: return tree_occupancy<12>();
-        default: return 1;
-    }
+// Instantiates X(depth, walker) for every compiled traversal.
+#define SWV_TREE_SHAPES(X)                                                            \
+    X(1, 0) X(2, 0) X(3, 0) X(4, 0) X(5, 0) X(6, 0) X(7, 0) X(8, 0) X(9, 0) X(10, 0)  \
+    X(11, 0) X(12, 0)                                                                 \
+    X(1, 1) X(2, 1) X(3, 1) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) X(9, 1) X(10, 1)  \
+    X(11, 1) X(12, 1) X(13, 1) X(14, 1) X(15, 1) X(16, 1)
+
+int batch_tree_blocks_per_cu(int walker, int depth) {
+#define SWV_OCC_T(D, W) if (walker == W && depth == D) return tree_occupancy<D, W>();
+    SWV_TREE_SHAPES(SWV_OCC_T)
+#undef SWV_OCC_T
+    return 1;
 }
 
 hipError_t launch_batch_direct(hipStream_t s, int vpl, int block, int grid,
@@ -186,27 +182,22 @@ hipError_t launch_batch_direct(hipStream_t s, int vpl, int block, int grid,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch_tree(hipStream_t s, int jmax, int grid, const TreeArgs& scales,
-                             const BatchInst* inst, const WorkItem* items, unsigned n_items,
-                             unsigned* counter, int* status) {
+hipError_t launch_batch_tree(hipStream_t s, int walker, int depth, int grid,
+                             const TreeArgs& scales, const BatchInst* inst,
+                             const WorkItem* items, unsigned n_items, unsigned* counter,
+                             int* status) {
     if (n_items == 0) return hipSuccess;
     const dim3 g(grid), b(kBatchTreeBlock);
-    switch (jmax) {
-        case 1: k_batch_tree<1><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
-        case 2: k_batch_tree<2><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
-        case 3: k_batch_tree<3><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
-        case 4: k_batch_tree<4><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
-        case 5: k_batch_tree<5><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
-        case 6: k_batch_tree<6><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
-        case 7: k_batch_tree<7><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
-        case 8: k_batch_tree<8><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
-        case 9: k_batch_tree<9><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
-        case 10: k_batch_tree<10><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
-        case 11: k_batch_tree<11><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
-        case 12: k_batch_tree<12><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); break;
-        default: return hipErrorInvalidValue;
+#define SWV_RUN_T(D, W)                                                                 \
+    if (walker == W && depth == D) {                                                    \
+        k_batch_tree<D, W><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); \
+        return hipGetLastError();                                                       \
     }
-    return hipGetLastError();
+    SWV_TREE_SHAPES(SWV_RUN_T)
+#undef SWV_RUN_T
+    return hipErrorInvalidValue;
 }
+
+#undef SWV_TREE_SHAPES
 
 }  // namespace swv

@@ -18,13 +18,20 @@
 // registers; one call site per level (inside a loop over the set bits of the
 // child mask) keeps the code linear in J.  Roots add A_1 lambda_1 eta_1.
 //
+// Deep trees are mostly runs of one-child nodes, so a second traversal (the
+// branch walker) keeps a register set only for open BRANCHING nodes: a run of
+// one-child nodes holds nothing while the subtree below it is walked and is
+// closed bottom-up afterwards.  Its depth parameter is the number of nested
+// branchings, which stays small (a few to a dozen) at any J, so it serves
+// J = 1 .. 29; both traversals perform the same operations in the same order.
+//
 // Imaginary parts are carried divided by 4 (cis2pi_q's convention; every step
 // is linear) and scaled back once at the end.
 #include "tree_walk.h"
 
 namespace swv {
 
-template <int JMAX, int BLOCK>
+template <int JMAX, int BLOCK, int WALKER>
 __global__ __launch_bounds__(BLOCK) void k_tree(TreeArgs ta, const double* __restrict__ u,
                                                 const double* __restrict__ v,
                                                 const double* __restrict__ w, int64_t n_vis,
@@ -34,29 +41,29 @@ __global__ __launch_bounds__(BLOCK) void k_tree(TreeArgs ta, const double* __res
     const int64_t j = jrow < n_vis ? jrow : n_vis - 1;
     const double U = u[j], V = v[j], W = w[j];
     double Vr, Vi;
-    tree_row<JMAX>(ta.rec, ta.n_roots, ta.J, ta, U, V, W, Vr, Vi);
+    tree_row<JMAX, WALKER>(ta.rec, ta.n_roots, ta.J, ta, U, V, W, Vr, Vi);
     if (jrow < n_vis) {
         if (!isfinite(U + V + W)) atomicOr(status, kStatusNonFinite);
         out[jrow] = make_double2(Vr, 4.0 * sgn * Vi);
     }
 }
 
-template <int JMAX>
+template <int JMAX, int WALKER>
 static hipError_t run_tree(hipStream_t s, int block, const TreeArgs& t, int64_t n_vis,
                            const double* u, const double* v, const double* w, int sign,
                            void* out, int* status) {
     const double sg = (double)sign;
     switch (block) {
         case 64:
-            k_tree<JMAX, 64><<<dim3((unsigned)((n_vis + 63) / 64)), dim3(64), 0, s>>>(
+            k_tree<JMAX, 64, WALKER><<<dim3((unsigned)((n_vis + 63) / 64)), dim3(64), 0, s>>>(
                 t, u, v, w, n_vis, sg, (double2*)out, status);
             break;
         case 128:
-            k_tree<JMAX, 128><<<dim3((unsigned)((n_vis + 127) / 128)), dim3(128), 0, s>>>(
+            k_tree<JMAX, 128, WALKER><<<dim3((unsigned)((n_vis + 127) / 128)), dim3(128), 0, s>>>(
                 t, u, v, w, n_vis, sg, (double2*)out, status);
             break;
         case 256:
-            k_tree<JMAX, 256><<<dim3((unsigned)((n_vis + 255) / 256)), dim3(256), 0, s>>>(
+            k_tree<JMAX, 256, WALKER><<<dim3((unsigned)((n_vis + 255) / 256)), dim3(256), 0, s>>>(
                 t, u, v, w, n_vis, sg, (double2*)out, status);
             break;
         default:
@@ -65,26 +72,32 @@ static hipError_t run_tree(hipStream_t s, int block, const TreeArgs& t, int64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_tree(hipStream_t s, int block, const TreeArgs& t, int64_t n_vis,
+#define SWV_TREE_CASE(N, W) \
+    case N: return run_tree<N, W>(s, block, t, n_vis, u, v, w, sign, out, status);
+
+hipError_t launch_tree(hipStream_t s, int walker, int block, const TreeArgs& t, int64_t n_vis,
                        const double* u, const double* v, const double* w, int sign, void* out,
                        int* status) {
     if (n_vis <= 0) return hipSuccess;
-    // the compiled traversal depth is the tree's J: register use grows with it
-    switch (t.J) {
-        case 1: return run_tree<1>(s, block, t, n_vis, u, v, w, sign, out, status);
-        case 2: return run_tree<2>(s, block, t, n_vis, u, v, w, sign, out, status);
-        case 3: return run_tree<3>(s, block, t, n_vis, u, v, w, sign, out, status);
-        case 4: return run_tree<4>(s, block, t, n_vis, u, v, w, sign, out, status);
-        case 5: return run_tree<5>(s, block, t, n_vis, u, v, w, sign, out, status);
-        case 6: return run_tree<6>(s, block, t, n_vis, u, v, w, sign, out, status);
-        case 7: return run_tree<7>(s, block, t, n_vis, u, v, w, sign, out, status);
-        case 8: return run_tree<8>(s, block, t, n_vis, u, v, w, sign, out, status);
-        case 9: return run_tree<9>(s, block, t, n_vis, u, v, w, sign, out, status);
-        case 10: return run_tree<10>(s, block, t, n_vis, u, v, w, sign, out, status);
-        case 11: return run_tree<11>(s, block, t, n_vis, u, v, w, sign, out, status);
-        case 12: return run_tree<12>(s, block, t, n_vis, u, v, w, sign, out, status);
+    if (walker == 0) {
+        // the compiled traversal depth is the tree's J: register use grows with it
+        switch (t.J) {
+            SWV_TREE_CASE(1, 0) SWV_TREE_CASE(2, 0) SWV_TREE_CASE(3, 0) SWV_TREE_CASE(4, 0)
+            SWV_TREE_CASE(5, 0) SWV_TREE_CASE(6, 0) SWV_TREE_CASE(7, 0) SWV_TREE_CASE(8, 0)
+            SWV_TREE_CASE(9, 0) SWV_TREE_CASE(10, 0) SWV_TREE_CASE(11, 0) SWV_TREE_CASE(12, 0)
+            default: return hipErrorInvalidValue;
+        }
+    }
+    // branch walker: compiled for the tree's number of nested segments
+    switch (t.seg_depth) {
+        SWV_TREE_CASE(1, 1) SWV_TREE_CASE(2, 1) SWV_TREE_CASE(3, 1) SWV_TREE_CASE(4, 1)
+        SWV_TREE_CASE(5, 1) SWV_TREE_CASE(6, 1) SWV_TREE_CASE(7, 1) SWV_TREE_CASE(8, 1)
+        SWV_TREE_CASE(9, 1) SWV_TREE_CASE(10, 1) SWV_TREE_CASE(11, 1) SWV_TREE_CASE(12, 1)
+        SWV_TREE_CASE(13, 1) SWV_TREE_CASE(14, 1) SWV_TREE_CASE(15, 1) SWV_TREE_CASE(16, 1)
         default: return hipErrorInvalidValue;
     }
 }
+
+#undef SWV_TREE_CASE
 
 }  // namespace swv

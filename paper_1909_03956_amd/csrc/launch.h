@@ -31,13 +31,19 @@ struct TreeArgs {
     const TRec* rec;
     int n_roots;
     int J;
+    int seg_depth;                    // 1 + most branching nodes on a root-to-leaf path
     double scale[SWV_MAX_LEVEL + 1];  // sqrt(A_j) / 4
 };
 
-// Largest J with a compiled register-resident traversal.
+// Largest J of the level walker (one register set per level).
 constexpr int kTreeMaxJ = 12;
+// Largest segment depth of the branch walker (one register set per branching
+// node); it serves every J.
+constexpr int kTreeMaxSeg = 16;
 
-hipError_t launch_tree(hipStream_t s, int block, const TreeArgs& t, int64_t n_vis,
+// walker 0: level walker (t.J <= kTreeMaxJ); 1: branch walker
+// (t.seg_depth <= kTreeMaxSeg).
+hipError_t launch_tree(hipStream_t s, int walker, int block, const TreeArgs& t, int64_t n_vis,
                        const double* u, const double* v, const double* w, int sign, void* out,
                        int* status);
 
@@ -89,11 +95,13 @@ hipError_t launch_batch_ingest(hipStream_t s, const BatchInst* inst, int n_inst,
 hipError_t launch_reset_counters(hipStream_t s, unsigned* counters, int n);
 // Blocks per CU that stay resident for the persistent kernels.
 int batch_direct_blocks_per_cu(int vpl, int block);
-int batch_tree_blocks_per_cu(int jmax);
+// walker / depth as for launch_tree: depth is the largest J (walker 0) or
+// segment depth (walker 1) over the plan's trees.
+int batch_tree_blocks_per_cu(int walker, int depth);
 hipError_t launch_batch_direct(hipStream_t s, int vpl, int block, int grid,
                                const BatchInst* inst, const Comp* pack, const WorkItem* items,
                                unsigned n_items, unsigned* counter, int* status);
-hipError_t launch_batch_tree(hipStream_t s, int jmax, int grid, const TreeArgs& scales,
+hipError_t launch_batch_tree(hipStream_t s, int walker, int depth, int grid, const TreeArgs& scales,
                              const BatchInst* inst, const WorkItem* items, unsigned n_items,
                              unsigned* counter, int* status);
 constexpr int kBatchTreeBlock = 64;

@@ -13,6 +13,9 @@
 // traversal the tree is also written as one depth-first (pre-order) record
 // stream: a root record per level-1 node, then node records, each followed by
 // its children's subtrees in child order, with leaf records at level J.
+// Runs of one-child nodes are marked in the stream, and the largest number of
+// branching nodes on a path is recorded, for a traversal that keeps state
+// only for branching ancestors.
 #include "tree.h"
 
 #include <algorithm>
@@ -29,12 +32,12 @@ static const double kSign[3][4] = {{+1, -1, +1, -1}, {+1, +1, -1, -1}, {+1, -1, 
 
 static void emit(const swv_tree_s& t, int j, int64_t idx, std::vector<TRec>& out) {
     if (j == t.J) {
-        out.push_back(TRec{t.leaf_l[idx], t.leaf_m[idx], t.leaf_nm1[idx], 0ull});
+        out.push_back(TRec{t.leaf_l[idx], t.leaf_m[idx], t.leaf_nm1[idx], make_meta(0, j, 0)});
         return;
     }
     const TreeLevel& L = t.levels[j - 1];
     out.push_back(TRec{L.gamma[3 * idx], L.gamma[3 * idx + 1], L.gamma[3 * idx + 2],
-                       (unsigned long long)L.mask[idx]});
+                       make_meta((unsigned)L.mask[idx], j, L.chain[idx])});
     int64_t child = L.first_child[idx];
     for (int c = 0; c < 4; ++c)
         if (L.mask[idx] & (1 << c)) emit(t, j + 1, child++, out);
@@ -80,6 +83,28 @@ void build_coefficients(swv_tree_s* t) {
         }
     }
     for (int j = 1; j <= J; ++j) t->level_scale[j] = std::sqrt(pixel_area(j)) / 4.0;
+
+    // one-child runs and branching depth, bottom-up
+    std::vector<int> depth_below(nl, 0);   // branching nodes strictly below, per node
+    top.chain.assign(nl, 0);
+    for (int j = J - 1; j >= 1; --j) {
+        TreeLevel& L = t->levels[j - 1];
+        const TreeLevel& below = t->levels[j];
+        const int64_t n = (int64_t)L.pix.size();
+        L.chain.assign(n, 0);
+        std::vector<int> depth(n, 0);
+        for (int64_t k = 0; k < n; ++k) {
+            const int nch = __builtin_popcount((unsigned)L.mask[k]);
+            const int64_t c0 = L.first_child[k];
+            int d = 0;
+            for (int i = 0; i < nch; ++i) d = std::max(d, depth_below[c0 + i]);
+            depth[k] = d + (nch >= 2 ? 1 : 0);
+            if (nch == 1) L.chain[k] = 1 + (j + 1 < J ? below.chain[c0] : 0);
+        }
+        depth_below.swap(depth);
+    }
+    t->max_branching = 0;
+    for (int d : depth_below) t->max_branching = std::max(t->max_branching, d);
 
     // depth-first record stream
     t->records.clear();

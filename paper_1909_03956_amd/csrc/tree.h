@@ -16,6 +16,7 @@ struct TreeLevel {
     std::vector<int64_t> first_child; // index of the first child in the next level
     std::vector<double> lambda;       // lambda_{j,k}
     std::vector<double> gamma;        // gamma^m_{j,k} at [3 k + m] (level < J)
+    std::vector<int32_t> chain;       // one-child run starting here (see TRec)
 };
 
 }  // namespace swv
@@ -31,6 +32,8 @@ struct swv_tree_s {
     // depth-first record stream consumed by the device traversal
     std::vector<swv::TRec> records;
     int64_t n_roots = 0;
+    // most nodes with two or more children on one root-to-leaf path
+    int max_branching = 0;
     double level_scale[SWV_MAX_LEVEL + 1] = {};  // sqrt(A_j) / 4
     double build_seconds = 0;
     // device copies of `records`, one per HIP device id

@@ -10,61 +10,127 @@ namespace swv {
 
 using RecPtr = const __attribute__((address_space(4))) TRec*;
 
+// Running sums of an open node over its finished children:
+//   S = sum_c eta_{j+1,c},   D^m = sum_c s^m_c eta_{j+1,c}   (m = 0, 1, 2).
+struct NodeSums {
+    double Sr = 0.0, Si = 0.0, D0r = 0.0, D0i = 0.0, D1r = 0.0, D1i = 0.0, D2r = 0.0,
+           D2i = 0.0;
+};
+
+// Adds child c's plane-wave coefficient x to the sums.
+__device__ __forceinline__ void add_child(NodeSums& n, int c, double xr, double xi) {
+    // Eq. 10 signs of child c: gamma^0 (+-+-), gamma^1 (++--), gamma^2 (+--+)
+    const double s0 = (c & 1) ? -1.0 : 1.0;
+    const double s1 = (c & 2) ? -1.0 : 1.0;
+    const double s2 = s0 * s1;
+    n.Sr += xr;
+    n.Si += xi;
+    n.D0r = fma(s0, xr, n.D0r);
+    n.D0i = fma(s0, xi, n.D0i);
+    n.D1r = fma(s1, xr, n.D1r);
+    n.D1i = fma(s1, xi, n.D1i);
+    n.D2r = fma(s2, xr, n.D2r);
+    n.D2i = fma(s2, xi, n.D2i);
+}
+
+// Closes a node at level j (a = sqrt(A_j)/4, g = gamma^m_j): eta_j (Eq. 9 on
+// the plane wave) goes to the parent, sigma^m_j (Eq. 10 on the plane wave) is
+// formed and gamma^m_j sigma^m_j added to V (Eq. 17).
+__device__ __forceinline__ void close_node(const NodeSums& n, double a, double g0, double g1,
+                                           double g2, double& er, double& ei, double& Vr,
+                                           double& Vi) {
+    er = 0.25 * n.Sr;
+    ei = 0.25 * n.Si;
+    const double s0r = a * n.D0r, s0i = a * n.D0i;
+    const double s1r = a * n.D1r, s1i = a * n.D1i;
+    const double s2r = a * n.D2r, s2i = a * n.D2i;
+    Vr = fma(g0, s0r, Vr);
+    Vi = fma(g0, s0i, Vi);
+    Vr = fma(g1, s1r, Vr);
+    Vi = fma(g1, s1i, Vi);
+    Vr = fma(g2, s2r, Vr);
+    Vi = fma(g2, s2i, Vi);
+}
+
+// Leaf: eta_{J,k} = exp(2 pi i B . (s_k - P)) (imaginary part / 4).
+__device__ __forceinline__ void leaf_wave(RecPtr rec, int me, double u, double v, double w,
+                                          double& er, double& ei) {
+    double c, q;
+    cis2pi_q(reduced_phase(u, v, w, rec[me].a, rec[me].b, rec[me].c), c, q);
+    er = c;
+    ei = q;
+}
+
+// Level walker: one register set per level, the level a template parameter.
 template <int LVL, int JMAX>
 __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const TreeArgs& ta,
                                      const double u, const double v, const double w, double& er,
                                      double& ei, double& Vr, double& Vi) {
     const int me = pos++;
     if (LVL == JMAX || LVL == J) {
-        // leaf: eta_{J,k} = exp(2 pi i B . (s_k - P))
-        double c, q;
-        cis2pi_q(reduced_phase(u, v, w, rec[me].a, rec[me].b, rec[me].c), c, q);
-        er = c;
-        ei = q;
+        leaf_wave(rec, me, u, v, w, er, ei);
         return;
     }
     if constexpr (LVL < JMAX) {
-        unsigned mask = (unsigned)rec[me].meta;
-        double Sr = 0.0, Si = 0.0, D0r = 0.0, D0i = 0.0, D1r = 0.0, D1i = 0.0, D2r = 0.0,
-               D2i = 0.0;
+        unsigned mask = meta_mask(rec[me].meta);
+        NodeSums n;
         while (mask) {
             const int c = __builtin_ctz(mask);
             mask &= mask - 1;
             double xr, xi;
             walk<LVL + 1, JMAX>(rec, pos, J, ta, u, v, w, xr, xi, Vr, Vi);
-            // Eq. 10 signs of child c: gamma^0 (+-+-), gamma^1 (++--), gamma^2 (+--+)
-            const double s0 = (c & 1) ? -1.0 : 1.0;
-            const double s1 = (c & 2) ? -1.0 : 1.0;
-            const double s2 = s0 * s1;
-            Sr += xr;
-            Si += xi;
-            D0r = fma(s0, xr, D0r);
-            D0i = fma(s0, xi, D0i);
-            D1r = fma(s1, xr, D1r);
-            D1i = fma(s1, xi, D1i);
-            D2r = fma(s2, xr, D2r);
-            D2i = fma(s2, xi, D2i);
+            add_child(n, c, xr, xi);
         }
-        // eta_j (Eq. 9 on the plane wave) goes up to the parent
-        er = 0.25 * Sr;
-        ei = 0.25 * Si;
-        // sigma^m_j (Eq. 10 on the plane wave), then gamma^m_j sigma^m_j (Eq. 17)
-        const double a = ta.scale[LVL];
-        const double g0 = rec[me].a, g1 = rec[me].b, g2 = rec[me].c;
-        const double s0r = a * D0r, s0i = a * D0i;
-        const double s1r = a * D1r, s1i = a * D1i;
-        const double s2r = a * D2r, s2i = a * D2i;
-        Vr = fma(g0, s0r, Vr);
-        Vi = fma(g0, s0i, Vi);
-        Vr = fma(g1, s1r, Vr);
-        Vi = fma(g1, s1i, Vi);
-        Vr = fma(g2, s2r, Vr);
-        Vi = fma(g2, s2i, Vi);
+        close_node(n, ta.scale[LVL], rec[me].a, rec[me].b, rec[me].c, er, ei, Vr, Vi);
+    }
+}
+
+// Branch walker: one register set per open BRANCHING node, so any J.  A
+// segment is a run of one-child nodes (possibly empty) and the leaf or
+// branching node below it; the run keeps no state while the part below is
+// walked, and is closed bottom-up afterwards with the same arithmetic a
+// one-child node gets in the level walker.  D counts segments from the root;
+// the host launches DMAX >= 1 + the tree's largest branching count on a path.
+template <int D, int DMAX>
+__device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, const TreeArgs& ta,
+                                         const double u, const double v, const double w,
+                                         double& er, double& ei, double& Vr, double& Vi) {
+    const int first = pos;
+    const int run = meta_chain(rec[first].meta);
+    const int term = first + run;
+    pos = term + 1;
+    const unsigned long long mt = rec[term].meta;
+    er = 0.0;
+    ei = 0.0;
+    if (meta_level(mt) == J) {
+        leaf_wave(rec, term, u, v, w, er, ei);
+    } else {
+        if constexpr (D < DMAX) {
+            unsigned mask = meta_mask(mt);
+            NodeSums n;
+            while (mask) {
+                const int c = __builtin_ctz(mask);
+                mask &= mask - 1;
+                double xr, xi;
+                seg_walk<D + 1, DMAX>(rec, pos, J, ta, u, v, w, xr, xi, Vr, Vi);
+                add_child(n, c, xr, xi);
+            }
+            close_node(n, ta.scale[meta_level(mt)], rec[term].a, rec[term].b, rec[term].c, er,
+                       ei, Vr, Vi);
+        }
+    }
+    for (int i = run - 1; i >= 0; --i) {
+        const int me = first + i;
+        const unsigned long long mm = rec[me].meta;
+        NodeSums n;
+        add_child(n, __builtin_ctz(meta_mask(mm)), er, ei);
+        close_node(n, ta.scale[meta_level(mm)], rec[me].a, rec[me].b, rec[me].c, er, ei, Vr, Vi);
     }
 }
 
 // V (real, imaginary / 4) of one row: the root loop of the traversal.
-template <int JMAX>
+// WALKER 0: level walker up to level JMAX; 1: branch walker up to JMAX segments.
+template <int JMAX, int WALKER = 0>
 __device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J,
                                          const TreeArgs& ta, double U, double V, double W,
                                          double& Vr, double& Vi) {
@@ -75,7 +141,10 @@ __device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J,
     for (int r = 0; r < n_roots; ++r) {
         const int root = pos++;
         double er, ei;
-        walk<1, JMAX>(rec, pos, J, ta, U, V, W, er, ei, Vr, Vi);
+        if constexpr (WALKER == 0)
+            walk<1, JMAX>(rec, pos, J, ta, U, V, W, er, ei, Vr, Vi);
+        else
+            seg_walk<1, JMAX>(rec, pos, J, ta, U, V, W, er, ei, Vr, Vi);
         const double A1lam = rec[root].a;  // A_1 lambda_1
         Vr = fma(A1lam, er, Vr);
         Vi = fma(A1lam, ei, Vi);

@@ -81,6 +81,26 @@ def test_batch_equals_single_instance_bitwise(env):
     assert not bad, bad
 
 
+def test_batch_with_deep_trees_bitwise(env):
+    # trees beyond J = 12 go through the branch walker, in the batch as alone
+    torch, swv = env
+    rng = np.random.default_rng(11)
+    insts, refs = [], []
+    for J, n, k in ((14, 5000, 90), (20, 3001, 140), (29, 777, 25), (9, 4096, 300)):
+        u, v, w = (dev(rng.uniform(-3e5, 3e5, n), torch) for _ in range(3))
+        l, m = rng.uniform(-0.02, 0.02, k), rng.uniform(-0.02, 0.02, k)
+        t = swv.Tree(J, 0.7, -0.2, l, m, rng.lognormal(-3, 1, k))
+        out = torch.full((n,), 7.0, dtype=torch.complex128, device="cuda")
+        insts.append(dict(route="tree", tree=t, u=u, v=v, w=w, out=out))
+        refs.append(lambda u=u, v=v, w=w, t=t: t.predict(u, v, w))
+    plan = swv.BatchPlan(insts)
+    plan.run()
+    swv.synchronize()
+    bad = _mismatches(insts, refs, torch)
+    plan.close()
+    assert not bad, bad
+
+
 def test_graph_replay_equals_eager(env):
     torch, swv = env
     insts, refs = _instances(torch, swv, np.random.default_rng(2))

@@ -113,10 +113,110 @@ def test_empty_tree_gives_zero(env):
     assert np.all(got == 0)
 
 
-def test_deep_tree_not_supported(env):
+def _nested_components(j0, J=29, ra=0.3, dec=0.4, l0=0.01, m0=0.003):
+    """One component plus, for every level j0..J, one at the centre of a sibling
+    of its level-j pixel: every ancestor from level j0-1 down branches."""
+    from paper_1909_03956_amd.api import ang2pix, pixel_centres
+    k = int(ang2pix(J, ra, dec, np.array([l0]), np.array([m0]))[0])
+    ls, ms = [l0], [m0]
+    for j in range(j0, J + 1):
+        cl, cm, _ = pixel_centres(j, ra, dec, np.array([(k >> 2 * (J - j)) ^ 1], np.int64))
+        ls.append(cl[0])
+        ms.append(cm[0])
+    return np.array(ls), np.array(ms)
+
+
+def _with_walker(swv, walker, fn):
+    """Runs fn() with the tree traversal forced to `walker` (1 level, 2 branch)."""
+    from paper_1909_03956_amd._lib import FAM_TREE
+    ctx = swv.context()
+    saved = [ctx.tune_get(FAM_TREE, c) for c in (0, 1)]
+    try:
+        for c in (0, 1):
+            ctx.tune_set(FAM_TREE, c, walker, saved[c][1])
+        return fn()
+    finally:
+        for c in (0, 1):
+            ctx.tune_set(FAM_TREE, c, *saved[c])
+
+
+@pytest.mark.parametrize("name,J", [("cfg1", 6), ("cfg2", 8), ("cfg2", 9), ("cfg2", 10)])
+def test_walkers_bitwise_equal(env, name, J):
+    # both traversals perform the same operations in the same order
+    torch, swv = env
+    W = configs.WORKLOADS[name]
+    u, v, w = (dev(a, torch) for a in W.track.uvw())
+    l, m, f = W.components()
+    t = swv.Tree(J, W.ra_p, W.dec_p, l, m, f)
+    a = _with_walker(swv, 1, lambda: t.predict(u, v, w))
+    b = _with_walker(swv, 2, lambda: t.predict(u, v, w))
+    swv.synchronize()
+    st = t.stats()
+    note(f"{name} J={J}: max_branching={st['max_branching']} rows={u.numel()}")
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("J", list(range(1, 13)))
+def test_walkers_bitwise_equal_small_trees(env, J):
+    torch, swv = env
+    rng = np.random.default_rng(200 + J)
+    n = 61
+    half = 0.5 if J < 5 else 0.05
+    l, m = rng.uniform(-half, half, n), rng.uniform(-half, half, n)
+    f = rng.lognormal(-3, 1, n)
+    u, v, w = (dev(rng.uniform(-2e4, 2e4, 1000), torch) for _ in range(3))
+    t = swv.Tree(J, 1.0, 0.3, l, m, f)
+    a = _with_walker(swv, 1, lambda: t.predict(u, v, w))
+    b = _with_walker(swv, 2, lambda: t.predict(u, v, w))
+    swv.synchronize()
+    assert torch.equal(a, b)
+
+
+def _deep_case(env, J, l, m, f, nv, seed, scale):
+    torch, swv = env
+    ra, dec = 0.3, 0.4
+    rng = np.random.default_rng(seed)
+    u, v, w = (rng.uniform(-scale, scale, nv) for _ in range(3))
+    t = swv.Tree(J, ra, dec, l, m, f)
+    got = host(t.predict(dev(u, torch), dev(v, torch), dev(w, torch)))
+    swv.synchronize()
+    rt = ot.build_tree(J, ra, dec, l, m, f)
+    assert t.stats()["n_leaves"] == rt.n_leaves
+    ref = ot.predict_tree(rt, u, v, w)
+    snapped = ot.predict_snapped(rt, u, v, w)
+    bound = fp64_row_bound(u, v, w, rt.leaf_l, rt.leaf_m, rt.leaf_nm1, rt.leaf_flux)
+    slack = (J + 2) * 4e-16 * np.abs(f).sum()
+    note(f"deep J={J}: leaves={rt.n_leaves} internal={rt.n_internal} "
+         f"max_branching={t.stats()['max_branching']} "
+         f"max|d|/bound={np.max(np.abs(got - ref) / (bound + slack)):.3f}")
+    assert np.all(np.abs(got - ref) <= bound + slack)
+    assert np.all(np.abs(got - snapped) <= bound + slack)
+
+
+@pytest.mark.parametrize("J,n", [(13, 140), (16, 40), (20, 140), (25, 10), (25, 140), (29, 140)])
+def test_deep_trees_vs_oracle(env, J, n):
+    # the run-time sweep's regime: tens to ~140 leaves, J = 12 .. 29
+    rng = np.random.default_rng(J * 1000 + n)
+    l, m = rng.uniform(-0.02, 0.02, n), rng.uniform(-0.02, 0.02, n)
+    f = rng.lognormal(-3, 1, n)
+    _deep_case(env, J, l, m, f, 500, J, 4.6e5)
+
+
+def test_deepest_supported_branching(env):
+    # 15 nested branchings: the largest the branch walker is compiled for
+    l, m = _nested_components(15)
+    f = np.random.default_rng(5).lognormal(-3, 1, l.size)
+    torch, swv = env
+    assert swv.Tree(29, 0.3, 0.4, l, m, f).stats()["max_branching"] == 15
+    _deep_case(env, 29, l, m, f, 300, 7, 4.6e5)
+
+
+def test_too_many_branchings_not_supported(env):
     torch, swv = env
     from paper_1909_03956_amd._lib import SWV_ENOTSUP, SwvError
-    t = swv.Tree(20, 0.0, 0.5, [0.01], [0.0], [1.0])
+    l, m = _nested_components(14)
+    t = swv.Tree(29, 0.3, 0.4, l, m, np.ones(l.size))
+    assert t.stats()["max_branching"] == 16
     x = dev(np.ones(4), torch)
     with pytest.raises(SwvError) as e:
         t.predict(x, x, x)

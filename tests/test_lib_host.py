@@ -86,6 +86,30 @@ def test_tree_builder_matches_oracle(swv, name, J):
     assert st["n_records"] == st["n_leaves"] + st["n_internal"] + st["nodes_per_level"][0]
 
 
+def _branching_from_levels(tree):
+    """Most nodes with >= 2 children on one root-to-leaf path, counted on the
+    oracle's level arrays."""
+    below = np.zeros(tree.levels[-1].pix.size, int)
+    for j in range(tree.J - 1, 0, -1):
+        child = tree.levels[j - 1].child
+        cur = np.zeros(child.shape[0], int)
+        for k in range(child.shape[0]):
+            ch = child[k][child[k] >= 0]
+            cur[k] = below[ch].max() + (ch.size >= 2)
+        below = cur
+    return int(below.max()) if below.size else 0
+
+
+@pytest.mark.parametrize("J", [1, 6, 10, 17, 29])
+def test_max_branching_matches_oracle_levels(swv, J):
+    from paper_1909_03956_amd.api import Tree
+    W = configs.CFG2
+    l, m, f = W.components()
+    t = Tree(J, W.ra_p, W.dec_p, l[:300], m[:300], f[:300])
+    ref = ot.build_tree(J, W.ra_p, W.dec_p, l[:300], m[:300], f[:300])
+    assert t.stats()["max_branching"] == _branching_from_levels(ref)
+
+
 def test_ang2pix_and_centres_match_oracle(swv):
     from paper_1909_03956_amd.api import ang2pix, pixel_centres
     rng = np.random.default_rng(3)
