@@ -44,7 +44,7 @@ CPU_SHARE = 16                 # host cores of one GPU's share of the box
 FLOPS = {
     "direct_fp64": 5 + 2 + 34 + 4,            # MAC: 2 FMA                      -> 45
     "adjoint": 5 + 2 + 34 + 8,                # complex MAC: 4 FMA               -> 49
-    "grad": 5 + 2 + 34 + 6 + 2 + 12,          # z = conj(y) e, Z0 += z, 3 x 2 FMA -> 61
+    "grad": 5 + 2 + 34 + 6 + 1 + 6,           # z = conj(y) e; Re z; 3 FMA on Im z -> 54
     "tree_leaf": 5 + 2 + 34 + 14,             # + running sums S, D^0..2 (2 add, 6 FMA)
     "tree_node": 20 + 14,                     # eta, sigma, gamma sigma; + parent sums
     "tree_root": 20 + 4,                      # level-1 node: + A_1 lambda_1 eta_1
@@ -67,6 +67,8 @@ def parse():
                    help="short run for a profiler: no CPU baseline")
     p.add_argument("--no-tune", action="store_true",
                    help="keep the default tile shapes instead of autotuning first")
+    p.add_argument("--tune-out", default=None,
+                   help="write the autotuner's table and timings (JSON) to this path")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run one device copy of 1 GiB (HBM counter calibration)")
     return p.parse_args()
@@ -225,7 +227,7 @@ def main():
     families = ("direct_fp64", "direct_f32c", "tree", "adjoint", "grad")
     if not args.no_tune:
         t_tune = time.perf_counter()
-        ctx.autotune(quick=True)                  # untimed: picks the tile shapes
+        ctx.autotune(cache_path=args.tune_out, quick=True)   # untimed: picks the tile shapes
         log(f"autotuned in {time.perf_counter() - t_tune:.2f} s")
     tuning = {f: ctx.tune_get(i, 1) for i, f in enumerate(families)}
 

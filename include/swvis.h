@@ -174,7 +174,7 @@ int swv_tree_set_flux(swv_tree tree, const double* leaf_flux);
  * complex128 (SWV_FP64 only).  The tree is copied to the device on first use
  * with this context's device.
  * Two traversals compute the same operations in the same order (bitwise equal
- * results): one keeps a register set per level (J <= 12), the other one per
+ * results): one keeps a register set per level (J <= 11), the other one per
  * open node with two or more children (any J, up to 15 such nodes on one
  * root-to-leaf path, see swv_tree_stats_t.max_branching).  The tuning table
  * picks between them where both fit; SWV_ENOTSUP if neither does. */
@@ -232,7 +232,10 @@ int swv_adjoint(swv_ctx ctx, int64_t n_vis, const double* u, const double* v, co
  *     d_l[k]    = alpha Re sum_j conj(y_j) flux_k s 2 pi i (u_j - w_j l_k / n_k) e_jk
  *     d_m[k]    = alpha Re sum_j conj(y_j) flux_k s 2 pi i (v_j - w_j m_k / n_k) e_jk
  * y = residuals and alpha = -2/sigma^2 give d(chi^2); y = dL/dV* and alpha = 1
- * give the backward of a real loss.  All arrays DEVICE; FP64.  Deterministic. */
+ * give the backward of a real loss.  All arrays DEVICE; FP64.  Deterministic.
+ * Per component only four real sums over the rows are formed:
+ * Re sum conj(y) e and Im sum {u, v, w} conj(y) e.  Uses a workspace of
+ * 32 * n_comp * ceil(n_vis / chunk) bytes plus the packed components. */
 int swv_grad_direct(swv_ctx ctx, int64_t n_vis, const double* u, const double* v,
                     const double* w, const void* y, int64_t n_comp, const double* l,
                     const double* m, const double* flux, int sign, double alpha,
@@ -310,8 +313,9 @@ int swv_tune_load(swv_ctx ctx, const char* cache_path);
  * 0 direct FP64, 1 direct F32C, 2 tree, 3 adjoint, 4 gradients.  Size class
  * 0 is fewer than 2^20 visibility rows, 1 the rest.  per_lane is rows per lane
  * (direct), pixels per lane (adjoint) or components per lane (gradients), in
- * {1, 2, 4}; for the tree it selects the traversal (1: register set per level,
- * 2: per branching node; see swv_predict_tree).  block is threads per block
+ * {1, 2, 4}; for the tree it selects the traversal (1: register set per level
+ * where J <= 11, else per branching node; 2: always per branching node; see
+ * swv_predict_tree).  block is threads per block
  * in {64, 128, 256} (128 for the gradients).  Results do not depend on the shape except for
  * the summation order of the adjoint and gradients. */
 int swv_tune_get(swv_ctx ctx, int family, int size_class, int* per_lane, int* block);

@@ -108,10 +108,11 @@ class Context:
             self._h = C.c_void_p()
 
     def __del__(self):
-        if _EXITING[0]:
-            return
+        # skipped at interpreter shutdown (module globals may be gone; the
+        # process exit frees everything); never raises
         try:
-            self.close()
+            if not _EXITING[0]:
+                self.close()
         except Exception:
             pass
 
@@ -229,10 +230,11 @@ class Tree:
             self._h = C.c_void_p()
 
     def __del__(self):
-        if _EXITING[0]:
-            return
+        # skipped at interpreter shutdown (module globals may be gone; the
+        # process exit frees everything); never raises
         try:
-            self.close()
+            if not _EXITING[0]:
+                self.close()
         except Exception:
             pass
 
@@ -340,10 +342,11 @@ class Graph:
             self._h = C.c_void_p()
 
     def __del__(self):
-        if _EXITING[0]:
-            return
+        # skipped at interpreter shutdown (module globals may be gone; the
+        # process exit frees everything); never raises
         try:
-            self.close()
+            if not _EXITING[0]:
+                self.close()
         except Exception:
             pass
 
@@ -413,10 +416,11 @@ class BatchPlan:
             self._h = C.c_void_p()
 
     def __del__(self):
-        if _EXITING[0]:
-            return
+        # skipped at interpreter shutdown (module globals may be gone; the
+        # process exit frees everything); never raises
         try:
-            self.close()
+            if not _EXITING[0]:
+                self.close()
         except Exception:
             pass
 

@@ -538,7 +538,7 @@ int swv_adjoint(swv_ctx ctx, int64_t n_vis, const double* u, const double* v, co
     const int sc = size_class(n_vis);
     const int ppl = ctx->per_lane[kFamAdjoint][sc], block = ctx->block[kFamAdjoint][sc];
     const int64_t tiles = (n_pix + (int64_t)ppl * block - 1) / ((int64_t)ppl * block);
-    const int64_t chunk = choose_chunk(n_vis, tiles, ctx->n_cu, kAdjointBlocksPerCU);
+    const int64_t chunk = choose_chunk(n_vis, tiles, ctx->n_cu, adjoint_blocks_per_cu(prec, ppl, block));
     const int64_t n_chunks = n_vis > 0 ? (n_vis + chunk - 1) / chunk : 0;
     rc = ensure(ctx, ctx->partial, 16 * (size_t)n_pix * (size_t)(n_chunks > 0 ? n_chunks : 1));
     if (rc) return rc;
@@ -569,9 +569,9 @@ int swv_grad_direct(swv_ctx ctx, int64_t n_vis, const double* u, const double* v
     HIPCALL(launch_ingest(ctx->stream, n_comp, l, m, flux, comp, ctx->d_status));
     const int cpl = ctx->per_lane[kFamGrad][size_class(n_vis)];
     const int64_t tiles = (n_comp + 128 * cpl - 1) / (128 * cpl);
-    const int64_t chunk = choose_chunk(n_vis, tiles, ctx->n_cu, kGradBlocksPerCU);
+    const int64_t chunk = choose_chunk(n_vis, tiles, ctx->n_cu, grad_blocks_per_cu(cpl));
     const int64_t n_chunks = n_vis > 0 ? (n_vis + chunk - 1) / chunk : 0;
-    rc = ensure(ctx, ctx->partial, 64 * (size_t)n_comp * (size_t)(n_chunks > 0 ? n_chunks : 1));
+    rc = ensure(ctx, ctx->partial, 32 * (size_t)n_comp * (size_t)(n_chunks > 0 ? n_chunks : 1));
     if (rc) return rc;
     HIPCALL(launch_grad(ctx->stream, cpl, chunk, n_vis, u, v, w, y, comp, n_comp, sign, alpha,
                         (double*)ctx->partial.p, d_flux, d_l, d_m));

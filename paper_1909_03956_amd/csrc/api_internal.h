@@ -52,10 +52,9 @@ int ensure(swv_ctx ctx, DevBuf& b, size_t bytes);
 void tune_defaults(swv_ctx ctx);
 int size_class(int64_t rows);
 // Rows per chunk of the adjoint (image) and gradient reductions: enough
-// (chunk, tile) blocks to give every compute unit `blocks_per_cu` of them.
+// (chunk, tile) blocks for one full round of resident blocks, `blocks_per_cu`
+// on each compute unit.
 int64_t choose_chunk(int64_t n_rows, int64_t tiles, int n_cu, int blocks_per_cu);
-constexpr int kAdjointBlocksPerCU = 8;
-constexpr int kGradBlocksPerCU = 16;
 int check_sign_prec(int sign, int prec, bool allow_f32);
 bool tune_valid(int family, int per_lane, int block);
 int upload_tree(swv_ctx ctx, swv_tree t, const TRec** out);

@@ -186,7 +186,7 @@ int swv_batch_plan(swv_ctx ctx, int n, const swv_instance* inst, swv_plan* out) 
             }
         }
         for (int j = 0; j <= SWV_MAX_LEVEL; ++j)
-            p->scales.scale[j] = j >= 1 ? std::sqrt(pixel_area(j)) / 4.0 : 0.0;
+            p->scales.scale[j] = j >= 1 ? level_scale(j) : 0.0;
         p->scales.J = p->jmax;
         // one traversal for all trees of the plan: the tuned one where it fits
         const bool level_ok = p->jmax <= kTreeMaxJ, branch_ok = p->smax <= kTreeMaxSeg;
@@ -496,7 +496,7 @@ int swv_autotune(swv_ctx ctx, const char* cache_path, int flags) {
                                             ctx->d_status);
                         } else if (fam == kFamAdjoint) {
                             const int64_t tiles = (n_pix + (int64_t)pl * bl - 1) / ((int64_t)pl * bl);
-                            const int64_t chunk = choose_chunk(rows, tiles, ctx->n_cu, kAdjointBlocksPerCU);
+                            const int64_t chunk = choose_chunk(rows, tiles, ctx->n_cu, adjoint_blocks_per_cu(SWV_FP64, pl, bl));
                             const int64_t nch = (rows + chunk - 1) / chunk;
                             rc = ensure(ctx, ctx->partial, 16 * (size_t)n_pix * nch);
                             if (rc) { result = rc; break; }
@@ -505,9 +505,9 @@ int swv_autotune(swv_ctx ctx, const char* cache_path, int flags) {
                                                l, m, nm, -1, part, out);
                         } else {
                             const int64_t tiles = (n_comp + 128 * pl - 1) / (128 * pl);
-                            const int64_t chunk = choose_chunk(rows, tiles, ctx->n_cu, kGradBlocksPerCU);
+                            const int64_t chunk = choose_chunk(rows, tiles, ctx->n_cu, grad_blocks_per_cu(pl));
                             const int64_t nch = (rows + chunk - 1) / chunk;
-                            rc = ensure(ctx, ctx->partial, 64 * (size_t)n_comp * nch);
+                            rc = ensure(ctx, ctx->partial, 32 * (size_t)n_comp * nch);
                             if (rc) { result = rc; break; }
                             part = (double*)ctx->partial.p;
                             e = launch_grad(s, pl, chunk, rows, u, v, w, y, comp, n_comp, -1, 1.0,

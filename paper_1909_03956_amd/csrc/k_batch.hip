@@ -154,7 +154,7 @@ static int tree_occupancy() {
 // Instantiates X(depth, walker) for every compiled traversal.
 #define SWV_TREE_SHAPES(X)                                                            \
     X(1, 0) X(2, 0) X(3, 0) X(4, 0) X(5, 0) X(6, 0) X(7, 0) X(8, 0) X(9, 0) X(10, 0)  \
-    X(11, 0) X(12, 0)                                                                 \
+    X(11, 0)                                                                          \
     X(1, 1) X(2, 1) X(3, 1) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) X(9, 1) X(10, 1)  \
     X(11, 1) X(12, 1) X(13, 1) X(14, 1) X(15, 1) X(16, 1)
 

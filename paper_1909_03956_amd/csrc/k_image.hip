@@ -158,6 +158,35 @@ static hipError_t run_adjoint_b(hipStream_t s, int block, int64_t grid, int64_t 
     return hipGetLastError();
 }
 
+// Blocks of one kernel shape that fit on a compute unit at once (registers,
+// LDS, waves), from the runtime's occupancy calculator; cached per shape.
+template <class K>
+static int resident_blocks(K kernel, int block) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return nb > 0 ? nb : 1;
+}
+
+template <int PPL, int BLOCK, int PREC>
+static int adjoint_occ() {
+    static const int v = resident_blocks(k_adjoint<PPL, BLOCK, PREC>, BLOCK);
+    return v;
+}
+
+int adjoint_blocks_per_cu(int prec, int ppl, int block) {
+#define SWV_OCC_A(P, B)                                                                   \
+    if (ppl == P && block == B)                                                           \
+        return prec == SWV_FP64 ? adjoint_occ<P, B, SWV_FP64>() : adjoint_occ<P, B, SWV_F32C>();
+    SWV_OCC_A(1, 64) SWV_OCC_A(1, 128) SWV_OCC_A(1, 256)
+    SWV_OCC_A(2, 64) SWV_OCC_A(2, 128) SWV_OCC_A(2, 256)
+    SWV_OCC_A(4, 64) SWV_OCC_A(4, 128) SWV_OCC_A(4, 256)
+#undef SWV_OCC_A
+    return 1;
+}
+
 hipError_t launch_adjoint(hipStream_t s, int prec, int ppl, int block, int64_t chunk,
                           int64_t n_vis, const double* u, const double* v, const double* w,
                           const void* y, int64_t n_pix, const double* l, const double* m,
@@ -191,8 +220,10 @@ hipError_t launch_adjoint(hipStream_t s, int prec, int ppl, int block, int64_t c
 }
 
 // -------------------------------------------------------------- gradients --
-// Per component k (CPL per lane) and chunk of rows:
-//   Z0 = sum conj(y) e,  Zu = sum u conj(y) e,  Zv = ..., Zw = ...
+// The gradients need four real sums per component k (CPL per lane) and chunk
+// of rows, with z = conj(y) e:
+//   Z0 = Re sum z                    (flux:      dchi2/dI ~ Re A^H r)
+//   Zu, Zv, Zw = Im sum {u, v, w} z  (positions: d phi/dl = u - w l / n, ...)
 // conj(y) e = (yr - i yi)(c + i s S) = (yr c + yi s S) + i (yr s S - yi c),
 // S = 4 q; the products 4 s y are formed once per row for all CPL components.
 constexpr int kGradBlock = 128;
@@ -208,7 +239,7 @@ __global__ __launch_bounds__(kGradBlock) void k_grad_partial(
     if (chunk_id >= n_chunks) return;   // padding of the last XCD group
     const int64_t k0 = tile * (kGradBlock * CPL) + threadIdx.x;
     double L[CPL], M[CPL], N[CPL];
-    double z0r[CPL], z0i[CPL], zur[CPL], zui[CPL], zvr[CPL], zvi[CPL], zwr[CPL], zwi[CPL];
+    double z0[CPL], zu[CPL], zv[CPL], zw[CPL];
 #pragma unroll
     for (int i = 0; i < CPL; ++i) {
         int64_t k = k0 + (int64_t)i * kGradBlock;
@@ -216,7 +247,7 @@ __global__ __launch_bounds__(kGradBlock) void k_grad_partial(
         L[i] = comp[k].l;
         M[i] = comp[k].m;
         N[i] = comp[k].nm1;
-        z0r[i] = z0i[i] = zur[i] = zui[i] = zvr[i] = zvi[i] = zwr[i] = zwi[i] = 0.0;
+        z0[i] = zu[i] = zv[i] = zw[i] = 0.0;
     }
     const int64_t j0 = chunk_id * chunk;
     const int64_t j1 = j0 + chunk < n_vis ? j0 + chunk : n_vis;
@@ -238,50 +269,49 @@ __global__ __launch_bounds__(kGradBlock) void k_grad_partial(
             cis2pi_q(reduced_phase(uj, vj, wj, L[i], M[i], N[i]), c, q);
             const double zr = fma(q, y4i, yr * c);
             const double zi = fma(q, y4r, -(yi * c));
-            z0r[i] += zr;
-            z0i[i] += zi;
-            zur[i] = fma(uj, zr, zur[i]);
-            zui[i] = fma(uj, zi, zui[i]);
-            zvr[i] = fma(vj, zr, zvr[i]);
-            zvi[i] = fma(vj, zi, zvi[i]);
-            zwr[i] = fma(wj, zr, zwr[i]);
-            zwi[i] = fma(wj, zi, zwi[i]);
+            z0[i] += zr;
+            zu[i] = fma(uj, zi, zu[i]);
+            zv[i] = fma(vj, zi, zv[i]);
+            zw[i] = fma(wj, zi, zw[i]);
         }
     }
 #pragma unroll
     for (int i = 0; i < CPL; ++i) {
         const int64_t k = k0 + (int64_t)i * kGradBlock;
         if (k < n_comp) {
-            double* o = partial + (chunk_id * 8) * n_comp + k;
-            o[0 * n_comp] = z0r[i];
-            o[1 * n_comp] = z0i[i];
-            o[2 * n_comp] = zur[i];
-            o[3 * n_comp] = zui[i];
-            o[4 * n_comp] = zvr[i];
-            o[5 * n_comp] = zvi[i];
-            o[6 * n_comp] = zwr[i];
-            o[7 * n_comp] = zwi[i];
+            double* o = partial + (chunk_id * 4) * n_comp + k;
+            o[0 * n_comp] = z0[i];
+            o[1 * n_comp] = zu[i];
+            o[2 * n_comp] = zv[i];
+            o[3 * n_comp] = zw[i];
         }
     }
 }
 
-// d_flux = alpha Re Z0
-// d_l    = alpha I Re[s 2 pi i (Zu - (l/n) Zw)] = -alpha I s 2 pi Im(Zu - (l/n) Zw)
-// d_m    = -alpha I s 2 pi Im(Zv - (m/n) Zw)
 __global__ void k_grad_finish(const double* __restrict__ partial, int64_t n_chunks,
                               const Comp* __restrict__ comp, int64_t n_comp, double sgn,
                               double alpha, double* __restrict__ d_flux, double* __restrict__ d_l,
                               double* __restrict__ d_m) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_comp) return;
-    double z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double z[4] = {0, 0, 0, 0};
     for (int64_t c = 0; c < n_chunks; ++c)
-        for (int t = 0; t < 8; ++t) z[t] += partial[(c * 8 + t) * n_comp + k];
+        for (int t = 0; t < 4; ++t) z[t] += partial[(c * 4 + t) * n_comp + k];
     const double n = 1.0 + comp[k].nm1;
     const double f = -alpha * comp[k].I * sgn * 2.0 * M_PI;
     d_flux[k] = alpha * z[0];
-    d_l[k] = f * (z[3] - (comp[k].l / n) * z[7]);
-    d_m[k] = f * (z[5] - (comp[k].m / n) * z[7]);
+    d_l[k] = f * (z[1] - (comp[k].l / n) * z[3]);
+    d_m[k] = f * (z[2] - (comp[k].m / n) * z[3]);
+}
+
+template <int CPL>
+static int grad_occ() {
+    static const int v = resident_blocks(k_grad_partial<CPL>, kGradBlock);
+    return v;
+}
+
+int grad_blocks_per_cu(int cpl) {
+    return cpl == 1 ? grad_occ<1>() : cpl == 2 ? grad_occ<2>() : grad_occ<4>();
 }
 
 hipError_t launch_grad(hipStream_t s, int cpl, int64_t chunk, int64_t n_vis, const double* u,

@@ -84,7 +84,7 @@ hipError_t launch_tree(hipStream_t s, int walker, int block, const TreeArgs& t, 
         switch (t.J) {
             SWV_TREE_CASE(1, 0) SWV_TREE_CASE(2, 0) SWV_TREE_CASE(3, 0) SWV_TREE_CASE(4, 0)
             SWV_TREE_CASE(5, 0) SWV_TREE_CASE(6, 0) SWV_TREE_CASE(7, 0) SWV_TREE_CASE(8, 0)
-            SWV_TREE_CASE(9, 0) SWV_TREE_CASE(10, 0) SWV_TREE_CASE(11, 0) SWV_TREE_CASE(12, 0)
+            SWV_TREE_CASE(9, 0) SWV_TREE_CASE(10, 0) SWV_TREE_CASE(11, 0)
             default: return hipErrorInvalidValue;
         }
     }

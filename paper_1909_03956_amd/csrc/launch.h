@@ -35,8 +35,10 @@ struct TreeArgs {
     double scale[SWV_MAX_LEVEL + 1];  // sqrt(A_j) / 4
 };
 
-// Largest J of the level walker (one register set per level).
-constexpr int kTreeMaxJ = 12;
+// Largest J of the level walker (one register set per level); beyond it the
+// per-level state no longer fits two waves per SIMD and the branch walker is
+// the faster one.
+constexpr int kTreeMaxJ = 11;
 // Largest segment depth of the branch walker (one register set per branching
 // node); it serves every J.
 constexpr int kTreeMaxSeg = 16;
@@ -51,6 +53,10 @@ hipError_t launch_adjoint(hipStream_t s, int prec, int ppl, int block, int64_t c
                           int64_t n_vis, const double* u, const double* v, const double* w,
                           const void* y, int64_t n_pix, const double* l, const double* m,
                           const double* nm1, int sign, void* partial, void* out);
+
+// Resident blocks per compute unit of the adjoint and gradient kernels.
+int adjoint_blocks_per_cu(int prec, int ppl, int block);
+int grad_blocks_per_cu(int cpl);
 
 hipError_t launch_grad(hipStream_t s, int cpl, int64_t chunk, int64_t n_vis, const double* u,
                        const double* v, const double* w, const void* y, const Comp* comp,

@@ -26,6 +26,8 @@ int64_t n_pixels(int j) { return 12LL << (2 * (j - 1)); }
 
 double pixel_area(int j) { return 4.0 * M_PI / (double)n_pixels(j); }
 
+double level_scale(int j) { return std::ldexp(std::sqrt(pixel_area(1)) / 4.0, 1 - j); }
+
 Frame make_frame(double ra_p, double dec_p) {
     const ld ca = cosl((ld)ra_p), sa = sinl((ld)ra_p);
     const ld cd = cosl((ld)dec_p), sd = sinl((ld)dec_p);

@@ -32,5 +32,8 @@ void xyz_to_lmn(const Frame& F, const ld xyz[3], double* l, double* m, double* n
 // N_j = 12 * 4^(j-1) and A_j = 4 pi / N_j.
 int64_t n_pixels(int j);
 double pixel_area(int j);
+// sqrt(A_j) / 4, formed as sqrt(A_1)/4 * 2^(1-j) (equal to the direct
+// evaluation, since A_j = A_1 4^(1-j) exactly in binary floating point).
+double level_scale(int j);
 
 }  // namespace swv

@@ -82,7 +82,9 @@ void build_coefficients(swv_tree_s* t) {
             s = e;
         }
     }
-    for (int j = 1; j <= J; ++j) t->level_scale[j] = std::sqrt(pixel_area(j)) / 4.0;
+    // sqrt(A_j)/4; A_j = A_1 4^(1-j), so every level's factor is the level-1
+    // factor times an exact power of two (the device forms it that way too)
+    for (int j = 1; j <= SWV_MAX_LEVEL; ++j) t->level_scale[j] = level_scale(j);
 
     // one-child runs and branching depth, bottom-up
     std::vector<int> depth_below(nl, 0);   // branching nodes strictly below, per node

@@ -52,6 +52,13 @@ __device__ __forceinline__ void close_node(const NodeSums& n, double a, double g
     Vi = fma(g2, s2i, Vi);
 }
 
+// sqrt(A_j)/4 of a level known only at run time: the level-1 factor times
+// 2^(1-j), the same value the host stores for every level, with no load that
+// waits on the record.
+__device__ __forceinline__ double level_factor(const TreeArgs& ta, int j) {
+    return ldexp(ta.scale[1], 1 - j);
+}
+
 // Leaf: eta_{J,k} = exp(2 pi i B . (s_k - P)) (imaginary part / 4).
 __device__ __forceinline__ void leaf_wave(RecPtr rec, int me, double u, double v, double w,
                                           double& er, double& ei) {
@@ -115,16 +122,18 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
                 seg_walk<D + 1, DMAX>(rec, pos, J, ta, u, v, w, xr, xi, Vr, Vi);
                 add_child(n, c, xr, xi);
             }
-            close_node(n, ta.scale[meta_level(mt)], rec[term].a, rec[term].b, rec[term].c, er,
-                       ei, Vr, Vi);
+            close_node(n, level_factor(ta, meta_level(mt)), rec[term].a, rec[term].b,
+                       rec[term].c, er, ei, Vr, Vi);
         }
     }
+    // the run, bottom-up
     for (int i = run - 1; i >= 0; --i) {
         const int me = first + i;
         const unsigned long long mm = rec[me].meta;
         NodeSums n;
         add_child(n, __builtin_ctz(meta_mask(mm)), er, ei);
-        close_node(n, ta.scale[meta_level(mm)], rec[me].a, rec[me].b, rec[me].c, er, ei, Vr, Vi);
+        close_node(n, level_factor(ta, meta_level(mm)), rec[me].a, rec[me].b, rec[me].c, er, ei,
+                   Vr, Vi);
     }
 }
 
