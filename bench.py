@@ -65,8 +65,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--profile", action="store_true",
                    help="short run for a profiler: no CPU baseline")
-    p.add_argument("--no-tune", action="store_true",
-                   help="keep the default tile shapes instead of autotuning first")
+    p.add_argument("--tune", action="store_true",
+                   help="run the autotuner (quick sweep) before the warmup instead of using "
+                        "the library's default tile shapes")
     p.add_argument("--tune-out", default=None,
                    help="write the autotuner's table and timings (JSON) to this path")
     p.add_argument("--copy-calibration", action="store_true",
@@ -225,7 +226,7 @@ def main():
         f"components, {n_pix} pixels")
     ctx = swv.context(dev)
     families = ("direct_fp64", "direct_f32c", "tree", "adjoint", "grad")
-    if not args.no_tune:
+    if args.tune:
         t_tune = time.perf_counter()
         ctx.autotune(cache_path=args.tune_out, quick=True)   # untimed: picks the tile shapes
         log(f"autotuned in {time.perf_counter() - t_tune:.2f} s")

@@ -117,18 +117,38 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
     }
 }
 
-// out[p] = sum over chunks c (in order) of partial[c][p]
-__global__ void k_sum_chunks_c128(const double2* __restrict__ partial, int64_t n_chunks,
-                                  int64_t n, double2* __restrict__ out) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+// out[p] = sum over chunks c of partial[c][p].
+// Chunk reductions: a block owns kSumCols consecutive outputs (coalesced along
+// x); its kSumQ rows of threads each add the chunks q, q + kSumQ, ... in order,
+// and the kSumQ subtotals are then added by a fixed binary tree in LDS.  The
+// order depends only on the chunk count, so results are run-to-run identical.
+constexpr int kSumCols = 64;
+constexpr int kSumQ = 16;
+
+__global__ __launch_bounds__(kSumCols * kSumQ) void k_sum_chunks_c128(
+    const double2* __restrict__ partial, int64_t n_chunks, int64_t n, double2* __restrict__ out) {
+    __shared__ double red_r[kSumQ][kSumCols], red_i[kSumQ][kSumCols];
+    const int tx = threadIdx.x % kSumCols, q = threadIdx.x / kSumCols;
+    const int64_t p = (int64_t)blockIdx.x * kSumCols + tx;
     double re = 0.0, im = 0.0;
-    for (int64_t c = 0; c < n_chunks; ++c) {
-        const double2 x = partial[c * n + p];
-        re += x.x;
-        im += x.y;
+    if (p < n) {
+        for (int64_t c = q; c < n_chunks; c += kSumQ) {
+            const double2 x = partial[c * n + p];
+            re += x.x;
+            im += x.y;
+        }
     }
-    out[p] = make_double2(re, im);
+    red_r[q][tx] = re;
+    red_i[q][tx] = im;
+    __syncthreads();
+    for (int h = kSumQ / 2; h > 0; h >>= 1) {
+        if (q < h) {
+            red_r[q][tx] += red_r[q + h][tx];
+            red_i[q][tx] += red_i[q + h][tx];
+        }
+        __syncthreads();
+    }
+    if (q == 0 && p < n) out[p] = make_double2(red_r[0][tx], red_i[0][tx]);
 }
 
 template <int PPL, int BLOCK, int PREC>
@@ -214,8 +234,9 @@ hipError_t launch_adjoint(hipStream_t s, int prec, int ppl, int block, int64_t c
         }
         if (e != hipSuccess) return e;
     }
-    k_sum_chunks_c128<<<dim3((unsigned)((n_pix + 255) / 256)), dim3(256), 0, s>>>(
-        (const double2*)partial, n_chunks, n_pix, (double2*)out);
+    k_sum_chunks_c128<<<dim3((unsigned)((n_pix + kSumCols - 1) / kSumCols)),
+                        dim3(kSumCols * kSumQ), 0, s>>>((const double2*)partial, n_chunks, n_pix,
+                                                       (double2*)out);
     return hipGetLastError();
 }
 
@@ -288,20 +309,33 @@ __global__ __launch_bounds__(kGradBlock) void k_grad_partial(
     }
 }
 
-__global__ void k_grad_finish(const double* __restrict__ partial, int64_t n_chunks,
-                              const Comp* __restrict__ comp, int64_t n_comp, double sgn,
-                              double alpha, double* __restrict__ d_flux, double* __restrict__ d_l,
-                              double* __restrict__ d_m) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_comp) return;
+__global__ __launch_bounds__(kSumCols * kSumQ) void k_grad_finish(
+    const double* __restrict__ partial, int64_t n_chunks, const Comp* __restrict__ comp,
+    int64_t n_comp, double sgn, double alpha, double* __restrict__ d_flux,
+    double* __restrict__ d_l, double* __restrict__ d_m) {
+    __shared__ double red[4][kSumQ][kSumCols];
+    const int tx = threadIdx.x % kSumCols, q = threadIdx.x / kSumCols;
+    const int64_t k = (int64_t)blockIdx.x * kSumCols + tx;
     double z[4] = {0, 0, 0, 0};
-    for (int64_t c = 0; c < n_chunks; ++c)
-        for (int t = 0; t < 4; ++t) z[t] += partial[(c * 4 + t) * n_comp + k];
+    if (k < n_comp) {
+        for (int64_t c = q; c < n_chunks; c += kSumQ)
+            for (int t = 0; t < 4; ++t) z[t] += partial[(c * 4 + t) * n_comp + k];
+    }
+    for (int t = 0; t < 4; ++t) red[t][q][tx] = z[t];
+    __syncthreads();
+    for (int h = kSumQ / 2; h > 0; h >>= 1) {
+        if (q < h)
+            for (int t = 0; t < 4; ++t) red[t][q][tx] += red[t][q + h][tx];
+        __syncthreads();
+    }
+    if (q != 0 || k >= n_comp) return;
+    const double z0 = red[0][0][tx], zu = red[1][0][tx], zv = red[2][0][tx],
+                 zw = red[3][0][tx];
     const double n = 1.0 + comp[k].nm1;
     const double f = -alpha * comp[k].I * sgn * 2.0 * M_PI;
-    d_flux[k] = alpha * z[0];
-    d_l[k] = f * (z[1] - (comp[k].l / n) * z[3]);
-    d_m[k] = f * (z[2] - (comp[k].m / n) * z[3]);
+    d_flux[k] = alpha * z0;
+    d_l[k] = f * (zu - (comp[k].l / n) * zw);
+    d_m[k] = f * (zv - (comp[k].m / n) * zw);
 }
 
 template <int CPL>
@@ -338,8 +372,9 @@ hipError_t launch_grad(hipStream_t s, int cpl, int64_t chunk, int64_t n_vis, con
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    k_grad_finish<<<dim3((unsigned)((n_comp + 127) / 128)), dim3(128), 0, s>>>(
-        partial, n_chunks, comp, n_comp, (double)sign, alpha, d_flux, d_l, d_m);
+    k_grad_finish<<<dim3((unsigned)((n_comp + kSumCols - 1) / kSumCols)), dim3(kSumCols * kSumQ),
+                    0, s>>>(partial, n_chunks, comp, n_comp, (double)sign, alpha, d_flux, d_l,
+                            d_m);
     return hipGetLastError();
 }
 
@@ -374,12 +409,21 @@ __global__ __launch_bounds__(kResBlock) void k_residual(const double2* __restric
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void k_chi2_finish(const double* __restrict__ partial, int nb, double inv_sigma2,
-                              double* __restrict__ chi2) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One block: thread t adds partials t, t + kResBlock, ... in order, then a
+// fixed binary tree in LDS.
+__global__ __launch_bounds__(kResBlock) void k_chi2_finish(const double* __restrict__ partial,
+                                                           int nb, double inv_sigma2,
+                                                           double* __restrict__ chi2) {
+    __shared__ double red[kResBlock];
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partial[b];
-    *chi2 = s * inv_sigma2;
+    for (int b = threadIdx.x; b < nb; b += kResBlock) s += partial[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = kResBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *chi2 = red[0] * inv_sigma2;
 }
 
 hipError_t launch_residual(hipStream_t s, int64_t n_vis, const void* obs, const void* model,
@@ -392,7 +436,7 @@ hipError_t launch_residual(hipStream_t s, int64_t n_vis, const void* obs, const 
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    k_chi2_finish<<<1, 1, 0, s>>>(partial, nb, inv_sigma2, chi2);
+    k_chi2_finish<<<1, kResBlock, 0, s>>>(partial, nb, inv_sigma2, chi2);
     return hipGetLastError();
 }
 

@@ -223,6 +223,20 @@ def _run_batched(torch, swv, B, label):
     return outs, keep
 
 
+def test_device_tracks_equal_host_tracks(env):
+    # the batched workload's rows are made on the device; the oracle's on the host
+    torch, swv = env
+    B = configs.BatchedWorkload(scale=0.01)
+    for k in (0, 100, 255):
+        inst = B.instances[k]
+        kept, *_ = B.instance_rows_kept(inst)
+        dev_uvw = B.instance_uvw_torch(inst, kept, "cuda")
+        rows = configs.sample_rows(kept.size, 512, seed=k, tile=64)
+        host_uvw = B.instance_uvw_rows(inst, kept[rows])
+        for a, b in zip(dev_uvw, host_uvw):
+            assert np.array_equal(host(a[torch.as_tensor(rows, device="cuda")]), b)
+
+
 def test_batched_workload_scaled(env):
     torch, swv = env
     B = configs.BatchedWorkload(scale=0.01)
