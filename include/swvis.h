@@ -174,7 +174,7 @@ int swv_tree_set_flux(swv_tree tree, const double* leaf_flux);
  * complex128 (SWV_FP64 only).  The tree is copied to the device on first use
  * with this context's device.
  * Two traversals compute the same operations in the same order (bitwise equal
- * results): one keeps a register set per level (J <= 11), the other one per
+ * results): one keeps a register set per level (J <= 10), the other one per
  * open node with two or more children (any J, up to 15 such nodes on one
  * root-to-leaf path, see swv_tree_stats_t.max_branching).  The tuning table
  * picks between them where both fit; SWV_ENOTSUP if neither does. */
@@ -314,7 +314,7 @@ int swv_tune_load(swv_ctx ctx, const char* cache_path);
  * 0 is fewer than 2^20 visibility rows, 1 the rest.  per_lane is rows per lane
  * (direct), pixels per lane (adjoint) or components per lane (gradients), in
  * {1, 2, 4}; for the tree it selects the traversal (1: register set per level
- * where J <= 11, else per branching node; 2: always per branching node; see
+ * where J <= 10, else per branching node; 2: always per branching node; see
  * swv_predict_tree).  block is threads per block
  * in {64, 128, 256} (128 for the gradients).  Results do not depend on the shape except for
  * the summation order of the adjoint and gradients. */

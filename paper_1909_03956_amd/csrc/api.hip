@@ -51,7 +51,7 @@ void tune_defaults(swv_ctx ctx) {
     // (per_lane, block) per family, both size classes; see swv_tune_get.  The
     // fastest shapes measured on MI355X for a few thousand components, a
     // thousand pixels and 10^6 - 10^7 rows.
-    const int pl[kFamilies][2] = {{2, 64}, {1, 256}, {1, 128}, {4, 128}, {2, 128}};
+    const int pl[kFamilies][2] = {{2, 64}, {1, 256}, {1, 64}, {4, 128}, {2, 128}};
     for (int f = 0; f < kFamilies; ++f)
         for (int c = 0; c < 2; ++c) {
             ctx->per_lane[f][c] = pl[f][0];

@@ -95,6 +95,8 @@ __global__ __launch_bounds__(kBatchTreeBlock) void k_batch_tree(
     const int lane = threadIdx.x & 63;
     const auto* IT = uniform_ptr(items);
     const auto* IN = uniform_ptr(inst);
+    constexpr int LDSL = tree_lds_levels<JMAX, kBatchTreeBlock>();
+    __shared__ double sums[LDSL > 0 ? LDSL * 8 * kBatchTreeBlock : 1];
     for (;;) {
         const unsigned it = next_item(counter);
         if (it >= n_items) break;
@@ -115,7 +117,8 @@ __global__ __launch_bounds__(kBatchTreeBlock) void k_batch_tree(
             const int64_t j = jr < limit ? jr : limit - 1;
             const double U = u[j], V = v[j], W = w[j];
             double Vr, Vi;
-            tree_row<JMAX, WALKER>(rec, n_roots, J, scales, U, V, W, Vr, Vi);
+            tree_row<JMAX, WALKER, LDSL, kBatchTreeBlock>(rec, n_roots, J, scales, (LdsPtr)sums, U, V, W,
+                                                           Vr, Vi);
             if (jr < limit) {
                 if (!isfinite(U + V + W)) atomicOr(status, kStatusNonFinite);
                 out[jr] = make_double2(Vr, s4 * Vi);
@@ -154,7 +157,6 @@ static int tree_occupancy() {
 // Instantiates X(depth, walker) for every compiled traversal.
 #define SWV_TREE_SHAPES(X)                                                            \
     X(1, 0) X(2, 0) X(3, 0) X(4, 0) X(5, 0) X(6, 0) X(7, 0) X(8, 0) X(9, 0) X(10, 0)  \
-    X(11, 0)                                                                          \
     X(1, 1) X(2, 1) X(3, 1) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) X(9, 1) X(10, 1)  \
     X(11, 1) X(12, 1) X(13, 1) X(14, 1) X(15, 1) X(16, 1)
 

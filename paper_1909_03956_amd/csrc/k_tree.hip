@@ -40,8 +40,10 @@ __global__ __launch_bounds__(BLOCK) void k_tree(TreeArgs ta, const double* __res
     const int64_t jrow = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int64_t j = jrow < n_vis ? jrow : n_vis - 1;
     const double U = u[j], V = v[j], W = w[j];
+    constexpr int LDSL = tree_lds_levels<JMAX, BLOCK>();
+    __shared__ double sums[LDSL > 0 ? LDSL * 8 * BLOCK : 1];
     double Vr, Vi;
-    tree_row<JMAX, WALKER>(ta.rec, ta.n_roots, ta.J, ta, U, V, W, Vr, Vi);
+    tree_row<JMAX, WALKER, LDSL, BLOCK>(ta.rec, ta.n_roots, ta.J, ta, (LdsPtr)sums, U, V, W, Vr, Vi);
     if (jrow < n_vis) {
         if (!isfinite(U + V + W)) atomicOr(status, kStatusNonFinite);
         out[jrow] = make_double2(Vr, 4.0 * sgn * Vi);
@@ -84,7 +86,7 @@ hipError_t launch_tree(hipStream_t s, int walker, int block, const TreeArgs& t, 
         switch (t.J) {
             SWV_TREE_CASE(1, 0) SWV_TREE_CASE(2, 0) SWV_TREE_CASE(3, 0) SWV_TREE_CASE(4, 0)
             SWV_TREE_CASE(5, 0) SWV_TREE_CASE(6, 0) SWV_TREE_CASE(7, 0) SWV_TREE_CASE(8, 0)
-            SWV_TREE_CASE(9, 0) SWV_TREE_CASE(10, 0) SWV_TREE_CASE(11, 0)
+            SWV_TREE_CASE(9, 0) SWV_TREE_CASE(10, 0)
             default: return hipErrorInvalidValue;
         }
     }

@@ -38,7 +38,7 @@ struct TreeArgs {
 // Largest J of the level walker (one register set per level); beyond it the
 // per-level state no longer fits two waves per SIMD and the branch walker is
 // the faster one.
-constexpr int kTreeMaxJ = 11;
+constexpr int kTreeMaxJ = 10;
 // Largest segment depth of the branch walker (one register set per branching
 // node); it serves every J.
 constexpr int kTreeMaxSeg = 16;

@@ -9,6 +9,11 @@
 namespace swv {
 
 using RecPtr = const __attribute__((address_space(4))) TRec*;
+using LdsPtr = __attribute__((address_space(3))) double*;
+
+// Open levels (segments) whose running sums stay in registers; the ones above
+// them are kept in LDS (see slot_store).
+constexpr int kTreeRegLevels = 6;
 
 // Running sums of an open node over its finished children:
 //   S = sum_c eta_{j+1,c},   D^m = sum_c s^m_c eta_{j+1,c}   (m = 0, 1, 2).
@@ -52,6 +57,43 @@ __device__ __forceinline__ void close_node(const NodeSums& n, double a, double g
     Vi = fma(g2, s2i, Vi);
 }
 
+// Sums of the open nodes of the top LDSL levels (level walker) or segments
+// (branch walker) are kept in LDS rather than registers: such a node is
+// touched only when one of its few children finishes, and its registers would
+// otherwise stay allocated through every subtree below it, which limits how
+// many waves share a SIMD.  Layout [slot][8][BLOCK]: lane-contiguous, so the
+// accesses are free of bank conflicts.
+// The accesses are volatile: otherwise the compiler, seeing the whole inlined
+// walk, forwards each stored value to its reload and keeps it in registers.
+template <int BLOCK>
+__device__ __forceinline__ void slot_store(LdsPtr lds, int slot, const NodeSums& n) {
+    volatile __attribute__((address_space(3))) double* p = lds + slot * 8 * BLOCK + threadIdx.x;
+    p[0 * BLOCK] = n.Sr;
+    p[1 * BLOCK] = n.Si;
+    p[2 * BLOCK] = n.D0r;
+    p[3 * BLOCK] = n.D0i;
+    p[4 * BLOCK] = n.D1r;
+    p[5 * BLOCK] = n.D1i;
+    p[6 * BLOCK] = n.D2r;
+    p[7 * BLOCK] = n.D2i;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ NodeSums slot_load(LdsPtr lds, int slot) {
+    const volatile __attribute__((address_space(3))) double* p =
+        lds + slot * 8 * BLOCK + threadIdx.x;
+    NodeSums n;
+    n.Sr = p[0 * BLOCK];
+    n.Si = p[1 * BLOCK];
+    n.D0r = p[2 * BLOCK];
+    n.D0i = p[3 * BLOCK];
+    n.D1r = p[4 * BLOCK];
+    n.D1i = p[5 * BLOCK];
+    n.D2r = p[6 * BLOCK];
+    n.D2i = p[7 * BLOCK];
+    return n;
+}
+
 // sqrt(A_j)/4 of a level known only at run time: the level-1 factor times
 // 2^(1-j), the same value the host stores for every level, with no load that
 // waits on the record.
@@ -68,11 +110,12 @@ __device__ __forceinline__ void leaf_wave(RecPtr rec, int me, double u, double v
     ei = q;
 }
 
-// Level walker: one register set per level, the level a template parameter.
-template <int LVL, int JMAX>
+// Level walker: one register set per level, the level a template parameter
+// (levels <= LDSL keep theirs in LDS).
+template <int LVL, int JMAX, int LDSL, int BLOCK>
 __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const TreeArgs& ta,
-                                     const double u, const double v, const double w, double& er,
-                                     double& ei, double& Vr, double& Vi) {
+                                     LdsPtr lds, const double u, const double v, const double w,
+                                     double& er, double& ei, double& Vr, double& Vi) {
     const int me = pos++;
     if (LVL == JMAX || LVL == J) {
         leaf_wave(rec, me, u, v, w, er, ei);
@@ -81,12 +124,19 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const Tr
     if constexpr (LVL < JMAX) {
         unsigned mask = meta_mask(rec[me].meta);
         NodeSums n;
+        if constexpr (LVL <= LDSL) slot_store<BLOCK>(lds, LVL - 1, n);
         while (mask) {
             const int c = __builtin_ctz(mask);
             mask &= mask - 1;
             double xr, xi;
-            walk<LVL + 1, JMAX>(rec, pos, J, ta, u, v, w, xr, xi, Vr, Vi);
-            add_child(n, c, xr, xi);
+            walk<LVL + 1, JMAX, LDSL, BLOCK>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr, Vi);
+            if constexpr (LVL <= LDSL) {
+                n = slot_load<BLOCK>(lds, LVL - 1);
+                add_child(n, c, xr, xi);
+                if (mask) slot_store<BLOCK>(lds, LVL - 1, n);
+            } else {
+                add_child(n, c, xr, xi);
+            }
         }
         close_node(n, ta.scale[LVL], rec[me].a, rec[me].b, rec[me].c, er, ei, Vr, Vi);
     }
@@ -98,10 +148,11 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const Tr
 // walked, and is closed bottom-up afterwards with the same arithmetic a
 // one-child node gets in the level walker.  D counts segments from the root;
 // the host launches DMAX >= 1 + the tree's largest branching count on a path.
-template <int D, int DMAX>
+template <int D, int DMAX, int LDSL, int BLOCK>
 __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, const TreeArgs& ta,
-                                         const double u, const double v, const double w,
-                                         double& er, double& ei, double& Vr, double& Vi) {
+                                         LdsPtr lds, const double u, const double v,
+                                         const double w, double& er, double& ei, double& Vr,
+                                         double& Vi) {
     const int first = pos;
     const int run = meta_chain(rec[first].meta);
     const int term = first + run;
@@ -115,12 +166,20 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
         if constexpr (D < DMAX) {
             unsigned mask = meta_mask(mt);
             NodeSums n;
+            if constexpr (D <= LDSL) slot_store<BLOCK>(lds, D - 1, n);
             while (mask) {
                 const int c = __builtin_ctz(mask);
                 mask &= mask - 1;
                 double xr, xi;
-                seg_walk<D + 1, DMAX>(rec, pos, J, ta, u, v, w, xr, xi, Vr, Vi);
-                add_child(n, c, xr, xi);
+                seg_walk<D + 1, DMAX, LDSL, BLOCK>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr,
+                                                   Vi);
+                if constexpr (D <= LDSL) {
+                    n = slot_load<BLOCK>(lds, D - 1);
+                    add_child(n, c, xr, xi);
+                    if (mask) slot_store<BLOCK>(lds, D - 1, n);
+                } else {
+                    add_child(n, c, xr, xi);
+                }
             }
             close_node(n, level_factor(ta, meta_level(mt)), rec[term].a, rec[term].b,
                        rec[term].c, er, ei, Vr, Vi);
@@ -137,12 +196,22 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
     }
 }
 
+// Levels (segments) of a traversal compiled to depth JMAX whose sums go to
+// LDS: all but the deepest kTreeRegLevels, within 64 KB per block.
+template <int JMAX, int BLOCK>
+constexpr int tree_lds_levels() {
+    constexpr int want = JMAX > kTreeRegLevels ? JMAX - kTreeRegLevels : 0;
+    constexpr int cap = (64 * 1024) / (8 * 8 * BLOCK);
+    return want < cap ? want : cap;
+}
+
 // V (real, imaginary / 4) of one row: the root loop of the traversal.
 // WALKER 0: level walker up to level JMAX; 1: branch walker up to JMAX segments.
-template <int JMAX, int WALKER = 0>
+// lds: the block's [LDSL][8][BLOCK] sum slots.
+template <int JMAX, int WALKER, int LDSL, int BLOCK>
 __device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J,
-                                         const TreeArgs& ta, double U, double V, double W,
-                                         double& Vr, double& Vi) {
+                                         const TreeArgs& ta, LdsPtr lds, double U, double V,
+                                         double W, double& Vr, double& Vi) {
     const RecPtr rec = uniform_ptr(recs);
     Vr = 0.0;
     Vi = 0.0;
@@ -151,9 +220,9 @@ __device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J,
         const int root = pos++;
         double er, ei;
         if constexpr (WALKER == 0)
-            walk<1, JMAX>(rec, pos, J, ta, U, V, W, er, ei, Vr, Vi);
+            walk<1, JMAX, LDSL, BLOCK>(rec, pos, J, ta, lds, U, V, W, er, ei, Vr, Vi);
         else
-            seg_walk<1, JMAX>(rec, pos, J, ta, U, V, W, er, ei, Vr, Vi);
+            seg_walk<1, JMAX, LDSL, BLOCK>(rec, pos, J, ta, lds, U, V, W, er, ei, Vr, Vi);
         const double A1lam = rec[root].a;  // A_1 lambda_1
         Vr = fma(A1lam, er, Vr);
         Vi = fma(A1lam, ei, Vi);
