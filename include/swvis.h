@@ -296,6 +296,24 @@ int swv_graph_launch(swv_graph graph);
 int swv_graph_destroy(swv_graph graph);
 int swv_plan_destroy(swv_plan plan);
 
+/* ------------------------------------------------------ measured peaks --- */
+
+typedef struct {
+    double fp64_fma_tflops;   /* FP64 FMA stream, flop/s (FMA = 2) */
+    double fp32_fma_tflops;   /* FP32 FMA stream, unpacked instructions */
+    double sincos_f32_gops;   /* hardware FP32 sine + cosine pairs per second */
+    double cis2pi_f64_gops;   /* FP64 phasors (the polynomial of every FP64
+                                 kernel) per second */
+} swv_peaks_t;
+
+/* Measures the arithmetic ceilings of the device of `ctx` with
+ * microbenchmarks of independent dependency chains (one warm-up launch, then
+ * the median of three, tens of milliseconds each; about 0.3 s in all).  The
+ * published peak is an upper bound the part reaches only at full clock; these
+ * figures are what this library's kernels can reach.  Allocates and frees a
+ * scratch buffer; synchronises the context's stream. */
+int swv_measure_peaks(swv_ctx ctx, swv_peaks_t* out);
+
 /* ------------------------------------------------------------- tuning --- */
 
 /* Times every compiled tile shape of each kernel family (direct FP64,

@@ -32,6 +32,11 @@ class TreeStats(C.Structure):
                 ("build_seconds", C.c_double), ("max_branching", C.c_int)]
 
 
+class Peaks(C.Structure):
+    _fields_ = [("fp64_fma_tflops", C.c_double), ("fp32_fma_tflops", C.c_double),
+                ("sincos_f32_gops", C.c_double), ("cis2pi_f64_gops", C.c_double)]
+
+
 class PlanStats(C.Structure):
     _fields_ = [("n_instances", C.c_int64), ("n_items", C.c_int64),
                 ("total_terms", C.c_int64), ("tile_rows", C.c_int),
@@ -80,6 +85,7 @@ SIGNATURES = {
     "swv_tune_load": [_vp, C.c_char_p],
     "swv_tune_get": [_vp, _int, _int, C.POINTER(C.c_int), C.POINTER(C.c_int)],
     "swv_tune_set": [_vp, _int, _int, _int, _int],
+    "swv_measure_peaks": [_vp, _vp],
 }
 
 _lib = None

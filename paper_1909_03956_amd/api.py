@@ -99,6 +99,14 @@ class Context:
         p = cache_path.encode() if cache_path else None
         check(lib().swv_autotune(self._h, p, 1 if quick else 0))
 
+    def measure_peaks(self) -> dict:
+        """Measured arithmetic ceilings of this context's device (about 0.3 s)."""
+        from ._lib import Peaks
+        p = Peaks()
+        check(lib().swv_measure_peaks(self._h, C.byref(p)))
+        return {"fp64_fma_tflops": p.fp64_fma_tflops, "fp32_fma_tflops": p.fp32_fma_tflops,
+                "sincos_f32_gops": p.sincos_f32_gops, "cis2pi_f64_gops": p.cis2pi_f64_gops}
+
     def tune_load(self, cache_path):
         check(lib().swv_tune_load(self._h, cache_path.encode()))
 

@@ -1,0 +1,21 @@
+"""The measured arithmetic ceilings (the microbenchmarks behind the bench's
+measured-peak figures) run and give plausible rates: positive and within the
+published MI355X peaks (FP64 vector 78.6 TFLOP/s, FP32 vector 157.3 TFLOP/s)."""
+import pytest
+
+from .gpu_util import note, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def test_measured_peaks_plausible():
+    torch, swv = require_gpu()
+    p = swv.context().measure_peaks()
+    note("measured peaks: " + ", ".join(f"{k} {v:.2f}" for k, v in p.items()))
+    assert 10.0 < p["fp64_fma_tflops"] <= 78.6 * 1.05
+    assert 10.0 < p["fp32_fma_tflops"] <= 157.3 * 1.05
+    assert p["sincos_f32_gops"] > 0
+    # one FP64 phasor costs 21 FP64 VALU lane-operations: phasors per second
+    # times 21 cannot beat the FMA stream's lane-operation rate
+    fma_lane_ops = p["fp64_fma_tflops"] * 1e12 / 2
+    assert p["cis2pi_f64_gops"] * 1e9 * 21 <= fma_lane_ops * 1.05
