@@ -29,27 +29,57 @@ __host__ __device__ __forceinline__ double reduced_phase(double u, double v, dou
     return ph - rint(ph);
 }
 
-__host__ __device__ __forceinline__ void cis2pi_q(double r, double& c, double& q) {
+// Fused multiply-add as one 3-operand v_fma_f64 on VGPRs: the same rounding
+// as fma(), but never the two-address form (a copy of the addend into the
+// destination, then v_fmac_f64) that the compiler picks when the addend is a
+// value it keeps, such as a polynomial coefficient held in a register across
+// loops.
+__device__ __forceinline__ double fma_v(double a, double b, double c) {
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
+template <bool VOP3>
+__host__ __device__ __forceinline__ double fma_sel(double a, double b, double c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (VOP3) return fma_v(a, b, c);
+#endif
+    return fma(a, b, c);
+}
+
+template <bool VOP3>
+__host__ __device__ __forceinline__ void cis2pi_q_impl(double r, double& c, double& q) {
     const double t = r * r;
     double ps = kS64[6];
-    ps = fma(ps, t, kS64[5]);
-    ps = fma(ps, t, kS64[4]);
-    ps = fma(ps, t, kS64[3]);
-    ps = fma(ps, t, kS64[2]);
-    ps = fma(ps, t, kS64[1]);
-    ps = fma(ps, t, kS64[0]);
+    ps = fma_sel<VOP3>(ps, t, kS64[5]);
+    ps = fma_sel<VOP3>(ps, t, kS64[4]);
+    ps = fma_sel<VOP3>(ps, t, kS64[3]);
+    ps = fma_sel<VOP3>(ps, t, kS64[2]);
+    ps = fma_sel<VOP3>(ps, t, kS64[1]);
+    ps = fma_sel<VOP3>(ps, t, kS64[0]);
     double pc = kC64[5];
-    pc = fma(pc, t, kC64[4]);
-    pc = fma(pc, t, kC64[3]);
-    pc = fma(pc, t, kC64[2]);
-    pc = fma(pc, t, kC64[1]);
-    pc = fma(pc, t, kC64[0]);
+    pc = fma_sel<VOP3>(pc, t, kC64[4]);
+    pc = fma_sel<VOP3>(pc, t, kC64[3]);
+    pc = fma_sel<VOP3>(pc, t, kC64[2]);
+    pc = fma_sel<VOP3>(pc, t, kC64[1]);
+    pc = fma_sel<VOP3>(pc, t, kC64[0]);
     const double s1 = r * ps;
     const double c1 = fma(pc, t, 1.0);
     const double p = s1 * c1;
     const double d = fma(c1, c1, -(s1 * s1));
     c = fma(-8.0 * p, p, 1.0);
     q = p * d;
+}
+
+__host__ __device__ __forceinline__ void cis2pi_q(double r, double& c, double& q) {
+    cis2pi_q_impl<false>(r, c, q);
+}
+
+// The same phasor with every polynomial step a 3-operand FMA (for kernels
+// whose coefficients live in VGPRs; bitwise equal to cis2pi_q).
+__host__ __device__ __forceinline__ void cis2pi_q_vop3(double r, double& c, double& q) {
+    cis2pi_q_impl<true>(r, c, q);
 }
 
 // FP32 phasor of a reduced phase |r| <= 1/2 in cycles: cos(2 pi r), sin(2 pi r)

@@ -18,24 +18,37 @@ constexpr int kTreeRegLevels = 6;
 // Running sums of an open node over its finished children:
 //   S = sum_c eta_{j+1,c},   D^m = sum_c s^m_c eta_{j+1,c}   (m = 0, 1, 2).
 struct NodeSums {
-    double Sr = 0.0, Si = 0.0, D0r = 0.0, D0i = 0.0, D1r = 0.0, D1i = 0.0, D2r = 0.0,
-           D2i = 0.0;
+    double Sr, Si, D0r, D0i, D1r, D1i, D2r, D2i;
 };
 
-// Adds child c's plane-wave coefficient x to the sums.
-__device__ __forceinline__ void add_child(NodeSums& n, int c, double xr, double xi) {
-    // Eq. 10 signs of child c: gamma^0 (+-+-), gamma^1 (++--), gamma^2 (+--+)
+// Takes child c's plane-wave coefficient x into the sums: the first child
+// sets them (S = x, D^m = s^m_c x), later ones add to them.  `first` is the
+// same for every lane, so this is a scalar branch, and no sums need zeroing.
+__device__ __forceinline__ void add_child(NodeSums& n, int c, double xr, double xi, bool first) {
+    // Eq. 10 signs of child c: gamma^0 (+-+-), gamma^1 (++--), gamma^2 (+--+),
+    // chosen as scalars
     const double s0 = (c & 1) ? -1.0 : 1.0;
     const double s1 = (c & 2) ? -1.0 : 1.0;
-    const double s2 = s0 * s1;
-    n.Sr += xr;
-    n.Si += xi;
-    n.D0r = fma(s0, xr, n.D0r);
-    n.D0i = fma(s0, xi, n.D0i);
-    n.D1r = fma(s1, xr, n.D1r);
-    n.D1i = fma(s1, xi, n.D1i);
-    n.D2r = fma(s2, xr, n.D2r);
-    n.D2i = fma(s2, xi, n.D2i);
+    const double s2 = ((c ^ (c >> 1)) & 1) ? -1.0 : 1.0;
+    if (first) {
+        n.Sr = xr;
+        n.Si = xi;
+        n.D0r = s0 * xr;
+        n.D0i = s0 * xi;
+        n.D1r = s1 * xr;
+        n.D1i = s1 * xi;
+        n.D2r = s2 * xr;
+        n.D2i = s2 * xi;
+    } else {
+        n.Sr += xr;
+        n.Si += xi;
+        n.D0r = fma(s0, xr, n.D0r);
+        n.D0i = fma(s0, xi, n.D0i);
+        n.D1r = fma(s1, xr, n.D1r);
+        n.D1i = fma(s1, xi, n.D1i);
+        n.D2r = fma(s2, xr, n.D2r);
+        n.D2i = fma(s2, xi, n.D2i);
+    }
 }
 
 // Closes a node at level j (a = sqrt(A_j)/4, g = gamma^m_j): eta_j (Eq. 9 on
@@ -101,11 +114,40 @@ __device__ __forceinline__ double level_factor(const TreeArgs& ta, int j) {
     return ldexp(ta.scale[1], 1 - j);
 }
 
-// Leaf: eta_{J,k} = exp(2 pi i B . (s_k - P)) (imaginary part / 4).
+// Closes a node whose only child c returned x: eta_j = x / 4 and
+// sigma^m_j = (s^m_c a) x -- equal bit for bit to close_node after add_child
+// (a (s^m_c x)), since a product with +-1 is exact -- then gamma^m_j sigma^m_j
+// is added to V.
+__device__ __forceinline__ void close_single(int c, double a, double g0, double g1, double g2,
+                                             double& er, double& ei, double& Vr, double& Vi) {
+    const double xr = er, xi = ei;
+    const double a0 = (c & 1) ? -a : a;
+    const double a1 = (c & 2) ? -a : a;
+    const double a2 = ((c ^ (c >> 1)) & 1) ? -a : a;
+    er = 0.25 * xr;
+    ei = 0.25 * xi;
+    const double s0r = a0 * xr, s0i = a0 * xi;
+    const double s1r = a1 * xr, s1i = a1 * xi;
+    const double s2r = a2 * xr, s2i = a2 * xi;
+    Vr = fma(g0, s0r, Vr);
+    Vi = fma(g0, s0i, Vi);
+    Vr = fma(g1, s1r, Vr);
+    Vi = fma(g1, s1i, Vi);
+    Vr = fma(g2, s2r, Vr);
+    Vi = fma(g2, s2i, Vi);
+}
+
+// Leaf: eta_{J,k} = exp(2 pi i B . (s_k - P)) (imaginary part / 4).  VOP3
+// selects the phasor whose polynomial steps are 3-operand FMAs (same values).
+template <bool VOP3>
 __device__ __forceinline__ void leaf_wave(RecPtr rec, int me, double u, double v, double w,
                                           double& er, double& ei) {
     double c, q;
-    cis2pi_q(reduced_phase(u, v, w, rec[me].a, rec[me].b, rec[me].c), c, q);
+    const double r = reduced_phase(u, v, w, rec[me].a, rec[me].b, rec[me].c);
+    if constexpr (VOP3)
+        cis2pi_q_vop3(r, c, q);
+    else
+        cis2pi_q(r, c, q);
     er = c;
     ei = q;
 }
@@ -118,25 +160,29 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const Tr
                                      double& er, double& ei, double& Vr, double& Vi) {
     const int me = pos++;
     if (LVL == JMAX || LVL == J) {
-        leaf_wave(rec, me, u, v, w, er, ei);
+        leaf_wave<true>(rec, me, u, v, w, er, ei);
         return;
     }
     if constexpr (LVL < JMAX) {
         unsigned mask = meta_mask(rec[me].meta);
         NodeSums n;
-        if constexpr (LVL <= LDSL) slot_store<BLOCK>(lds, LVL - 1, n);
+        bool first = true;
         while (mask) {
             const int c = __builtin_ctz(mask);
             mask &= mask - 1;
             double xr, xi;
             walk<LVL + 1, JMAX, LDSL, BLOCK>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr, Vi);
             if constexpr (LVL <= LDSL) {
-                n = slot_load<BLOCK>(lds, LVL - 1);
-                add_child(n, c, xr, xi);
-                if (mask) slot_store<BLOCK>(lds, LVL - 1, n);
+                // a fresh value every iteration: nothing of this level stays
+                // in registers while the next child's subtree is walked
+                NodeSums m = first ? NodeSums{} : slot_load<BLOCK>(lds, LVL - 1);
+                add_child(m, c, xr, xi, first);
+                if (mask) slot_store<BLOCK>(lds, LVL - 1, m);
+                n = m;
             } else {
-                add_child(n, c, xr, xi);
+                add_child(n, c, xr, xi, first);
             }
+            first = false;
         }
         close_node(n, ta.scale[LVL], rec[me].a, rec[me].b, rec[me].c, er, ei, Vr, Vi);
     }
@@ -161,11 +207,12 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
     er = 0.0;
     ei = 0.0;
     if (meta_level(mt) == J) {
-        leaf_wave(rec, term, u, v, w, er, ei);
+        leaf_wave<false>(rec, term, u, v, w, er, ei);
     } else {
         if constexpr (D < DMAX) {
+            // a terminal node has two or more children: its sums start at zero
             unsigned mask = meta_mask(mt);
-            NodeSums n;
+            NodeSums n{};
             if constexpr (D <= LDSL) slot_store<BLOCK>(lds, D - 1, n);
             while (mask) {
                 const int c = __builtin_ctz(mask);
@@ -175,10 +222,10 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
                                                    Vi);
                 if constexpr (D <= LDSL) {
                     n = slot_load<BLOCK>(lds, D - 1);
-                    add_child(n, c, xr, xi);
+                    add_child(n, c, xr, xi, false);
                     if (mask) slot_store<BLOCK>(lds, D - 1, n);
                 } else {
-                    add_child(n, c, xr, xi);
+                    add_child(n, c, xr, xi, false);
                 }
             }
             close_node(n, level_factor(ta, meta_level(mt)), rec[term].a, rec[term].b,
@@ -189,10 +236,8 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
     for (int i = run - 1; i >= 0; --i) {
         const int me = first + i;
         const unsigned long long mm = rec[me].meta;
-        NodeSums n;
-        add_child(n, __builtin_ctz(meta_mask(mm)), er, ei);
-        close_node(n, level_factor(ta, meta_level(mm)), rec[me].a, rec[me].b, rec[me].c, er, ei,
-                   Vr, Vi);
+        close_single(__builtin_ctz(meta_mask(mm)), level_factor(ta, meta_level(mm)), rec[me].a,
+                     rec[me].b, rec[me].c, er, ei, Vr, Vi);
     }
 }
 
