@@ -68,6 +68,10 @@ def parse():
     p.add_argument("--tune", action="store_true",
                    help="run the autotuner (quick sweep) before the warmup instead of using "
                         "the library's default tile shapes")
+    p.add_argument("--sweep", action="store_true",
+                   help="instead of the step: the tree route's run-time sweep over J = 12..25 "
+                        "and 10..140 distinct components on a one-hour, one-second 27-antenna "
+                        "track (one JSON line per point, then a summary line)")
     p.add_argument("--tune-out", default=None,
                    help="write the autotuner's table and timings (JSON) to this path")
     p.add_argument("--copy-calibration", action="store_true",
@@ -178,12 +182,87 @@ def traffic_for(kernel_file: str, per_launch_key: str):
     return rec.get("bytes_per_launch")
 
 
+def run_sweep():
+    """Time per visibility of the tree route (host build excluded, reported
+    apart) against J and against the number of distinct components, the two
+    axes of the paper's run-time scaling figure (section 3.6.1)."""
+    import numpy as np
+    import torch
+
+    import paper_1909_03956_amd as swv
+    from synth import configs
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    T = configs.SWEEP_TRACK
+    u, v, w = (torch.as_tensor(a, device=dev) for a in T.uvw())
+    ra, dec = math.radians(T.ra_deg), math.radians(T.dec_deg)
+    n = u.numel()
+    out = torch.empty(n, dtype=torch.complex128, device=dev)
+    ctx = swv.context(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def point(J, n_comp):
+        l, m, f = configs.sweep_components(n_comp)
+        t = swv.Tree(J, ra, dec, l, m, f)
+        st = t.stats()
+        t.predict(u, v, w, out=out)
+        ctx.synchronize()
+        times = []
+        for _ in range(5):
+            e0.record()
+            t.predict(u, v, w, out=out)
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        rec = {"sweep": True, "J": J, "n_comp": n_comp, "distinct": st["n_leaves"],
+               "internal_nodes": st["n_internal"], "max_branching": st["max_branching"],
+               "n_vis": n, "ms": round(ms, 4), "ns_per_vis": round(ms * 1e6 / n, 3),
+               "Gvis_terms_per_s": round(n * n_comp / (ms * 1e-3) / 1e9, 2),
+               "Gvis_nodes_per_s": round(n * (st["n_leaves"] + st["n_internal"]) /
+                                         (ms * 1e-3) / 1e9, 2),
+               "host_build_ms": round(1e3 * st["build_seconds"], 3)}
+        t.close()
+        print(json.dumps(rec), flush=True)
+        return rec
+
+    by_j = {nc: [point(J, nc) for J in range(12, 26)] for nc in (15, 140)}
+    by_n = {J: [point(J, nc) for nc in range(10, 141, 10)] for J in (12, 15, 25)}
+
+    def growth(recs):   # least-squares exp fit: time ~ g^J
+        J = np.array([r["J"] for r in recs], float)
+        y = np.log([r["ms"] for r in recs])
+        return float(np.exp(np.polyfit(J, y, 1)[0]))
+
+    def linearity(recs):   # time against distinct components: slope, intercept, R^2
+        x = np.array([r["distinct"] for r in recs], float)
+        y = np.array([r["ms"] for r in recs], float)
+        a, b = np.polyfit(x, y, 1)
+        r2 = 1 - np.sum((y - (a * x + b)) ** 2) / np.sum((y - y.mean()) ** 2)
+        return {"ms_per_distinct": round(float(a), 5), "ms_at_zero": round(float(b), 4),
+                "r2": round(float(r2), 5)}
+
+    j20 = {nc: next(r for r in by_j[nc] if r["J"] == 20) for nc in by_j}
+    print(json.dumps({
+        "sweep_summary": True, "track": "27 antennas, 1 h at 1 s, 1,263,600 rows",
+        "growth_per_level": {str(nc): round(growth(by_j[nc]), 4) for nc in by_j},
+        "paper_growth_per_level": 1.07,
+        "time_vs_distinct": {str(J): linearity(by_n[J]) for J in by_n},
+        "J20_ms": {str(nc): j20[nc]["ms"] for nc in j20},
+        "paper_J20_s_per_major_cycle": {"140": 1000, "15": 146},
+    }), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (--gpus "
               f"{args.gpus} requested); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.sweep:
+        run_sweep()
+        return
 
     import numpy as np
     import torch

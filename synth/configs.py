@@ -15,6 +15,8 @@ cfg4  batched case: 64 channels (0.95-1.75 GHz) x 4 pointings; per instance
 cfg5  adjoint case: cfg2 tracks and model; a perturbed model plus complex
       noise (sigma 0.01 Jy) gives observed visibilities; residual image on the
       level-9 pixels within 4 deg of the phase centre.
+sweep tree-route run-time sweep: a 27-antenna one-hour, one-second track
+      (1,263,600 rows), 10-140 distinct components, J = 12-25.
 
 The phase centre of every config is at right ascension 12h, the
 declination of its tracks.
@@ -103,6 +105,20 @@ CFG5_SEED_PERTURB = 502
 CFG5_SEED_NOISE = 503
 
 WORKLOADS = {w.name: w for w in (CFG1, CFG2, CFG3)}
+
+# Run-time sweep of the tree route (section 3.6.1): a JVLA-like one-hour track
+# at one-second sampling, 27 antennas -> 351 baselines x 3600 = 1,263,600 rows
+# (C-configuration extent, the 10 MHz, dec +45 deg simulation the sweep used);
+# distinct components uniform over a 20 deg field.
+SWEEP_TRACK = TrackSpec(27, 1.7e3, 45.0, 1 * H, 3600, 1.0e7, seed=601)
+SWEEP_FIELD_DEG = 20.0
+SWEEP_SEED_MODEL = 602
+
+
+def sweep_components(n_distinct: int, seed: int = SWEEP_SEED_MODEL):
+    """n_distinct components uniform over the sweep field, lognormal fluxes."""
+    rng = np.random.default_rng(seed + n_distinct)
+    return models.uniform_components(n_distinct, SWEEP_FIELD_DEG, rng)
 
 
 def sample_rows(n_vis: int, n_sample: int, seed: int, tile: int = 256) -> np.ndarray:

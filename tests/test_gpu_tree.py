@@ -230,3 +230,23 @@ def test_tree_bitwise_reproducible(env):
     _, a = _tree_run(env, 6, W.ra_p, W.dec_p, l, m, f, u, v, w)
     _, b = _tree_run(env, 6, W.ra_p, W.dec_p, l, m, f, u, v, w)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("J,n", [(20, 140), (25, 15)])
+def test_sweep_workload_vs_oracle(env, J, n):
+    # the run-time sweep's own inputs: a one-hour, one-second 27-antenna track
+    torch, swv = env
+    T = configs.SWEEP_TRACK
+    u, v, w = T.uvw()
+    l, m, f = configs.sweep_components(n)
+    ra, dec = np.radians(T.ra_deg), np.radians(T.dec_deg)
+    t = swv.Tree(J, ra, dec, l, m, f)
+    out = t.predict(dev(u, torch), dev(v, torch), dev(w, torch))
+    swv.synchronize()
+    rows = configs.sample_rows(u.size, 1024, seed=J)
+    got = host(out[torch.as_tensor(rows, device="cuda")])
+    rt = ot.build_tree(J, ra, dec, l, m, f)
+    ref = ot.predict_tree(rt, u[rows], v[rows], w[rows])
+    e_max, e_rms = errors(got, ref, f.sum())
+    note(f"sweep J={J} N~_C={rt.n_leaves}: E_max={e_max:.3e} E_rms={e_rms:.3e}")
+    assert e_max <= TOL64
