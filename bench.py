@@ -362,6 +362,30 @@ def main():
     ms_per_step = 1e3 * wall / args.steps
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step")
 
+    # outside the step: the tree route's precision form (FP32 leaf phasors)
+    extra_routes = {}
+    Tx = swv.Tree(max(TREE_LEVELS), W.ra_p, W.dec_p, l, m, f)
+    vx = torch.empty(n_vis, dtype=torch.complex64, device=dev)
+    for prec, key in (("fp64", f"tree_J{max(TREE_LEVELS)}_fp64"),
+                      ("f32c", f"tree_J{max(TREE_LEVELS)}_f32c")):
+        out_x = vx if prec == "f32c" else vt[max(TREE_LEVELS)]
+        Tx.predict(U, V, Wt, prec=prec, out=out_x)
+        times = []
+        for _ in range(max(3, args.steps // 2)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            Tx.predict(U, V, Wt, prec=prec, out=out_x)
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        extra_routes[key] = {"ms": round(ms, 4),
+                             "Gvis_terms_per_s": round(n_vis * n_comp / (ms * 1e-3) / 1e9, 2)}
+    extra_routes["tree_speedup_f32c_over_fp64"] = round(
+        extra_routes[f"tree_J{max(TREE_LEVELS)}_fp64"]["ms"] /
+        extra_routes[f"tree_J{max(TREE_LEVELS)}_f32c"]["ms"], 3)
+    Tx.close()
+
     # per-stage device times (median over steps)
     per = {s: [] for s in stages}
     for ev in all_events:
@@ -437,6 +461,8 @@ def main():
         "routes": routes,
         "roofline": roofline,
         "measured_peaks": {k: round(v, 2) for k, v in peaks.items()},
+        # measured after the timed steps, not part of the step or of value
+        "extra_routes": extra_routes,
         "tile_shapes": {f: {"per_lane": pl, "block": bl} for f, (pl, bl) in tuning.items()},
     }
     if args.copy_calibration:

@@ -171,8 +171,10 @@ int swv_tree_set_flux(swv_tree tree, const double* leaf_flux);
  *     vis_out = A_1 sum_k lambda_1 eta_1 + sum_{j<J} sum_k sum_m gamma^m sigma^m
  * (Eq. 17 with lambda_J a flux density; equal to the direct sum over the
  * pixel-snapped leaves, Eq. 16).  u, v, w [n_vis] DEVICE; vis_out DEVICE
- * complex128 (SWV_FP64 only).  The tree is copied to the device on first use
- * with this context's device.
+ * complex128 (SWV_FP64) or complex64 (SWV_F32C: the leaf phase in FP64,
+ * reduced exactly, then the FP32 hardware sine and cosine; the node
+ * arithmetic stays FP64).  The tree is copied to the device on first use with
+ * this context's device.
  * Two traversals compute the same operations in the same order (bitwise equal
  * results): one keeps a register set per level (J <= 10), the other one per
  * open node with two or more children (any J, up to 15 such nodes on one

@@ -218,18 +218,23 @@ class Tree:
         check(lib().swv_tree_set_flux(self._h, _np_ptr(f)))
 
     def predict(self, u, v, w, sign: int = -1, prec="fp64", out=None):
-        """Model visibilities by the wavelet route (Eqs. 14-17); complex128."""
+        """Model visibilities by the wavelet route (Eqs. 14-17): complex128
+        (prec "fp64") or complex64 ("f32c", FP32 phasors at the leaves)."""
         u = _dev_f64(u, "u")
         dev = u.device
         v, w = _dev_f64(v, "v", dev), _dev_f64(w, "w", dev)
         n = u.numel()
         if v.numel() != n or w.numel() != n:
             raise ValueError("length mismatch")
+        p = _prec(prec)
+        dt = torch.complex128 if p == SWV_FP64 else torch.complex64
         if out is None:
-            out = torch.empty(n, dtype=torch.complex128, device=dev)
+            out = torch.empty(n, dtype=dt, device=dev)
+        elif out.dtype != dt or out.numel() != n or not out.is_contiguous() or out.device != dev:
+            raise ValueError("out has the wrong dtype, size or device")
         ctx = context(dev)
-        check(lib().swv_predict_tree(ctx.handle, self._h, n, _ptr(u), _ptr(v), _ptr(w), sign,
-                                     _prec(prec), _ptr(out)))
+        check(lib().swv_predict_tree(ctx.handle, self._h, n, _ptr(u), _ptr(v), _ptr(w), sign, p,
+                                     _ptr(out)))
         return out
 
     def close(self):

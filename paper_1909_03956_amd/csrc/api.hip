@@ -385,7 +385,7 @@ int swv_predict_tree(swv_ctx ctx, swv_tree t, int64_t n_vis, const double* u, co
     if (!t) return fail(SWV_EINVAL, "swv_predict_tree: null tree");
     if (n_vis < 0) return fail(SWV_EINVAL, "swv_predict_tree: negative n_vis");
     NEED(u, n_vis); NEED(v, n_vis); NEED(w, n_vis); NEED(vis_out, n_vis);
-    int rc = check_sign_prec(sign, prec, false);
+    int rc = check_sign_prec(sign, prec, true);
     if (rc) return rc;
     const int sc = size_class(n_vis);
     const int walker = tree_walker(t, ctx->per_lane[kFamTree][sc]);
@@ -401,8 +401,8 @@ int swv_predict_tree(swv_ctx ctx, swv_tree t, int64_t n_vis, const double* u, co
     rc = upload_tree(ctx, t, &rec);
     if (rc) return rc;
     const TreeArgs a = tree_args(t, rec);
-    HIPCALL(launch_tree(ctx->stream, walker, ctx->block[kFamTree][sc], a, n_vis, u, v, w, sign,
-                        vis_out, ctx->d_status));
+    HIPCALL(launch_tree(ctx->stream, walker, ctx->block[kFamTree][sc], prec, a, n_vis, u, v, w,
+                        sign, vis_out, ctx->d_status));
     return SWV_OK;
     TRY_END
 }

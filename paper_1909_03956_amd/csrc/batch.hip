@@ -492,7 +492,8 @@ int swv_autotune(swv_ctx ctx, const char* cache_path, int flags) {
                             e = launch_direct(s, fam == kFamDirect64 ? SWV_FP64 : SWV_F32C, pl, bl,
                                               rows, u, v, w, comp, n_comp, -1, out, ctx->d_status);
                         } else if (fam == kFamTree) {
-                            e = launch_tree(s, pl == 2 ? 1 : 0, bl, ta, rows, u, v, w, -1, out,
+                            e = launch_tree(s, pl == 2 ? 1 : 0, bl, SWV_FP64, ta, rows, u, v, w,
+                                            -1, out,
                                             ctx->d_status);
                         } else if (fam == kFamAdjoint) {
                             const int64_t tiles = (n_pix + (int64_t)pl * bl - 1) / ((int64_t)pl * bl);

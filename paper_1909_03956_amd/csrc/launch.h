@@ -44,10 +44,11 @@ constexpr int kTreeMaxJ = 10;
 constexpr int kTreeMaxSeg = 16;
 
 // walker 0: level walker (t.J <= kTreeMaxJ); 1: branch walker
-// (t.seg_depth <= kTreeMaxSeg).
-hipError_t launch_tree(hipStream_t s, int walker, int block, const TreeArgs& t, int64_t n_vis,
-                       const double* u, const double* v, const double* w, int sign, void* out,
-                       int* status);
+// (t.seg_depth <= kTreeMaxSeg).  prec SWV_FP64 (complex128 out) or SWV_F32C
+// (FP32 leaf phasors, complex64 out).
+hipError_t launch_tree(hipStream_t s, int walker, int block, int prec, const TreeArgs& t,
+                       int64_t n_vis, const double* u, const double* v, const double* w,
+                       int sign, void* out, int* status);
 
 hipError_t launch_adjoint(hipStream_t s, int prec, int ppl, int block, int64_t chunk,
                           int64_t n_vis, const double* u, const double* v, const double* w,

@@ -138,29 +138,38 @@ __device__ __forceinline__ void close_single(int c, double a, double g0, double 
 }
 
 // Leaf: eta_{J,k} = exp(2 pi i B . (s_k - P)) (imaginary part / 4).  VOP3
-// selects the phasor whose polynomial steps are 3-operand FMAs (same values).
-template <bool VOP3>
+// selects the phasor whose polynomial steps are 3-operand FMAs (same values);
+// F32 the precision form: the FP64 phase, reduced exactly in FP64, then the
+// FP32 hardware sine and cosine (everything after the leaf stays FP64).
+template <bool VOP3, bool F32>
 __device__ __forceinline__ void leaf_wave(RecPtr rec, int me, double u, double v, double w,
                                           double& er, double& ei) {
-    double c, q;
     const double r = reduced_phase(u, v, w, rec[me].a, rec[me].b, rec[me].c);
-    if constexpr (VOP3)
-        cis2pi_q_vop3(r, c, q);
-    else
-        cis2pi_q(r, c, q);
-    er = c;
-    ei = q;
+    if constexpr (F32) {
+        float c32, s32;
+        cis2pi_f32((float)r, c32, s32);
+        er = (double)c32;
+        ei = 0.25 * (double)s32;
+    } else {
+        double c, q;
+        if constexpr (VOP3)
+            cis2pi_q_vop3(r, c, q);
+        else
+            cis2pi_q(r, c, q);
+        er = c;
+        ei = q;
+    }
 }
 
 // Level walker: one register set per level, the level a template parameter
 // (levels <= LDSL keep theirs in LDS).
-template <int LVL, int JMAX, int LDSL, int BLOCK>
+template <int LVL, int JMAX, int LDSL, int BLOCK, bool F32>
 __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const TreeArgs& ta,
                                      LdsPtr lds, const double u, const double v, const double w,
                                      double& er, double& ei, double& Vr, double& Vi) {
     const int me = pos++;
     if (LVL == JMAX || LVL == J) {
-        leaf_wave<true>(rec, me, u, v, w, er, ei);
+        leaf_wave<true, F32>(rec, me, u, v, w, er, ei);
         return;
     }
     if constexpr (LVL < JMAX) {
@@ -171,7 +180,7 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const Tr
             const int c = __builtin_ctz(mask);
             mask &= mask - 1;
             double xr, xi;
-            walk<LVL + 1, JMAX, LDSL, BLOCK>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr, Vi);
+            walk<LVL + 1, JMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr, Vi);
             if constexpr (LVL <= LDSL) {
                 // a fresh value every iteration: nothing of this level stays
                 // in registers while the next child's subtree is walked
@@ -194,7 +203,7 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const Tr
 // walked, and is closed bottom-up afterwards with the same arithmetic a
 // one-child node gets in the level walker.  D counts segments from the root;
 // the host launches DMAX >= 1 + the tree's largest branching count on a path.
-template <int D, int DMAX, int LDSL, int BLOCK>
+template <int D, int DMAX, int LDSL, int BLOCK, bool F32>
 __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, const TreeArgs& ta,
                                          LdsPtr lds, const double u, const double v,
                                          const double w, double& er, double& ei, double& Vr,
@@ -207,7 +216,7 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
     er = 0.0;
     ei = 0.0;
     if (meta_level(mt) == J) {
-        leaf_wave<false>(rec, term, u, v, w, er, ei);
+        leaf_wave<false, F32>(rec, term, u, v, w, er, ei);
     } else {
         if constexpr (D < DMAX) {
             // a terminal node has two or more children: its sums start at zero
@@ -218,8 +227,8 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
                 const int c = __builtin_ctz(mask);
                 mask &= mask - 1;
                 double xr, xi;
-                seg_walk<D + 1, DMAX, LDSL, BLOCK>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr,
-                                                   Vi);
+                seg_walk<D + 1, DMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, u, v, w, xr, xi,
+                                                        Vr, Vi);
                 if constexpr (D <= LDSL) {
                     n = slot_load<BLOCK>(lds, D - 1);
                     add_child(n, c, xr, xi, false);
@@ -252,8 +261,8 @@ constexpr int tree_lds_levels() {
 
 // V (real, imaginary / 4) of one row: the root loop of the traversal.
 // WALKER 0: level walker up to level JMAX; 1: branch walker up to JMAX segments.
-// lds: the block's [LDSL][8][BLOCK] sum slots.
-template <int JMAX, int WALKER, int LDSL, int BLOCK>
+// lds: the block's [LDSL][8][BLOCK] sum slots.  F32: FP32 phasors at the leaves.
+template <int JMAX, int WALKER, int LDSL, int BLOCK, bool F32 = false>
 __device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J,
                                          const TreeArgs& ta, LdsPtr lds, double U, double V,
                                          double W, double& Vr, double& Vi) {
@@ -265,9 +274,9 @@ __device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J,
         const int root = pos++;
         double er, ei;
         if constexpr (WALKER == 0)
-            walk<1, JMAX, LDSL, BLOCK>(rec, pos, J, ta, lds, U, V, W, er, ei, Vr, Vi);
+            walk<1, JMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, U, V, W, er, ei, Vr, Vi);
         else
-            seg_walk<1, JMAX, LDSL, BLOCK>(rec, pos, J, ta, lds, U, V, W, er, ei, Vr, Vi);
+            seg_walk<1, JMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, U, V, W, er, ei, Vr, Vi);
         const double A1lam = rec[root].a;  // A_1 lambda_1
         Vr = fma(A1lam, er, Vr);
         Vi = fma(A1lam, ei, Vi);

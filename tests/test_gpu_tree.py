@@ -250,3 +250,57 @@ def test_sweep_workload_vs_oracle(env, J, n):
     e_max, e_rms = errors(got, ref, f.sum())
     note(f"sweep J={J} N~_C={rt.n_leaves}: E_max={e_max:.3e} E_rms={e_rms:.3e}")
     assert e_max <= TOL64
+
+
+# Precision form of the tree route: FP64 phase reduced exactly, FP32 hardware
+# sine/cosine at the leaves, FP64 node arithmetic.  Per leaf the phasor is off
+# by at most 2 pi 2^-25 (the FP32 rounding of the reduced phase) plus the
+# hardware sincos error (<= 2.5e-7, test_gpu_direct): < 4.4e-7, so
+# |V - V_exact| < 4.4e-7 sum |F|; gate E_max <= 1e-6 as for the direct form.
+TOL32 = 1e-6
+
+
+@pytest.mark.parametrize("J", [8, 9, 10])
+def test_tree_f32c_cfg2_sampled(env, J):
+    torch, swv = env
+    W = configs.CFG2
+    u, v, w = W.track.uvw()
+    l, m, f = W.components()
+    t = swv.Tree(J, W.ra_p, W.dec_p, l, m, f)
+    out = t.predict(dev(u, torch), dev(v, torch), dev(w, torch), prec="f32c")
+    swv.synchronize()
+    assert out.dtype == torch.complex64
+    rows = configs.sample_rows(u.size, 2048, seed=J + 40)
+    got = host(out[torch.as_tensor(rows, device="cuda")]).astype(np.complex128)
+    ref = ot.predict_tree(ot.build_tree(J, W.ra_p, W.dec_p, l, m, f), u[rows], v[rows], w[rows])
+    e_max, e_rms = errors(got, ref, f.sum())
+    note(f"cfg2 tree f32c J={J}: E_max={e_max:.3e} E_rms={e_rms:.3e}")
+    assert e_max <= TOL32
+
+
+def test_tree_f32c_deep_and_walkers(env):
+    torch, swv = env
+    T = configs.SWEEP_TRACK
+    u, v, w = T.uvw()
+    rows = configs.sample_rows(u.size, 1024, seed=3)
+    l, m, f = configs.sweep_components(140)
+    ra, dec = np.radians(T.ra_deg), np.radians(T.dec_deg)
+    U, V, W = (dev(a[rows], torch) for a in (u, v, w))
+    for J in (10, 20):
+        t = swv.Tree(J, ra, dec, l, m, f)
+        a = _with_walker(swv, 1, lambda: t.predict(U, V, W, prec="f32c"))
+        b = _with_walker(swv, 2, lambda: t.predict(U, V, W, prec="f32c"))
+        swv.synchronize()
+        assert torch.equal(a, b)
+        ref = ot.predict_tree(ot.build_tree(J, ra, dec, l, m, f), u[rows], v[rows], w[rows])
+        e_max, _ = errors(host(a).astype(np.complex128), ref, f.sum())
+        note(f"sweep tree f32c J={J}: E_max={e_max:.3e}")
+        assert e_max <= TOL32
+
+
+def test_tree_f32c_out_dtype_checked(env):
+    torch, swv = env
+    t = swv.Tree(6, 0.0, 0.5, [0.01], [0.0], [1.0])
+    x = dev(np.ones(4), torch)
+    with pytest.raises(ValueError):
+        t.predict(x, x, x, prec="f32c", out=torch.empty(4, dtype=torch.complex128, device="cuda"))
