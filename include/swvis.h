@@ -335,9 +335,10 @@ int swv_tune_load(swv_ctx ctx, const char* cache_path);
  * (direct), pixels per lane (adjoint) or components per lane (gradients), in
  * {1, 2, 4}; for the tree it selects the traversal (1: register set per level
  * where J <= 10, else per branching node; 2: always per branching node; see
- * swv_predict_tree).  block is threads per block
- * in {64, 128, 256} (128 for the gradients).  Results do not depend on the shape except for
- * the summation order of the adjoint and gradients. */
+ * swv_predict_tree).  block is threads per block in {64, 128, 256}; the
+ * gradients ignore it and take the narrowest block of 128 .. 1024 threads that
+ * holds every component at per_lane (else 1024).  Results do not depend on the
+ * shape except for the summation order of the adjoint and gradients. */
 int swv_tune_get(swv_ctx ctx, int family, int size_class, int* per_lane, int* block);
 
 /* Sets one entry of the context's tuning table (SWV_EINVAL for a shape that is

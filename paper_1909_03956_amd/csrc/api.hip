@@ -51,7 +51,7 @@ void tune_defaults(swv_ctx ctx) {
     // (per_lane, block) per family, both size classes; see swv_tune_get.  The
     // fastest shapes measured on MI355X for a few thousand components, a
     // thousand pixels and 10^6 - 10^7 rows.
-    const int pl[kFamilies][2] = {{2, 64}, {1, 256}, {1, 64}, {4, 128}, {2, 128}};
+    const int pl[kFamilies][2] = {{2, 64}, {1, 256}, {1, 64}, {4, 128}, {4, 128}};
     for (int f = 0; f < kFamilies; ++f)
         for (int c = 0; c < 2; ++c) {
             ctx->per_lane[f][c] = pl[f][0];
@@ -570,8 +570,10 @@ int swv_grad_direct(swv_ctx ctx, int64_t n_vis, const double* u, const double* v
     Comp* comp = (Comp*)ctx->comp.p;
     HIPCALL(launch_ingest(ctx->stream, n_comp, l, m, flux, comp, ctx->d_status));
     const int cpl = ctx->per_lane[kFamGrad][size_class(n_vis)];
-    const int64_t tiles = (n_comp + 128 * cpl - 1) / (128 * cpl);
-    const int64_t chunk = choose_chunk(n_vis, tiles, ctx->n_cu, grad_blocks_per_cu(cpl));
+    int gblock = 128;
+    int64_t tiles = 1;
+    grad_tiling(cpl, n_comp, &gblock, &tiles);
+    const int64_t chunk = choose_chunk(n_vis, tiles, ctx->n_cu, grad_blocks_per_cu(cpl, gblock));
     const int64_t n_chunks = n_vis > 0 ? (n_vis + chunk - 1) / chunk : 0;
     rc = ensure(ctx, ctx->partial, 32 * (size_t)n_comp * (size_t)(n_chunks > 0 ? n_chunks : 1));
     if (rc) return rc;

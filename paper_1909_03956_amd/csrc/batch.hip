@@ -505,8 +505,11 @@ int swv_autotune(swv_ctx ctx, const char* cache_path, int flags) {
                             e = launch_adjoint(s, SWV_FP64, pl, bl, chunk, rows, u, v, w, y, n_pix,
                                                l, m, nm, -1, part, out);
                         } else {
-                            const int64_t tiles = (n_comp + 128 * pl - 1) / (128 * pl);
-                            const int64_t chunk = choose_chunk(rows, tiles, ctx->n_cu, grad_blocks_per_cu(pl));
+                            int gblock = 128;
+                            int64_t tiles = 1;
+                            grad_tiling(pl, n_comp, &gblock, &tiles);
+                            const int64_t chunk =
+                                choose_chunk(rows, tiles, ctx->n_cu, grad_blocks_per_cu(pl, gblock));
                             const int64_t nch = (rows + chunk - 1) / chunk;
                             rc = ensure(ctx, ctx->partial, 32 * (size_t)n_comp * nch);
                             if (rc) { result = rc; break; }

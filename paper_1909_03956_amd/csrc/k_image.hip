@@ -247,23 +247,31 @@ hipError_t launch_adjoint(hipStream_t s, int prec, int ppl, int block, int64_t c
 //   Zu, Zv, Zw = Im sum {u, v, w} z  (positions: d phi/dl = u - w l / n, ...)
 // conj(y) e = (yr - i yi)(c + i s S) = (yr c + yi s S) + i (yr s S - yi c),
 // S = 4 q; the products 4 s y are formed once per row for all CPL components.
-constexpr int kGradBlock = 128;
+//
+// Rows are staged through LDS in tiles of kGradRowTile: the block loads each
+// tile once with coalesced vector loads and forms 4 s y there, once per row;
+// every wave then reads the rows as LDS broadcasts.  The block is as wide as
+// the component list needs (up to 1024 threads), so that one block covers
+// every component of a chunk and each row is fetched from memory once.
+constexpr int kGradRowTile = 256;
 
-template <int CPL>
-__global__ __launch_bounds__(kGradBlock) void k_grad_partial(
+template <int CPL, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_grad_partial(
     const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
     const double2* __restrict__ y, int64_t n_vis, int64_t chunk, const Comp* __restrict__ comp,
     int64_t n_comp, double sgn, int64_t n_chunks, int64_t tiles, int64_t bid0,
     double* __restrict__ partial) {
+    // one row: u, v, w, yr, yi, 4 s yr, 4 s yi, (pad) -- 64 bytes
+    __shared__ double2 rows[kGradRowTile][4];
     int64_t chunk_id, tile;
     chunk_tile(bid0 + blockIdx.x, tiles, chunk_id, tile);
-    if (chunk_id >= n_chunks) return;   // padding of the last XCD group
-    const int64_t k0 = tile * (kGradBlock * CPL) + threadIdx.x;
+    if (chunk_id >= n_chunks) return;   // padding of the last XCD group (whole block)
+    const int64_t k0 = tile * (BLOCK * CPL) + threadIdx.x;
     double L[CPL], M[CPL], N[CPL];
     double z0[CPL], zu[CPL], zv[CPL], zw[CPL];
 #pragma unroll
     for (int i = 0; i < CPL; ++i) {
-        int64_t k = k0 + (int64_t)i * kGradBlock;
+        int64_t k = k0 + (int64_t)i * BLOCK;
         k = k < n_comp ? k : n_comp - 1;
         L[i] = comp[k].l;
         M[i] = comp[k].m;
@@ -272,33 +280,42 @@ __global__ __launch_bounds__(kGradBlock) void k_grad_partial(
     }
     const int64_t j0 = chunk_id * chunk;
     const int64_t j1 = j0 + chunk < n_vis ? j0 + chunk : n_vis;
-    // wave-uniform trip count, kept in scalar registers
-    const int nrow = __builtin_amdgcn_readfirstlane((int)(j1 - j0));
-    const auto* U = uniform_ptr(u + j0);
-    const auto* V = uniform_ptr(v + j0);
-    const auto* W = uniform_ptr(w + j0);
-    const auto* Y = uniform_ptr(y + j0);
     const double s4 = 4.0 * sgn;
-#pragma unroll 2
-    for (int j = 0; j < nrow; ++j) {
-        const double uj = U[j], vj = V[j], wj = W[j];
-        const double yr = Y[j].x, yi = Y[j].y;
-        const double y4r = s4 * yr, y4i = s4 * yi;
+    for (int64_t t0 = j0; t0 < j1; t0 += kGradRowTile) {
+        const int nt = (int)(j1 - t0 < kGradRowTile ? j1 - t0 : kGradRowTile);
+        __syncthreads();   // the previous tile has been read by every wave
+        for (int r = threadIdx.x; r < nt; r += BLOCK) {
+            const int64_t j = t0 + r;
+            const double2 yj = y[j];
+            rows[r][0] = make_double2(u[j], v[j]);
+            rows[r][1] = make_double2(w[j], yj.x);
+            rows[r][2] = make_double2(yj.y, s4 * yj.x);
+            rows[r][3] = make_double2(s4 * yj.y, 0.0);
+        }
+        __syncthreads();
+        // wave-uniform trip count, kept in scalar registers
+        const int nrow = __builtin_amdgcn_readfirstlane(nt);
+#pragma unroll 1
+        for (int r = 0; r < nrow; ++r) {
+            const double2 a = rows[r][0], b = rows[r][1], c2 = rows[r][2], d = rows[r][3];
+            const double uj = a.x, vj = a.y, wj = b.x;
+            const double yr = b.y, yi = c2.x, y4r = c2.y, y4i = d.x;
 #pragma unroll
-        for (int i = 0; i < CPL; ++i) {
-            double c, q;
-            cis2pi_q(reduced_phase(uj, vj, wj, L[i], M[i], N[i]), c, q);
-            const double zr = fma(q, y4i, yr * c);
-            const double zi = fma(q, y4r, -(yi * c));
-            z0[i] += zr;
-            zu[i] = fma(uj, zi, zu[i]);
-            zv[i] = fma(vj, zi, zv[i]);
-            zw[i] = fma(wj, zi, zw[i]);
+            for (int i = 0; i < CPL; ++i) {
+                double c, q;
+                cis2pi_q(reduced_phase(uj, vj, wj, L[i], M[i], N[i]), c, q);
+                const double zr = fma(q, y4i, yr * c);
+                const double zi = fma(q, y4r, -(yi * c));
+                z0[i] += zr;
+                zu[i] = fma(uj, zi, zu[i]);
+                zv[i] = fma(vj, zi, zv[i]);
+                zw[i] = fma(wj, zi, zw[i]);
+            }
         }
     }
 #pragma unroll
     for (int i = 0; i < CPL; ++i) {
-        const int64_t k = k0 + (int64_t)i * kGradBlock;
+        const int64_t k = k0 + (int64_t)i * BLOCK;
         if (k < n_comp) {
             double* o = partial + (chunk_id * 4) * n_comp + k;
             o[0 * n_comp] = z0[i];
@@ -338,14 +355,26 @@ __global__ __launch_bounds__(kSumCols * kSumQ) void k_grad_finish(
     d_m[k] = f * (zv - (comp[k].m / n) * zw);
 }
 
-template <int CPL>
+template <int CPL, int BLOCK>
 static int grad_occ() {
-    static const int v = resident_blocks(k_grad_partial<CPL>, kGradBlock);
+    static const int v = resident_blocks(k_grad_partial<CPL, BLOCK>, BLOCK);
     return v;
 }
 
-int grad_blocks_per_cu(int cpl) {
-    return cpl == 1 ? grad_occ<1>() : cpl == 2 ? grad_occ<2>() : grad_occ<4>();
+void grad_tiling(int cpl, int64_t n_comp, int* block, int64_t* tiles) {
+    int b = 128;
+    while (b < 1024 && (int64_t)b * cpl < n_comp) b *= 2;
+    *block = b;
+    *tiles = n_comp > 0 ? (n_comp + (int64_t)b * cpl - 1) / ((int64_t)b * cpl) : 1;
+}
+
+int grad_blocks_per_cu(int cpl, int block) {
+#define SWV_OCC_G(C, B) if (cpl == C && block == B) return grad_occ<C, B>();
+    SWV_OCC_G(1, 128) SWV_OCC_G(1, 256) SWV_OCC_G(1, 512) SWV_OCC_G(1, 1024)
+    SWV_OCC_G(2, 128) SWV_OCC_G(2, 256) SWV_OCC_G(2, 512) SWV_OCC_G(2, 1024)
+    SWV_OCC_G(4, 128) SWV_OCC_G(4, 256) SWV_OCC_G(4, 512) SWV_OCC_G(4, 1024)
+#undef SWV_OCC_G
+    return 1;
 }
 
 hipError_t launch_grad(hipStream_t s, int cpl, int64_t chunk, int64_t n_vis, const double* u,
@@ -353,21 +382,23 @@ hipError_t launch_grad(hipStream_t s, int cpl, int64_t chunk, int64_t n_vis, con
                        int64_t n_comp, int sign, double alpha, double* partial, double* d_flux,
                        double* d_l, double* d_m) {
     if (n_comp <= 0) return hipSuccess;
+    if (cpl != 1 && cpl != 2 && cpl != 4) return hipErrorInvalidValue;
     const int64_t n_chunks = n_vis > 0 ? (n_vis + chunk - 1) / chunk : 0;
     if (n_chunks > 0) {
-        const int64_t per_block = (int64_t)kGradBlock * cpl;
-        const int64_t tiles = (n_comp + per_block - 1) / per_block;
+        int block = 128;
+        int64_t tiles = 1;
+        grad_tiling(cpl, n_comp, &block, &tiles);
         const double sg = (double)sign;
         const double2* yy = (const double2*)y;
-        if (cpl != 1 && cpl != 2 && cpl != 4) return hipErrorInvalidValue;
         launch_slabs(xcd_padded(n_chunks) * tiles, [&](int64_t b0, unsigned nb) {
-            const dim3 g(nb), b(kGradBlock);
-            if (cpl == 1)
-                k_grad_partial<1><<<g, b, 0, s>>>(u, v, w, yy, n_vis, chunk, comp, n_comp, sg, n_chunks, tiles, b0, partial);
-            else if (cpl == 2)
-                k_grad_partial<2><<<g, b, 0, s>>>(u, v, w, yy, n_vis, chunk, comp, n_comp, sg, n_chunks, tiles, b0, partial);
-            else
-                k_grad_partial<4><<<g, b, 0, s>>>(u, v, w, yy, n_vis, chunk, comp, n_comp, sg, n_chunks, tiles, b0, partial);
+#define SWV_RUN_G(C, B)                                                                      \
+    if (cpl == C && block == B)                                                              \
+        k_grad_partial<C, B><<<dim3(nb), dim3(B), 0, s>>>(u, v, w, yy, n_vis, chunk, comp, n_comp, \
+                                                          sg, n_chunks, tiles, b0, partial);
+            SWV_RUN_G(1, 128) SWV_RUN_G(1, 256) SWV_RUN_G(1, 512) SWV_RUN_G(1, 1024)
+            SWV_RUN_G(2, 128) SWV_RUN_G(2, 256) SWV_RUN_G(2, 512) SWV_RUN_G(2, 1024)
+            SWV_RUN_G(4, 128) SWV_RUN_G(4, 256) SWV_RUN_G(4, 512) SWV_RUN_G(4, 1024)
+#undef SWV_RUN_G
         });
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

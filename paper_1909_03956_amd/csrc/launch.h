@@ -57,7 +57,10 @@ hipError_t launch_adjoint(hipStream_t s, int prec, int ppl, int block, int64_t c
 
 // Resident blocks per compute unit of the adjoint and gradient kernels.
 int adjoint_blocks_per_cu(int prec, int ppl, int block);
-int grad_blocks_per_cu(int cpl);
+// Gradient kernel block (128 .. 1024 threads, the smallest that holds every
+// component at cpl per lane, else 1024) and the component tiles it leaves.
+void grad_tiling(int cpl, int64_t n_comp, int* block, int64_t* tiles);
+int grad_blocks_per_cu(int cpl, int block);
 
 hipError_t launch_grad(hipStream_t s, int cpl, int64_t chunk, int64_t n_vis, const double* u,
                        const double* v, const double* w, const void* y, const Comp* comp,
