@@ -17,6 +17,9 @@ cfg5  adjoint case: cfg2 tracks and model; a perturbed model plus complex
       level-9 pixels within 4 deg of the phase centre.
 sweep tree-route run-time sweep: a 27-antenna one-hour, one-second track
       (1,263,600 rows), 10-140 distinct components, J = 12-25.
+clean7 the clean loop's wide-field simulation: the same array at 10 MHz for
+      2,016 s (707,616 rows), seven 1 Jy sources, a 256 x 256 image over
+      42 deg 40'; clean_small is its parity case (8,424 rows, 40 x 40 pixels).
 
 The phase centre of every config is at right ascension 12h, the
 declination of its tracks.
@@ -119,6 +122,58 @@ def sweep_components(n_distinct: int, seed: int = SWEEP_SEED_MODEL):
     """n_distinct components uniform over the sweep field, lognormal fluxes."""
     rng = np.random.default_rng(seed + n_distinct)
     return models.uniform_components(n_distinct, SWEEP_FIELD_DEG, rng)
+
+
+# Clean loop (sections 2.2, 3.5, 3.6): the wide-field seven-source simulation.
+# A 27-antenna C-configuration-like array (1.7 km radius), 10 MHz, dec +45 deg,
+# 2,016 s at one-second sampling -> 351 x 2016 = 707,616 rows; seven compact
+# 1 Jy sources uniform within a 30 deg field; complex noise of sigma 0.01 Jy;
+# a 256 x 256 image grid over 42 deg 40'.
+@dataclass(frozen=True)
+class CleanSpec:
+    track: TrackSpec
+    n_pix: int                 # image is n_pix x n_pix
+    fov_deg: float             # full width of the image in direction cosines (small angle)
+    source_field_deg: float
+    J: int
+    gain: float
+    minor_iter: int            # Hogbom iterations per major cycle
+    n_major: int
+    seed_model: int
+    seed_noise: int
+    noise_sigma: float = 0.01
+    n_sources: int = 7
+
+    @property
+    def ra_p(self) -> float:
+        return math.radians(self.track.ra_deg)
+
+    @property
+    def dec_p(self) -> float:
+        return math.radians(self.track.dec_deg)
+
+    @property
+    def cell(self) -> float:
+        return math.radians(self.fov_deg) / self.n_pix
+
+    def sources(self):
+        """(l, m, flux): n_sources 1 Jy sources uniform over source_field_deg."""
+        rng = np.random.default_rng(self.seed_model)
+        l, m, _ = models.uniform_components(self.n_sources, self.source_field_deg, rng)
+        return l, m, np.ones(self.n_sources)
+
+    def noise(self):
+        rng = np.random.default_rng(self.seed_noise)
+        return models.complex_noise(self.track.n_vis, self.noise_sigma, rng)
+
+
+CLEAN7 = CleanSpec(TrackSpec(27, 1.7e3, 45.0, 2016.0, 2016, 1.0e7, seed=701), 256,
+                   42.0 + 40.0 / 60.0, 30.0, J=9, gain=0.1, minor_iter=300, n_major=2,
+                   seed_model=702, seed_noise=703)
+# The same array on a short track and a small grid: the parity case.
+CLEAN_SMALL = CleanSpec(TrackSpec(27, 1.7e3, 45.0, 2016.0, 24, 1.0e7, seed=711), 40,
+                        4.0, 3.0, J=11, gain=0.1, minor_iter=60, n_major=2,
+                        seed_model=712, seed_noise=713)
 
 
 def sample_rows(n_vis: int, n_sample: int, seed: int, tile: int = 256) -> np.ndarray:

@@ -204,3 +204,69 @@ def test_tree_set_flux_recomputes_coefficients(swv):
     assert np.array_equal(t.leaves()["flux"], F2)
     with pytest.raises(ValueError):
         t.set_leaf_flux(F2[:-1])
+
+
+# ------------------------------------------------- clean loop, host side --
+def test_cross_reference_matches_oracle(swv):
+    from oracle import clean as oc
+    import paper_1909_03956_amd as lib
+    S = configs.CLEAN7
+    for n, cell, J in ((S.n_pix, S.cell, S.J), (37, 1e-3, 20), (1, 0.2, 3)):
+        got = lib.cross_reference(J, S.ra_p, S.dec_p, n, n + 3, cell)
+        l, m, _, _ = oc.image_grid(n, n + 3, cell)
+        assert np.array_equal(got, oc.cross_reference(J, S.ra_p, S.dec_p, l, m))
+    with pytest.raises(lib.SwvError, match="SWV_EDOMAIN"):
+        lib.cross_reference(9, S.ra_p, S.dec_p, 64, 64, 0.05)   # corners off the disk
+    with pytest.raises(lib.SwvError, match="SWV_EINVAL"):
+        lib.cross_reference(9, S.ra_p, S.dec_p, 0, 64, 0.001)
+
+
+def test_tree_build_pixels_matches_oracle(swv):
+    from oracle import clean as oc
+    from paper_1909_03956_amd.api import Tree
+    import paper_1909_03956_amd as lib
+    S = configs.CLEAN7
+    rng = np.random.default_rng(31)
+    kJ = lib.cross_reference(S.J, S.ra_p, S.dec_p, S.n_pix, S.n_pix, S.cell)
+    pick = rng.choice(kJ.size, 300)               # with repeats: merged leaves
+    flux = rng.normal(size=300)
+    t = Tree.from_pixels(S.J, S.ra_p, S.dec_p, kJ[pick], flux)
+    ref = oc.tree_from_pixels(S.J, S.ra_p, S.dec_p, kJ[pick], flux)
+    lv = t.leaves()
+    assert np.array_equal(lv["pix"], ref.leaf_pix)
+    np.testing.assert_allclose(lv["flux"], ref.leaf_flux, rtol=1e-14, atol=1e-14)
+    for j in range(1, S.J + 1):
+        got, exp = t.level(j), ref.levels[j - 1]
+        assert np.array_equal(got["pix"], exp.pix)
+        scale = np.abs(exp.lam).max()
+        assert np.max(np.abs(got["lambda"] - exp.lam)) <= 1e-14 * scale
+    with pytest.raises(lib.SwvError, match="SWV_EDOMAIN"):
+        Tree.from_pixels(3, S.ra_p, S.dec_p, [12 * 16], [1.0])   # level 3 has 192 pixels
+
+
+def test_fit_clean_beam_matches_oracle(swv):
+    from oracle import clean as oc
+    import paper_1909_03956_amd as lib
+    dy, dx = np.meshgrid(np.arange(-30, 31), np.arange(-40, 41), indexing="ij")
+    rng = np.random.default_rng(4)
+    for a, b, c in ((0.05, 0.02, 0.09), (0.3, -0.1, 0.2)):
+        beam = np.exp(-(a * dx * dx + 2 * b * dx * dy + c * dy * dy))
+        beam *= 1 + 0.05 * rng.uniform(-1, 1, beam.shape)   # not exactly Gaussian
+        beam[30, 40] = 1.0
+        got = lib.fit_clean_beam(beam)
+        np.testing.assert_allclose(got, oc.fit_clean_beam(beam), rtol=1e-11)
+    # an oracle dirty beam of the small clean workload
+    S = configs.CLEAN_SMALL
+    u, v, w = TrackSpecSmall.uvw()
+    db = oc.dirty_beam(u, v, w, 20, 20, S.cell)
+    np.testing.assert_allclose(lib.fit_clean_beam(db), oc.fit_clean_beam(db), rtol=1e-11)
+    plus = np.zeros((9, 9))
+    plus[4, 4] = 1.0
+    plus[4, 5] = plus[4, 3] = plus[3, 4] = plus[5, 4] = 0.6
+    with pytest.raises(lib.SwvError, match="SWV_EDOMAIN"):
+        lib.fit_clean_beam(plus)
+    with pytest.raises(lib.SwvError, match="SWV_EDOMAIN"):
+        lib.fit_clean_beam(np.zeros((5, 5)))
+
+
+TrackSpecSmall = configs.TrackSpec(27, 1.7e3, 45.0, 2016.0, 4, 1.0e7, seed=731)
