@@ -63,6 +63,8 @@ def parse():
     p.add_argument("--cpu-rows", type=int, default=32768,
                    help="rows of the workload the oracle is timed on")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-clean", action="store_true",
+                   help="skip the clean-loop measurement after the step")
     p.add_argument("--profile", action="store_true",
                    help="short run for a profiler: no CPU baseline")
     p.add_argument("--tune", action="store_true",
@@ -252,6 +254,51 @@ def run_sweep():
         "J20_ms": {str(nc): j20[nc]["ms"] for nc in j20},
         "paper_J20_s_per_major_cycle": {"140": 1000, "15": 146},
     }), flush=True)
+
+
+def run_clean(swv, torch, np, dev, configs):
+    """The wavelet clean loop on the seven-source wide-field workload (outside
+    the step): dirty beam, dirty image, then major cycles of 300 Hogbom
+    iterations, tree prediction and residual image, as per-stage device times."""
+    S = configs.CLEAN7
+
+    def D(x):
+        return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+    u, v, w = S.track.uvw()
+    l, m, f = S.sources()
+    U, V, Wt = D(u), D(v), D(w)
+    vis = swv.predict_direct(U, V, Wt, D(l), D(m), D(f))
+    vis += torch.as_tensor(S.noise(), dtype=torch.complex128, device=dev)
+    n = S.n_pix
+    args = (U, V, Wt, vis, n, n, S.cell, S.J, S.ra_p, S.dec_p, S.gain, 0.0, S.minor_iter,
+            S.n_major)
+    swv.wavelet_clean(*args)          # first call: scratch allocation, code upload
+    t0 = time.perf_counter()
+    out = swv.wavelet_clean(*args)
+    wall = 1e3 * (time.perf_counter() - t0)
+    cyc = out["cycles"]
+    iters = sum(c["found"] for c in cyc)
+    ms_minor = sum(c["ms_minor"] for c in cyc)
+    ms_image = [c["ms_image"] for c in cyc]
+    n_vis = u.size
+    return {
+        "workload": "clean7: 27-antenna 1.7 km array, 10 MHz, dec +45, 2,016 s at 1 s "
+                    "(707,616 vis); seven 1 Jy sources; 256 x 256 image over 42 deg 40'; "
+                    f"J={S.J}; gain {S.gain}; {S.n_major} major cycles of {S.minor_iter} "
+                    "Hogbom iterations",
+        "n_vis": n_vis, "n_pix": n * n, "wall_ms": round(wall, 2),
+        "beam_ms": round(out["ms_beam"], 3), "dirty_image_ms": round(out["ms_dirty"], 3),
+        "cycles": [{k: (round(c[k], 4) if isinstance(c[k], float) else c[k]) for k in c}
+                   for c in cyc],
+        "components": int(out["pix"].size), "flux_found": round(float(out["val"].sum()), 4),
+        "hogbom_us_per_iter": round(1e3 * ms_minor / max(iters, 1), 3),
+        # image read + write and beam read per pixel and iteration
+        "hogbom_GB_per_s": round(24 * n * n * iters / (ms_minor * 1e-3) / 1e9, 1),
+        "residual_image_Gterms_per_s": round(n_vis * n * n / (float(np.median(ms_image)) * 1e-3)
+                                             / 1e9, 1),
+        "beam_Gterms_per_s": round(n_vis * (2 * n - 1) ** 2 / (out["ms_beam"] * 1e-3) / 1e9, 1),
+    }
 
 
 def main():
@@ -465,6 +512,9 @@ def main():
         "extra_routes": extra_routes,
         "tile_shapes": {f: {"per_lane": pl, "block": bl} for f, (pl, bl) in tuning.items()},
     }
+    if not args.no_clean:
+        log("clean loop on the seven-source workload ...")
+        out["clean_loop"] = run_clean(swv, torch, np, dev, configs)
     if args.copy_calibration:
         # an elementwise kernel that reads 1 GiB and writes 1 GiB (a memcpy
         # would run on the copy engine, outside the counters' view)

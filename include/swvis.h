@@ -243,6 +243,124 @@ int swv_grad_direct(swv_ctx ctx, int64_t n_vis, const double* u, const double* v
                     const double* m, const double* flux, int sign, double alpha,
                     double* d_flux, double* d_l, double* d_m);
 
+/* ------------------------------------------------------- clean loop --- */
+/* Cotton-Schwab cleaning with the wavelet predictor (sections 2.1, 2.2, 3.5).
+ * Images are row-major (ny, nx) FP64 grids: pixel p = iy * nx + ix at the
+ * SIN-projected direction l = (ix - cx) cell, m = (iy - cy) cell,
+ * n - 1 = -(l^2 + m^2) / (1 + sqrt(1 - l^2 - m^2)).  An image grid has its
+ * phase centre at (cx, cy) = (nx / 2, ny / 2) (integer division); a beam grid
+ * is (2 ny - 1, 2 nx - 1) pixel offsets with the zero offset at
+ * (nx - 1, ny - 1). */
+
+#define SWV_HOGBOM_ABS 1   /* take the peak of |I| instead of I */
+
+/* Directions of a grid: l, m, nm1 [nx * ny] DEVICE.  cx, cy is the pixel of
+ * the phase centre.  Directions off the unit disk (l^2 + m^2 >= 1) get
+ * l = m = nm1 = 0.  cell > 0 in direction cosines. */
+int swv_image_grid(swv_ctx ctx, int nx, int ny, int cx, int cy, double cell, double* l,
+                   double* m, double* nm1);
+
+/* Dirty image from visibilities (section 2.1, first two steps, as the exact
+ * adjoint of Eq. 12 instead of gridding and an inverse FFT):
+ *     img_out[p] = (1 / n_vis) Re sum_j conj(e_jp) y[j]
+ * on the grid (nx, ny, cx, cy, cell); a unit source on a pixel gives 1 there.
+ * Pixels whose direction is off the unit disk are 0.  y [n_vis] DEVICE
+ * complex128; img_out [nx * ny] DEVICE FP64.  With y = NULL the visibilities
+ * are all 1: on the beam grid (cx = nx' - 1 of an nx' image) that is the
+ * dirty beam B_D, the image of a unit source at the phase centre.  Uses
+ * 40 * nx * ny bytes of device scratch plus the adjoint's workspace. */
+int swv_dirty_image(swv_ctx ctx, int64_t n_vis, const double* u, const double* v,
+                    const double* w, const void* y, int nx, int ny, int cx, int cy,
+                    double cell, int sign, double* img_out);
+
+/* Hogbom minor cycle (section 2.1, Eqs. 4 and 5) on image [ny][nx] (DEVICE,
+ * updated in place to the residual) with beam [2 ny - 1][2 nx - 1] (DEVICE,
+ * zero offset at its centre).  Iteration n takes the peak pixel p_n, the first
+ * in row-major order holding the largest value (largest |value| with
+ * SWV_HOGBOM_ABS), with value C_n; stops if the peak is not above `threshold`
+ * or after max_iter components; else records comp_pix[n] = p_n and
+ * comp_val[n] = gain * C_n and subtracts comp_val[n] * beam shifted to p_n from
+ * every pixel (one product, one subtraction: the result does not depend on
+ * the device).  comp_pix, comp_val [max_iter] DEVICE; *n_found DEVICE
+ * receives the number of components.  Image and beam must be finite.  One
+ * workgroup runs the whole cycle; the call does not synchronise. */
+int swv_hogbom(swv_ctx ctx, int nx, int ny, double* image, const double* beam, double gain,
+               double threshold, int64_t max_iter, int flags, int64_t* comp_pix,
+               double* comp_val, int64_t* n_found);
+
+/* Cross-reference table of an image grid (section 3.5): the level-J nested
+ * sphere pixel of every image pixel's direction (the grid's l, m rotated to
+ * the equatorial frame as in swv_tree_build).  pix [nx * ny] HOST.
+ * SWV_EDOMAIN if a grid direction is off the unit disk. */
+int swv_cross_reference(int J, double ra_p, double dec_p, int nx, int ny, double cell,
+                        int64_t* pix);
+
+/* swv_tree_build from the components' level-J pixel ids (the cross-referenced
+ * form of section 3.5): pix [n] HOST in [0, 12 * 4^(J-1)), flux [n] HOST. */
+int swv_tree_build_pixels(int J, double ra_p, double dec_p, int64_t n, const int64_t* pix,
+                          const double* flux, swv_tree* out);
+
+/* Clean beam B_C (section 2.1, third step): the rotated 2-D Gaussian
+ *     B_C(dx, dy) = exp(-(a dx^2 + 2 b dx dy + c dy^2)),  offsets in pixels,
+ * whose logarithm is the least-squares fit of ln B_D over the main lobe: the
+ * 8-connected region of beam >= 1/2 around the centre.  beam [nby][nbx] HOST
+ * with its zero offset at (nbx / 2, nby / 2); abc[3] HOST receives (a, b, c).
+ * SWV_EDOMAIN if the centre is below 1/2, the lobe does not determine the
+ * three parameters or the fit is not a peaked Gaussian. */
+int swv_fit_clean_beam(int nbx, int nby, const double* beam, double* abc);
+
+/* Clean image (Eq. 6): out[p] = sum_i comp_val[i] B_C(p - comp_pix[i]), the
+ * terms added in list order, plus residual[p] if residual is not NULL.
+ * comp_pix, comp_val [n_comp] DEVICE; residual, out [nx * ny] DEVICE;
+ * abc HOST as from swv_fit_clean_beam. */
+int swv_restore(swv_ctx ctx, int nx, int ny, int64_t n_comp, const int64_t* comp_pix,
+                const double* comp_val, const double* abc, const double* residual, double* out);
+
+typedef struct {
+    int nx, ny;           /* image grid, phase centre at (nx / 2, ny / 2) */
+    double cell;          /* pixel size in direction cosines */
+    int J;                /* wavelet resolution of the model */
+    double ra_p, dec_p;   /* phase centre, radians */
+    double gain;          /* Hogbom loop gain g */
+    double threshold;     /* minor cycles stop at a peak not above this */
+    int64_t minor_iter;   /* Hogbom iterations per major cycle */
+    int n_major;          /* major cycles */
+    int flags;            /* SWV_HOGBOM_ABS */
+    int sign;             /* phase sign of Eq. 12, +1 or -1 */
+} swv_clean_params_t;
+
+#define SWV_CLEAN_MAX_CYCLES 64
+
+typedef struct {
+    int n_cycles;                            /* major cycles run */
+    int64_t found[SWV_CLEAN_MAX_CYCLES];     /* components found per cycle */
+    int64_t leaves[SWV_CLEAN_MAX_CYCLES];    /* distinct level-J pixels after it */
+    double chi2[SWV_CLEAN_MAX_CYCLES];       /* sum |V - V_model|^2 after it */
+    double ms_minor[SWV_CLEAN_MAX_CYCLES];   /* Hogbom kernel */
+    double ms_build[SWV_CLEAN_MAX_CYCLES];   /* host tree build */
+    double ms_predict[SWV_CLEAN_MAX_CYCLES]; /* tree prediction */
+    double ms_image[SWV_CLEAN_MAX_CYCLES];   /* subtract + residual image */
+    double ms_beam, ms_dirty;                /* dirty beam, first dirty image */
+} swv_clean_stats_t;
+
+/* The whole wavelet clean (sections 2.2 and 3.5): the dirty beam and the
+ * cross-reference table once, the dirty image, then per major cycle up to
+ * minor_iter Hogbom iterations, the tree of every component found so far
+ * (swv_tree_build_pixels on the cross-referenced pixels), the model
+ * visibilities by the tree route (FP64), the residual visibilities and the new
+ * residual image.  Stops after n_major cycles (<= SWV_CLEAN_MAX_CYCLES) or
+ * when a minor cycle finds nothing.
+ * u, v, w, vis_obs [n_vis] DEVICE (vis_obs complex128).  Outputs: beam
+ * [(2 ny - 1)(2 nx - 1)] DEVICE, residual [nx * ny] DEVICE, vis_model [n_vis]
+ * DEVICE complex128, comp_pix / comp_val [cap] HOST (all components in the
+ * order found; cap >= minor_iter * n_major), *n_comp HOST, stats HOST (may be
+ * NULL).  Allocates its scratch for the call and synchronises the stream. */
+int swv_wavelet_clean(swv_ctx ctx, const swv_clean_params_t* params, int64_t n_vis,
+                      const double* u, const double* v, const double* w, const void* vis_obs,
+                      double* beam, double* residual, void* vis_model, int64_t cap,
+                      int64_t* comp_pix, double* comp_val, int64_t* n_comp,
+                      swv_clean_stats_t* stats);
+
 /* ------------------------------------------------------------ batched --- */
 
 /* One prediction instance (a channel x pointing), all pointers DEVICE except

@@ -10,6 +10,8 @@ SWV_OK, SWV_EINVAL, SWV_EDOMAIN, SWV_ENOMEM, SWV_EHIP, SWV_ENOTSUP = 0, -1, -2, 
 SWV_FP64, SWV_F32C = 0, 1
 SWV_ROUTE_DIRECT, SWV_ROUTE_TREE = 0, 1
 SWV_MAX_LEVEL = 29
+SWV_HOGBOM_ABS = 1
+SWV_CLEAN_MAX_CYCLES = 64
 # kernel families of the tuning table (swv_tune_get / swv_tune_set)
 FAM_DIRECT64, FAM_DIRECT32, FAM_TREE, FAM_ADJOINT, FAM_GRAD = 0, 1, 2, 3, 4
 STATUS_NAMES = {0: "SWV_OK", -1: "SWV_EINVAL", -2: "SWV_EDOMAIN", -3: "SWV_ENOMEM",
@@ -50,6 +52,24 @@ class Instance(C.Structure):
                 ("flux", C.c_void_p), ("tree", C.c_void_p), ("vis_out", C.c_void_p)]
 
 
+class CleanParams(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("cell", C.c_double), ("J", C.c_int),
+                ("ra_p", C.c_double), ("dec_p", C.c_double), ("gain", C.c_double),
+                ("threshold", C.c_double), ("minor_iter", C.c_int64), ("n_major", C.c_int),
+                ("flags", C.c_int), ("sign", C.c_int)]
+
+
+_NC = SWV_CLEAN_MAX_CYCLES
+
+
+class CleanStats(C.Structure):
+    _fields_ = [("n_cycles", C.c_int), ("found", C.c_int64 * _NC), ("leaves", C.c_int64 * _NC),
+                ("chi2", C.c_double * _NC), ("ms_minor", C.c_double * _NC),
+                ("ms_build", C.c_double * _NC), ("ms_predict", C.c_double * _NC),
+                ("ms_image", C.c_double * _NC), ("ms_beam", C.c_double),
+                ("ms_dirty", C.c_double)]
+
+
 _vp, _i64, _int, _dbl = C.c_void_p, C.c_int64, C.c_int, C.c_double
 _pvp = C.POINTER(C.c_void_p)
 
@@ -86,6 +106,15 @@ SIGNATURES = {
     "swv_tune_get": [_vp, _int, _int, C.POINTER(C.c_int), C.POINTER(C.c_int)],
     "swv_tune_set": [_vp, _int, _int, _int, _int],
     "swv_measure_peaks": [_vp, _vp],
+    "swv_image_grid": [_vp, _int, _int, _int, _int, _dbl, _vp, _vp, _vp],
+    "swv_dirty_image": [_vp, _i64, _vp, _vp, _vp, _vp, _int, _int, _int, _int, _dbl, _int, _vp],
+    "swv_hogbom": [_vp, _int, _int, _vp, _vp, _dbl, _dbl, _i64, _int, _vp, _vp, _vp],
+    "swv_cross_reference": [_int, _dbl, _dbl, _int, _int, _dbl, _vp],
+    "swv_tree_build_pixels": [_int, _dbl, _dbl, _i64, _vp, _vp, _pvp],
+    "swv_fit_clean_beam": [_int, _int, _vp, _vp],
+    "swv_restore": [_vp, _int, _int, _i64, _vp, _vp, _vp, _vp, _vp],
+    "swv_wavelet_clean": [_vp, C.POINTER(CleanParams), _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                          _i64, _vp, _vp, C.POINTER(_i64), C.POINTER(CleanStats)],
 }
 
 _lib = None

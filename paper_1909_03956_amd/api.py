@@ -8,8 +8,8 @@ import ctypes as C
 import numpy as np
 import torch
 
-from ._lib import (SWV_F32C, SWV_FP64, Instance, PlanStats, TreeStats,
-                   check, lib)
+from ._lib import (SWV_F32C, SWV_FP64, SWV_HOGBOM_ABS, CleanParams, CleanStats, Instance,
+                   PlanStats, TreeStats, check, lib)
 
 PRECISIONS = {"fp64": SWV_FP64, "f32c": SWV_F32C}
 
@@ -180,6 +180,21 @@ class Tree:
                                    _np_ptr(m), _np_ptr(flux), C.byref(self._h)))
         self.J, self.ra_p, self.dec_p = int(J), float(ra_p), float(dec_p)
 
+    @classmethod
+    def from_pixels(cls, J: int, ra_p: float, dec_p: float, pix, flux):
+        """The tree of components given by their level-J pixel ids (the
+        cross-referenced form of section 3.5)."""
+        pix = np.ascontiguousarray(np.asarray(pix, dtype=np.int64))
+        flux = _host_f64(flux)
+        if pix.shape != flux.shape or pix.ndim != 1:
+            raise ValueError("pix, flux must be 1-D of one length")
+        t = cls.__new__(cls)
+        t._h = C.c_void_p()
+        check(lib().swv_tree_build_pixels(int(J), float(ra_p), float(dec_p), pix.size,
+                                          _np_ptr(pix), _np_ptr(flux), C.byref(t._h)))
+        t.J, t.ra_p, t.dec_p = int(J), float(ra_p), float(dec_p)
+        return t
+
     @property
     def handle(self):
         return self._h
@@ -336,6 +351,164 @@ def grad_direct(u, v, w, y, l, m, flux, sign: int = -1, alpha: float = 1.0):
 
 # --------------------------------------------------------------- batched --
 ROUTES = {"direct": 0, "tree": 1}
+
+
+# ----------------------------------------------------------------- clean --
+def _dev(device):
+    if device is None:
+        return torch.device("cuda", torch.cuda.current_device())
+    return torch.device(device)
+
+
+def _uvw(u, v, w):
+    u = _dev_f64(u, "u")
+    dev = u.device
+    v, w = _dev_f64(v, "v", dev), _dev_f64(w, "w", dev)
+    if v.numel() != u.numel() or w.numel() != u.numel():
+        raise ValueError("length mismatch")
+    return u, v, w, dev
+
+
+def _image(t, name, shape, device):
+    if not isinstance(t, torch.Tensor) or t.device != device or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 tensor on {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def image_grid(nx: int, ny: int, cell: float, cx=None, cy=None, device=None):
+    """Directions (l, m, n - 1) of the pixels of an (ny, nx) grid, phase centre
+    at pixel (cx, cy) (default (nx // 2, ny // 2)); 1-D float64 tensors."""
+    dev = _dev(device)
+    n = int(nx) * int(ny)
+    l, m, nm1 = (torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
+    cx = int(nx) // 2 if cx is None else int(cx)
+    cy = int(ny) // 2 if cy is None else int(cy)
+    check(lib().swv_image_grid(context(dev).handle, int(nx), int(ny), cx, cy, float(cell),
+                               _ptr(l), _ptr(m), _ptr(nm1)))
+    return l, m, nm1
+
+
+def dirty_image(u, v, w, y, nx: int, ny: int, cell: float, cx=None, cy=None, sign: int = -1):
+    """(1 / N_vis) Re sum_j conj(e_jp) y_j on an (ny, nx) grid; y None means
+    unit visibilities.  Returns a (ny, nx) float64 tensor."""
+    u, v, w, dev = _uvw(u, v, w)
+    yp = C.c_void_p(0)
+    if y is not None:
+        y = _dev_c128(y, "y", dev)
+        if y.numel() != u.numel():
+            raise ValueError("length mismatch")
+        yp = _ptr(y)
+    cx = int(nx) // 2 if cx is None else int(cx)
+    cy = int(ny) // 2 if cy is None else int(cy)
+    out = torch.empty((int(ny), int(nx)), dtype=torch.float64, device=dev)
+    check(lib().swv_dirty_image(context(dev).handle, u.numel(), _ptr(u), _ptr(v), _ptr(w), yp,
+                                int(nx), int(ny), cx, cy, float(cell), int(sign), _ptr(out)))
+    return out
+
+
+def dirty_beam(u, v, w, nx: int, ny: int, cell: float, sign: int = -1):
+    """Dirty beam of an (ny, nx) image: the (2 ny - 1, 2 nx - 1) image of a
+    unit source at the phase centre, zero offset at (ny - 1, nx - 1)."""
+    return dirty_image(u, v, w, None, 2 * int(nx) - 1, 2 * int(ny) - 1, cell, int(nx) - 1,
+                       int(ny) - 1, sign)
+
+
+def hogbom(image, beam, gain: float, threshold: float, max_iter: int, absolute=False):
+    """Hogbom minor cycle (Eqs. 4, 5) on a (ny, nx) float64 image, updated in
+    place to the residual.  Returns (pixel ids, component values g C_n) as
+    device tensors; waits for the kernel to learn their number."""
+    if not isinstance(image, torch.Tensor) or image.dim() != 2:
+        raise ValueError("image must be a 2-D tensor")
+    dev = image.device
+    ny, nx = image.shape
+    _image(image, "image", (ny, nx), dev)
+    _image(beam, "beam", (2 * ny - 1, 2 * nx - 1), dev)
+    k = int(max_iter)
+    pix = torch.empty(max(k, 1), dtype=torch.int64, device=dev)
+    val = torch.empty(max(k, 1), dtype=torch.float64, device=dev)
+    n = torch.zeros(1, dtype=torch.int64, device=dev)
+    check(lib().swv_hogbom(context(dev).handle, nx, ny, _ptr(image), _ptr(beam), float(gain),
+                           float(threshold), k, SWV_HOGBOM_ABS if absolute else 0, _ptr(pix),
+                           _ptr(val), _ptr(n)))
+    found = int(n.item())
+    return pix[:found], val[:found]
+
+
+def cross_reference(J: int, ra_p: float, dec_p: float, nx: int, ny: int, cell: float):
+    """Level-J sphere pixel of every image pixel (section 3.5): int64 numpy [ny * nx]."""
+    out = np.empty(int(nx) * int(ny), np.int64)
+    check(lib().swv_cross_reference(int(J), float(ra_p), float(dec_p), int(nx), int(ny),
+                                    float(cell), _np_ptr(out)))
+    return out
+
+
+def fit_clean_beam(beam):
+    """(a, b, c) of the clean beam exp(-(a dx^2 + 2 b dx dy + c dy^2)) fitted to
+    the main lobe of a dirty beam (2-D, zero offset at its centre)."""
+    if isinstance(beam, torch.Tensor):
+        beam = beam.detach().cpu().numpy()
+    b = np.ascontiguousarray(np.asarray(beam, dtype=np.float64))
+    if b.ndim != 2:
+        raise ValueError("beam must be 2-D")
+    abc = np.empty(3)
+    check(lib().swv_fit_clean_beam(b.shape[1], b.shape[0], _np_ptr(b), _np_ptr(abc)))
+    return tuple(float(x) for x in abc)
+
+
+def restore(nx: int, ny: int, pix, val, abc, residual=None):
+    """Clean image of Eq. 6 (plus the residual image if given): (ny, nx) float64."""
+    if not isinstance(pix, torch.Tensor) or pix.dtype != torch.int64 or pix.dim() != 1:
+        raise TypeError("pix must be a 1-D int64 tensor")
+    dev = pix.device
+    pix = pix.contiguous()
+    val = _dev_f64(val, "val", dev)
+    if val.numel() != pix.numel():
+        raise ValueError("pix and val differ in length")
+    if residual is not None:
+        residual = _image(residual, "residual", (int(ny), int(nx)), dev)
+    out = torch.empty((int(ny), int(nx)), dtype=torch.float64, device=dev)
+    a = np.asarray(abc, dtype=np.float64)
+    check(lib().swv_restore(context(dev).handle, int(nx), int(ny), pix.numel(), _ptr(pix),
+                            _ptr(val), _np_ptr(a), _ptr(residual), _ptr(out)))
+    return out
+
+
+def wavelet_clean(u, v, w, vis_obs, nx: int, ny: int, cell: float, J: int, ra_p: float,
+                  dec_p: float, gain: float = 0.1, threshold: float = 0.0, minor_iter: int = 100,
+                  n_major: int = 1, absolute=False, sign: int = -1):
+    """Cotton-Schwab cleaning with the wavelet predictor (sections 2.2, 3.5).
+    Returns a dict: pix, val (numpy, all components in order), residual and
+    beam (device images), vis_model (device complex128) and per-cycle stats."""
+    u, v, w, dev = _uvw(u, v, w)
+    vis_obs = _dev_c128(vis_obs, "vis_obs", dev)
+    n = u.numel()
+    if vis_obs.numel() != n:
+        raise ValueError("length mismatch")
+    P = CleanParams(int(nx), int(ny), float(cell), int(J), float(ra_p), float(dec_p),
+                    float(gain), float(threshold), int(minor_iter), int(n_major),
+                    SWV_HOGBOM_ABS if absolute else 0, int(sign))
+    beam = torch.empty((2 * int(ny) - 1, 2 * int(nx) - 1), dtype=torch.float64, device=dev)
+    resid = torch.empty((int(ny), int(nx)), dtype=torch.float64, device=dev)
+    vm = torch.empty(n, dtype=torch.complex128, device=dev)
+    cap = max(int(minor_iter) * int(n_major), 1)
+    pix = np.empty(cap, np.int64)
+    val = np.empty(cap)
+    nc = C.c_int64(0)
+    st = CleanStats()
+    check(lib().swv_wavelet_clean(context(dev).handle, C.byref(P), n, _ptr(u), _ptr(v), _ptr(w),
+                                  _ptr(vis_obs), _ptr(beam), _ptr(resid), _ptr(vm), cap,
+                                  _np_ptr(pix), _np_ptr(val), C.byref(nc), C.byref(st)))
+    k = st.n_cycles
+    cycles = [{"found": st.found[i], "leaves": st.leaves[i], "chi2": st.chi2[i],
+               "ms_minor": st.ms_minor[i], "ms_build": st.ms_build[i],
+               "ms_predict": st.ms_predict[i], "ms_image": st.ms_image[i]} for i in range(k)]
+    return {"pix": pix[:nc.value].copy(), "val": val[:nc.value].copy(), "residual": resid,
+            "beam": beam, "vis_model": vm, "cycles": cycles, "ms_beam": st.ms_beam,
+            "ms_dirty": st.ms_dirty}
 
 
 class Graph:

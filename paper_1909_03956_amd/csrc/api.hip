@@ -137,7 +137,7 @@ void ctx_release(swv_ctx ctx) {
     {
         DeviceGuard g(ctx->device);
         (void)hipStreamSynchronize(ctx->stream);
-        for (DevBuf* b : {&ctx->comp, &ctx->partial, &ctx->partial2})
+        for (DevBuf* b : {&ctx->comp, &ctx->partial, &ctx->partial2, &ctx->grid, &ctx->ones})
             if (b->p) (void)hipFree(b->p);
         if (ctx->d_status) (void)hipFree(ctx->d_status);
     }

@@ -31,6 +31,8 @@ struct swv_ctx_s {
     swv::DevBuf comp;       // packed components
     swv::DevBuf partial;    // per-chunk partial sums (adjoint, gradients)
     swv::DevBuf partial2;   // per-block chi^2 partials
+    swv::DevBuf grid;       // image-grid directions and adjoint output (dirty images)
+    swv::DevBuf ones;       // unit visibilities (dirty beam)
     int* d_status = nullptr;  // deferred-error bits raised by kernels
     int n_cu = 256;
     int per_lane[swv::kFamilies][2];

@@ -119,18 +119,10 @@ void build_coefficients(swv_tree_s* t) {
     }
 }
 
-int build_tree(int J, double ra_p, double dec_p, int64_t n, const double* l, const double* m,
-               const double* flux, swv_tree_s* t) {
+int build_tree_pixels(int J, double ra_p, double dec_p, int64_t n, const int64_t* kJ,
+                      const double* flux, swv_tree_s* t) {
     const auto t0 = std::chrono::steady_clock::now();
     const Frame F = make_frame(ra_p, dec_p);
-
-    // pixel of every component
-    std::vector<int64_t> kJ(n);
-    for (int64_t i = 0; i < n; ++i) {
-        ld xyz[3];
-        lm_to_xyz(F, l[i], m[i], xyz);
-        kJ[i] = ang2pix(J, xyz);
-    }
     std::vector<int64_t> order(n);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
@@ -164,6 +156,23 @@ int build_tree(int J, double ra_p, double dec_p, int64_t n, const double* l, con
     t->build_seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return SWV_OK;
+}
+
+int build_tree(int J, double ra_p, double dec_p, int64_t n, const double* l, const double* m,
+               const double* flux, swv_tree_s* t) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const Frame F = make_frame(ra_p, dec_p);
+    // pixel of every component
+    std::vector<int64_t> kJ(n);
+    for (int64_t i = 0; i < n; ++i) {
+        ld xyz[3];
+        lm_to_xyz(F, l[i], m[i], xyz);
+        kJ[i] = ang2pix(J, xyz);
+    }
+    const int rc = build_tree_pixels(J, ra_p, dec_p, n, kJ.data(), flux, t);
+    t->build_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
 }
 
 }  // namespace swv

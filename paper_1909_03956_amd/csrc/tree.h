@@ -49,4 +49,8 @@ void build_coefficients(swv_tree_s* t);
 int build_tree(int J, double ra_p, double dec_p, int64_t n, const double* l, const double* m,
                const double* flux, swv_tree_s* out);
 
+// The same from the components' level-J pixel ids (the cross-referenced form).
+int build_tree_pixels(int J, double ra_p, double dec_p, int64_t n, const int64_t* kJ,
+                      const double* flux, swv_tree_s* out);
+
 }  // namespace swv
