@@ -2,7 +2,8 @@
  * swvis.h -- C ABI of libswvis.so: model-visibility prediction on MI355X
  * (gfx950) by the direct component sum and by the spherical-Haar-wavelet
  * tree of Skipper, Scaife & McEwen (2019), plus the exact adjoint and the
- * chi^2 gradients of the direct sum.
+ * chi^2 gradients of the direct sum, and the wavelet clean loop around them
+ * (Hogbom minor cycles, major cycles with the tree predictor).
  *
  * Notation.  A visibility row j has baseline B_j = (u_j, v_j, w_j) in
  * wavelengths; a component k has direction cosines (l_k, m_k), n_k =
