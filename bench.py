@@ -65,6 +65,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-clean", action="store_true",
                    help="skip the clean-loop measurement after the step")
+    p.add_argument("--clean-only", action="store_true",
+                   help="run only the clean loop on the seven-source workload (two calls) "
+                        "and print its JSON block")
     p.add_argument("--profile", action="store_true",
                    help="short run for a profiler: no CPU baseline")
     p.add_argument("--tune", action="store_true",
@@ -322,6 +325,9 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.clean_only:
+        print(json.dumps({"clean_loop": run_clean(swv, torch, np, dev, configs)}), flush=True)
+        return
     W = configs.CFG2
     t_in = time.perf_counter()
     u, v, w = W.track.uvw()
@@ -512,7 +518,7 @@ def main():
         "extra_routes": extra_routes,
         "tile_shapes": {f: {"per_lane": pl, "block": bl} for f, (pl, bl) in tuning.items()},
     }
-    if not args.no_clean:
+    if not (args.no_clean or args.profile):
         log("clean loop on the seven-source workload ...")
         out["clean_loop"] = run_clean(swv, torch, np, dev, configs)
     if args.copy_calibration:
