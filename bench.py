@@ -67,7 +67,7 @@ def parse():
                    help="skip the clean-loop measurement after the step")
     p.add_argument("--clean-only", action="store_true",
                    help="run only the clean loop on the seven-source workload (two calls) "
-                        "and print its JSON block")
+                        "and the predictor comparison, and print their JSON blocks")
     p.add_argument("--profile", action="store_true",
                    help="short run for a profiler: no CPU baseline")
     p.add_argument("--tune", action="store_true",
@@ -304,6 +304,67 @@ def run_clean(swv, torch, np, dev, configs):
     }
 
 
+def run_compare(swv, torch, np, dev, configs):
+    """Accuracy against speed of the predictors on the clean7 track and grid
+    (outside the step): 140 components on image pixels; the direct sum over
+    them is the reference; the tree route at several J (error = the snapping
+    of components to level-J pixel centres) and the FFT + degridding predictor
+    at several kernel widths W (error = the kernel's aliasing)."""
+    S = configs.CLEAN7
+
+    def D(x):
+        return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+    u, v, w = S.track.uvw()
+    U, V, Wt = D(u), D(v), D(w)
+    n = S.n_pix
+    pix, flux = configs.clean7_grid_model()
+    gl, gm, gn = (t.cpu().numpy() for t in swv.image_grid(n, n, S.cell, device=dev))
+    l, m = gl[pix], gm[pix]
+    img = np.zeros(n * n)
+    img[pix] = flux
+    IMG = D(img.reshape(n, n))
+    scale = float(np.abs(flux).sum())
+
+    def timed(fn, reps=3):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    ref = torch.empty(u.size, dtype=torch.complex128, device=dev)
+    L, M, F = D(l), D(m), D(flux)
+    ms_direct = timed(lambda: swv.predict_direct(U, V, Wt, L, M, F, out=ref))
+    out = {"workload": f"clean7 track (707,616 vis) and 256 x 256 grid; {pix.size} components "
+                       "on image pixels within 30 deg; reference: the direct sum",
+           "direct": {"ms": round(ms_direct, 4)}}
+    buf = torch.empty_like(ref)
+    for J in (11, 16, 20, 25):
+        T = swv.Tree(J, S.ra_p, S.dec_p, l, m, flux)
+        ms = timed(lambda: T.predict(U, V, Wt, out=buf))
+        err = float((buf - ref).abs().max()) / scale
+        out[f"tree_J{J}"] = {"ms": round(ms, 4), "E_max": float(f"{err:.3e}"),
+                             "leaves": T.stats()["n_leaves"]}
+        T.close()
+    for W in (6, 10, 14):
+        st = {}
+
+        def call():
+            _, s2 = swv.predict_degrid(IMG, U, V, Wt, S.cell, W, out=buf)
+            st.update(s2)
+        ms = timed(call)
+        err = float((buf - ref).abs().max()) / scale
+        out[f"degrid_W{W}"] = {"ms": round(ms, 4), "E_max": float(f"{err:.3e}"),
+                               "w_planes": st["n_planes"]}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -326,7 +387,9 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     if args.clean_only:
-        print(json.dumps({"clean_loop": run_clean(swv, torch, np, dev, configs)}), flush=True)
+        print(json.dumps({"clean_loop": run_clean(swv, torch, np, dev, configs),
+                          "predictor_comparison": run_compare(swv, torch, np, dev, configs)}),
+              flush=True)
         return
     W = configs.CFG2
     t_in = time.perf_counter()
@@ -521,6 +584,8 @@ def main():
     if not (args.no_clean or args.profile):
         log("clean loop on the seven-source workload ...")
         out["clean_loop"] = run_clean(swv, torch, np, dev, configs)
+        log("predictor comparison on the clean7 track ...")
+        out["predictor_comparison"] = run_compare(swv, torch, np, dev, configs)
     if args.copy_calibration:
         # an elementwise kernel that reads 1 GiB and writes 1 GiB (a memcpy
         # would run on the copy engine, outside the counters' view)

@@ -362,6 +362,44 @@ int swv_wavelet_clean(swv_ctx ctx, const swv_clean_params_t* params, int64_t n_v
                       int64_t* comp_pix, double* comp_val, int64_t* n_comp,
                       swv_clean_stats_t* stats);
 
+/* ------------------------------------------- degridding comparator --- */
+
+typedef struct {
+    int64_t n_planes;     /* w planes */
+    int grid_nx, grid_ny; /* padded uv grid (2 nx, 2 ny) */
+    double w0, dw;        /* w of plane 0, plane spacing (wavelengths) */
+    double c;             /* the centre of the image's n - 1 range */
+    int64_t plane_bytes;  /* device memory of the planes */
+    double host_ms;       /* wall time of the call up to the last launch */
+} swv_degrid_stats_t;
+
+/* The conventional predictor that section 2.2's major cycle uses and the
+ * wavelet route replaces: a forward FFT of the model image and degridding
+ * with an anti-aliasing kernel, plus a correction for the w-term.  Written as
+ * a type-2 non-uniform FFT in (u, v, w) with the exponential-of-semicircle
+ * kernel phi(z) = exp(beta (sqrt(1 - z^2) - 1)), beta = 2.3 W, over W cells in
+ * each of u, v and w (Barnett, Magland & af Klinteberg 2019; w planes
+ * interpolated as in the improved w-stacking of Ye et al. 2021):
+ *   uv grid 2 nx x 2 ny cells of 1 / (2 nx cell) wavelengths; w planes
+ *   dw = 1 / (2 E) apart, E the extent of n - 1 over the image and c its
+ *   midpoint, from w_0 = min w - (W / 2) dw;
+ *   plane q = FFT of the padded image I_p exp(s 2 pi i w_q (n_p - 1 - c))
+ *   divided by the kernel's Fourier transform in l, m and (n - 1 - c) dw
+ *   (100-node Gauss-Legendre quadrature in theta, x = (W / 2) sin theta);
+ *   V_j = exp(s 2 pi i w_j c) sum over the W (or W + 1) nearest planes, rows
+ *   and columns of kernel weight x plane value.
+ * V_j approximates sum_p image[p] e^{s 2 pi i (u l_p + v m_p + w (n_p - 1))}
+ * over the image grid of swv_image_grid (phase centre (nx / 2, ny / 2)) to
+ * about 10^(1 - W) of sum |image|.  image [ny][nx] DEVICE FP64; u, v, w
+ * [n_vis] DEVICE; vis_out [n_vis] DEVICE complex128 (NaN for a row with
+ * non-finite coordinates); support W in 2 .. 16; stats HOST or NULL.
+ * Synchronises once (for the w range); uses a context workspace of
+ * 16 n_planes (4 nx ny) bytes plus the image, and a cached FFT plan.
+ * SWV_ENOMEM if the planes would exceed 64 GiB. */
+int swv_predict_degrid(swv_ctx ctx, int nx, int ny, double cell, const double* image,
+                       int64_t n_vis, const double* u, const double* v, const double* w,
+                       int support, int sign, void* vis_out, swv_degrid_stats_t* stats);
+
 /* ------------------------------------------------------------ batched --- */
 
 /* One prediction instance (a channel x pointing), all pointers DEVICE except

@@ -7,7 +7,8 @@ library; the library must be built (build.py) -- there is no CPU fallback.
 from ._lib import SwvError, lib  # noqa: F401
 from .api import (BatchPlan, Context, Graph, Tree, adjoint, ang2pix, context,  # noqa: F401
                   cross_reference, dirty_beam, dirty_image, fit_clean_beam, grad_direct, hogbom,
-                  image_grid, pixel_centres, pixels_in_disk, predict_direct, residual_chi2,
+                  image_grid, pixel_centres, pixels_in_disk, predict_degrid, predict_direct,
+                  residual_chi2,
                   restore, synchronize, wavelet_clean)
 
 from . import autograd  # noqa: F401,E402

@@ -70,6 +70,12 @@ class CleanStats(C.Structure):
                 ("ms_dirty", C.c_double)]
 
 
+class DegridStats(C.Structure):
+    _fields_ = [("n_planes", C.c_int64), ("grid_nx", C.c_int), ("grid_ny", C.c_int),
+                ("w0", C.c_double), ("dw", C.c_double), ("c", C.c_double),
+                ("plane_bytes", C.c_int64), ("host_ms", C.c_double)]
+
+
 _vp, _i64, _int, _dbl = C.c_void_p, C.c_int64, C.c_int, C.c_double
 _pvp = C.POINTER(C.c_void_p)
 
@@ -113,6 +119,8 @@ SIGNATURES = {
     "swv_tree_build_pixels": [_int, _dbl, _dbl, _i64, _vp, _vp, _pvp],
     "swv_fit_clean_beam": [_int, _int, _vp, _vp],
     "swv_restore": [_vp, _int, _int, _i64, _vp, _vp, _vp, _vp, _vp],
+    "swv_predict_degrid": [_vp, _int, _int, _dbl, _vp, _i64, _vp, _vp, _vp, _int, _int, _vp,
+                           C.POINTER(DegridStats)],
     "swv_wavelet_clean": [_vp, C.POINTER(CleanParams), _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                           _i64, _vp, _vp, C.POINTER(_i64), C.POINTER(CleanStats)],
 }

@@ -8,8 +8,8 @@ import ctypes as C
 import numpy as np
 import torch
 
-from ._lib import (SWV_F32C, SWV_FP64, SWV_HOGBOM_ABS, CleanParams, CleanStats, Instance,
-                   PlanStats, TreeStats, check, lib)
+from ._lib import (SWV_F32C, SWV_FP64, SWV_HOGBOM_ABS, CleanParams, CleanStats, DegridStats,
+                   Instance, PlanStats, TreeStats, check, lib)
 
 PRECISIONS = {"fp64": SWV_FP64, "f32c": SWV_F32C}
 
@@ -475,6 +475,28 @@ def restore(nx: int, ny: int, pix, val, abc, residual=None):
     check(lib().swv_restore(context(dev).handle, int(nx), int(ny), pix.numel(), _ptr(pix),
                             _ptr(val), _np_ptr(a), _ptr(residual), _ptr(out)))
     return out
+
+
+def predict_degrid(image, u, v, w, cell: float, support: int = 10, sign: int = -1, out=None):
+    """Model visibilities of a (ny, nx) float64 image by FFT + degridding (the
+    conventional predictor; exponential-of-semicircle kernel over `support`
+    cells in u, v and w).  Returns (complex128 visibilities, stats dict)."""
+    u, v, w, dev = _uvw(u, v, w)
+    if not isinstance(image, torch.Tensor) or image.dim() != 2:
+        raise ValueError("image must be a 2-D tensor")
+    ny, nx = image.shape
+    _image(image, "image", (ny, nx), dev)
+    n = u.numel()
+    if out is None:
+        out = torch.empty(n, dtype=torch.complex128, device=dev)
+    elif out.dtype != torch.complex128 or out.numel() != n or out.device != dev:
+        raise ValueError("out has the wrong dtype, size or device")
+    st = DegridStats()
+    check(lib().swv_predict_degrid(context(dev).handle, nx, ny, float(cell), _ptr(image), n,
+                                   _ptr(u), _ptr(v), _ptr(w), int(support), int(sign), _ptr(out),
+                                   C.byref(st)))
+    return out, {"n_planes": st.n_planes, "grid": (st.grid_ny, st.grid_nx), "w0": st.w0,
+                 "dw": st.dw, "c": st.c, "plane_bytes": st.plane_bytes, "host_ms": st.host_ms}
 
 
 def wavelet_clean(u, v, w, vis_obs, nx: int, ny: int, cell: float, J: int, ra_p: float,

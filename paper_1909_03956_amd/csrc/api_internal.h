@@ -33,6 +33,9 @@ struct swv_ctx_s {
     swv::DevBuf partial2;   // per-block chi^2 partials
     swv::DevBuf grid;       // image-grid directions and adjoint output (dirty images)
     swv::DevBuf ones;       // unit visibilities (dirty beam)
+    swv::DevBuf degrid;     // w planes and image scratch of the degridding predictor
+    void* fft_plan = nullptr;   // batched 2-D FFT plan of the degridding predictor
+    int fft_shape[3] = {0, 0, 0};
     int* d_status = nullptr;  // deferred-error bits raised by kernels
     int n_cu = 256;
     int per_lane[swv::kFamilies][2];
@@ -64,5 +67,7 @@ TreeArgs tree_args(swv_tree t, const TRec* d_rec);
 // Traversal for tree t given the tuned choice (1 level walker, 2 branch
 // walker): 0 level walker, 1 branch walker, -1 if no compiled one fits.
 int tree_walker(swv_tree t, int preferred);
+// Releases a plan made by the degridding predictor (no-op on NULL).
+void destroy_fft_plan(void* plan);
 
 }  // namespace swv

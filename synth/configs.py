@@ -178,6 +178,27 @@ CLEAN_SMALL = CleanSpec(TrackSpec(27, 1.7e3, 45.0, 2016.0, 24, 1.0e7, seed=711),
                         seed_model=712, seed_noise=713)
 
 
+# Predictor comparison on the clean7 grid (section 3.6.1's 140 distinct
+# components): components on random image pixels within the 30 deg source
+# field, lognormal fluxes.
+COMPARE_N_COMP = 140
+COMPARE_SEED = 741
+
+
+def clean7_grid_model(n: int = COMPARE_N_COMP, seed: int = COMPARE_SEED):
+    """(pixel ids of the 256 x 256 clean7 grid, fluxes): distinct pixels."""
+    S = CLEAN7
+    rng = np.random.default_rng(seed)
+    h = models.half_width(S.source_field_deg) / S.cell
+    c = S.n_pix // 2
+    pix = set()
+    while len(pix) < n:
+        ix, iy = (int(np.rint(rng.uniform(-h, h))) + c for _ in range(2))
+        pix.add(iy * S.n_pix + ix)
+    pix = np.array(sorted(pix), dtype=np.int64)
+    return pix, models.lognormal_fluxes(n, rng)
+
+
 def sample_rows(n_vis: int, n_sample: int, seed: int, tile: int = 256) -> np.ndarray:
     """Sorted row indices: the first and last `tile` rows plus a seeded random
     sample, so a sample spans several kernel tiles and the ragged tail."""
