@@ -24,9 +24,17 @@ sphere.*                   N_j = 12 4^(j-1); the twelve base-pixel centres;
     nested parent rule k_j = k_J >> 2(J-j); round trip pix -> centre -> pix;
     equal areas (Monte-Carlo chi^2); frame axes (P -> (alpha_P, delta_P),
     u east, v north); the recommended-resolution table (tests/golden).
+clean.*                    (the clean loop) unit-source dirty image and beam;
+    Hogbom as a sort (gain 1, delta beam), as a geometric series, and
+    model + residual = image; cross reference = the tree builder's pixels;
+    clean-beam fit of a sampled Gaussian; Eq. 6 linear and peaked; the loop
+    lowers chi^2 and finds pixel-centred sources.
+degrid.*                   (the FFT + degridding comparator) error against
+    the direct sum falls with the kernel width and stays under 10^(2 - W);
+    conjugate under the sign flip; converged quadrature.
 tree.*                     analysis followed by synthesis recovers lambda_J;
     uniform model gives gamma = 0; single component gives F eta_leaf; J = 1;
     Eq. 17 equals the snapped direct sum; the unmasked full-sphere tree
     gives the same V (zero branches may be skipped).
 """
-from . import sphere, tree, visibility  # noqa: F401
+from . import clean, degrid, sphere, tree, visibility  # noqa: F401
