@@ -280,6 +280,15 @@ def run_clean(swv, torch, np, dev, configs):
     t0 = time.perf_counter()
     out = swv.wavelet_clean(*args)
     wall = 1e3 * (time.perf_counter() - t0)
+    # the same loop as conventional (FFT + degridding, W = 10) and exact (direct) clean
+    others = {}
+    for pred in ("degrid", "direct"):
+        swv.wavelet_clean(*args, predictor=pred, support=10)   # FFT plan, code upload
+        o = swv.wavelet_clean(*args, predictor=pred, support=10)
+        others[pred] = {"chi2": [round(c["chi2"], 4) for c in o["cycles"]],
+                        "ms_predict": [round(c["ms_predict"], 4) for c in o["cycles"]],
+                        "model_pixels": [c["leaves"] for c in o["cycles"]],
+                        "residual_rms": float(f"{float(o['residual'].std()):.6g}")}
     cyc = out["cycles"]
     iters = sum(c["found"] for c in cyc)
     ms_minor = sum(c["ms_minor"] for c in cyc)
@@ -301,6 +310,8 @@ def run_clean(swv, torch, np, dev, configs):
         "residual_image_Gterms_per_s": round(n_vis * n * n / (float(np.median(ms_image)) * 1e-3)
                                              / 1e9, 1),
         "beam_Gterms_per_s": round(n_vis * (2 * n - 1) ** 2 / (out["ms_beam"] * 1e-3) / 1e9, 1),
+        "residual_rms": float(f"{float(out['residual'].std()):.6g}"),
+        "same_loop_other_predictors": others,
     }
 
 

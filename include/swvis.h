@@ -328,7 +328,19 @@ typedef struct {
     int n_major;          /* major cycles */
     int flags;            /* SWV_HOGBOM_ABS */
     int sign;             /* phase sign of Eq. 12, +1 or -1 */
+    int predictor;        /* SWV_PREDICT_TREE (the wavelet clean), SWV_PREDICT_DEGRID or
+                             SWV_PREDICT_DIRECT */
+    int support;          /* kernel width W of SWV_PREDICT_DEGRID */
 } swv_clean_params_t;
+
+/* Model-visibility predictor of the major cycles.  TREE: the tree of every
+ * component so far at level J (the wavelet clean).  DEGRID: the model image
+ * (components summed per pixel, in list order) by swv_predict_degrid, the
+ * conventional clean's FFT + degridding.  DIRECT: the direct sum over the
+ * image pixels holding components (exact for the pixelated model). */
+#define SWV_PREDICT_TREE 0
+#define SWV_PREDICT_DEGRID 1
+#define SWV_PREDICT_DIRECT 2
 
 #define SWV_CLEAN_MAX_CYCLES 64
 
@@ -349,7 +361,9 @@ typedef struct {
  * minor_iter Hogbom iterations, the tree of every component found so far
  * (swv_tree_build_pixels on the cross-referenced pixels), the model
  * visibilities by the tree route (FP64), the residual visibilities and the new
- * residual image.  Stops after n_major cycles (<= SWV_CLEAN_MAX_CYCLES) or
+ * residual image.  With params->predictor DEGRID or DIRECT the same loop runs
+ * with that predictor instead of the tree (ms_build then times the host
+ * model-image or component-list step).  Stops after n_major cycles (<= SWV_CLEAN_MAX_CYCLES) or
  * when a minor cycle finds nothing.
  * u, v, w, vis_obs [n_vis] DEVICE (vis_obs complex128).  Outputs: beam
  * [(2 ny - 1)(2 nx - 1)] DEVICE, residual [nx * ny] DEVICE, vis_model [n_vis]

@@ -185,7 +185,7 @@ def restore(nx: int, ny: int, comp_pix, comp_val, abc, residual=None):
 
 def wavelet_clean(u, v, w, vis_obs, nx: int, ny: int, cell: float, J: int, ra_p: float,
                   dec_p: float, gain: float, threshold: float, minor_iter: int, n_major: int,
-                  absolute=False, sign=-1):
+                  absolute=False, sign=-1, predictor="tree", support=10):
     """Cotton-Schwab cleaning with the wavelet predictor (sections 2.2, 3.5).
 
     Before the loop: the image grid, the dirty beam, the cross-reference table
@@ -195,9 +195,17 @@ def wavelet_clean(u, v, w, vis_obs, nx: int, ny: int, cell: float, J: int, ra_p:
     from the observed ones and forms the new residual image.  Stops after
     n_major cycles or when a minor cycle finds no component.
 
+    predictor "degrid" or "direct" runs the same loop with the model image
+    (components summed per pixel in list order) predicted by FFT + degridding
+    (oracle.degrid, kernel width `support`) or by the direct sum over its
+    non-zero pixels: the conventional clean and the exact one.
+
     Returns a dict: pix, val (all components, in order), residual (ny, nx),
     beam, vis_model, kJ (cross-reference), cycles (per cycle: components
-    found, distinct leaves, chi^2 = sum |residual visibility|^2)."""
+    found, distinct leaves or model pixels, chi^2 = sum |residual visibility|^2)."""
+    from . import degrid
+    if predictor not in ("tree", "degrid", "direct"):
+        raise ValueError("predictor must be tree, degrid or direct")
     l, m, nm1, inside = image_grid(nx, ny, cell)
     if not inside.all():
         raise ValueError("image grid leaves the unit disk")
@@ -215,11 +223,24 @@ def wavelet_clean(u, v, w, vis_obs, nx: int, ny: int, cell: float, J: int, ra_p:
             break
         pix = np.concatenate([pix, p_new])
         val = np.concatenate([val, v_new])
-        t = tree_from_pixels(J, ra_p, dec_p, kJ[pix], val)
-        vis_model = tree.predict_tree(t, u, v, w, sign)
+        if predictor == "tree":
+            t = tree_from_pixels(J, ra_p, dec_p, kJ[pix], val)
+            vis_model = tree.predict_tree(t, u, v, w, sign)
+            leaves = t.n_leaves
+        else:
+            model = np.zeros(nx * ny)
+            for p, g in zip(pix, val):          # list order
+                model[p] += g
+            nz = np.nonzero(model)[0]
+            leaves = int(nz.shape[0])
+            if predictor == "degrid":
+                vis_model = degrid.predict_degrid(model.reshape(ny, nx), cell, u, v, w, support,
+                                                  sign)
+            else:
+                vis_model = visibility.predict_direct(u, v, w, l[nz], m[nz], model[nz], sign)
         r = vis_obs - vis_model
         resid = dirty_image(u, v, w, r, l, m, nm1, sign).reshape(ny, nx)
-        cycles.append({"found": int(p_new.shape[0]), "leaves": t.n_leaves,
+        cycles.append({"found": int(p_new.shape[0]), "leaves": leaves,
                        "chi2": float(np.sum(np.abs(r) ** 2))})
     return {"pix": pix, "val": val, "residual": resid, "beam": beam, "vis_model": vis_model,
             "kJ": kJ, "cycles": cycles}

@@ -11,6 +11,7 @@ SWV_FP64, SWV_F32C = 0, 1
 SWV_ROUTE_DIRECT, SWV_ROUTE_TREE = 0, 1
 SWV_MAX_LEVEL = 29
 SWV_HOGBOM_ABS = 1
+PREDICTORS = {"tree": 0, "degrid": 1, "direct": 2}
 SWV_CLEAN_MAX_CYCLES = 64
 # kernel families of the tuning table (swv_tune_get / swv_tune_set)
 FAM_DIRECT64, FAM_DIRECT32, FAM_TREE, FAM_ADJOINT, FAM_GRAD = 0, 1, 2, 3, 4
@@ -56,7 +57,8 @@ class CleanParams(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("cell", C.c_double), ("J", C.c_int),
                 ("ra_p", C.c_double), ("dec_p", C.c_double), ("gain", C.c_double),
                 ("threshold", C.c_double), ("minor_iter", C.c_int64), ("n_major", C.c_int),
-                ("flags", C.c_int), ("sign", C.c_int)]
+                ("flags", C.c_int), ("sign", C.c_int), ("predictor", C.c_int),
+                ("support", C.c_int)]
 
 
 _NC = SWV_CLEAN_MAX_CYCLES

@@ -8,8 +8,8 @@ import ctypes as C
 import numpy as np
 import torch
 
-from ._lib import (SWV_F32C, SWV_FP64, SWV_HOGBOM_ABS, CleanParams, CleanStats, DegridStats,
-                   Instance, PlanStats, TreeStats, check, lib)
+from ._lib import (PREDICTORS, SWV_F32C, SWV_FP64, SWV_HOGBOM_ABS, CleanParams, CleanStats,
+                   DegridStats, Instance, PlanStats, TreeStats, check, lib)
 
 PRECISIONS = {"fp64": SWV_FP64, "f32c": SWV_F32C}
 
@@ -501,10 +501,16 @@ def predict_degrid(image, u, v, w, cell: float, support: int = 10, sign: int = -
 
 def wavelet_clean(u, v, w, vis_obs, nx: int, ny: int, cell: float, J: int, ra_p: float,
                   dec_p: float, gain: float = 0.1, threshold: float = 0.0, minor_iter: int = 100,
-                  n_major: int = 1, absolute=False, sign: int = -1):
-    """Cotton-Schwab cleaning with the wavelet predictor (sections 2.2, 3.5).
-    Returns a dict: pix, val (numpy, all components in order), residual and
-    beam (device images), vis_model (device complex128) and per-cycle stats."""
+                  n_major: int = 1, absolute=False, sign: int = -1, predictor: str = "tree",
+                  support: int = 10):
+    """Cotton-Schwab cleaning with the wavelet predictor (sections 2.2, 3.5);
+    predictor "degrid" (FFT + degridding of the model image, kernel width
+    `support`) or "direct" (direct sum over the model pixels) runs the same
+    loop as conventional or exact clean.  Returns a dict: pix, val (numpy, all
+    components in order), residual and beam (device images), vis_model
+    (device complex128) and per-cycle stats."""
+    if predictor not in PREDICTORS:
+        raise ValueError(f"predictor must be one of {sorted(PREDICTORS)}")
     u, v, w, dev = _uvw(u, v, w)
     vis_obs = _dev_c128(vis_obs, "vis_obs", dev)
     n = u.numel()
@@ -512,7 +518,8 @@ def wavelet_clean(u, v, w, vis_obs, nx: int, ny: int, cell: float, J: int, ra_p:
         raise ValueError("length mismatch")
     P = CleanParams(int(nx), int(ny), float(cell), int(J), float(ra_p), float(dec_p),
                     float(gain), float(threshold), int(minor_iter), int(n_major),
-                    SWV_HOGBOM_ABS if absolute else 0, int(sign))
+                    SWV_HOGBOM_ABS if absolute else 0, int(sign), PREDICTORS[predictor],
+                    int(support))
     beam = torch.empty((2 * int(ny) - 1, 2 * int(nx) - 1), dtype=torch.float64, device=dev)
     resid = torch.empty((int(ny), int(nx)), dtype=torch.float64, device=dev)
     vm = torch.empty(n, dtype=torch.complex128, device=dev)

@@ -3,6 +3,7 @@
 // clean image (Eq. 6) and the major-cycle driver around the tree predictor.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -399,7 +400,7 @@ namespace {
 
 // Owns the per-call device scratch and events of swv_wavelet_clean.
 struct CleanScratch {
-    void* p[4] = {};
+    void* p[5] = {};
     hipEvent_t ev[2] = {};
     swv_tree tree = nullptr;
     ~CleanScratch() {
@@ -432,6 +433,11 @@ extern "C" int swv_wavelet_clean(swv_ctx ctx, const swv_clean_params_t* P, int64
         return fail(SWV_EINVAL, "swv_wavelet_clean: component arrays hold %lld, need %lld",
                     (long long)cap, (long long)need);
     if (P->sign != 1 && P->sign != -1) return fail(SWV_EDOMAIN, "sign must be +1 or -1");
+    if (P->predictor != SWV_PREDICT_TREE && P->predictor != SWV_PREDICT_DEGRID &&
+        P->predictor != SWV_PREDICT_DIRECT)
+        return fail(SWV_EINVAL, "swv_wavelet_clean: unknown predictor %d", P->predictor);
+    if (P->predictor == SWV_PREDICT_DEGRID && (P->support < 2 || P->support > 16))
+        return fail(SWV_EINVAL, "swv_wavelet_clean: support %d outside 2 .. 16", P->support);
     if (!std::isfinite(P->gain) || std::isnan(P->threshold))
         return fail(SWV_EDOMAIN, "swv_wavelet_clean: gain must be finite, threshold a number");
     const int nx = P->nx, ny = P->ny;
@@ -476,6 +482,13 @@ extern "C" int swv_wavelet_clean(swv_ctx ctx, const swv_clean_params_t* P, int64
         CLEAN_HIP(hipMemsetAsync(vis_model, 0, 16 * (size_t)n_vis, s));
         int64_t total = 0;
         std::vector<int64_t> kj;
+        std::vector<double> model, ml, mm, mf;
+        double* d_model = nullptr;
+        if (P->predictor != SWV_PREDICT_TREE) {
+            model.assign((size_t)n_pix, 0.0);
+            CLEAN_HIP(hipMalloc(&S.p[4], 24 * (size_t)n_pix));
+            d_model = (double*)S.p[4];
+        }
         for (int cyc = 0; cyc < P->n_major; ++cyc) {
             CLEAN_RC(swv_hogbom(ctx, nx, ny, residual, beam, P->gain, P->threshold, P->minor_iter,
                                 P->flags, d_pix + total, d_val + total, d_found));
@@ -490,21 +503,62 @@ extern "C" int swv_wavelet_clean(swv_ctx ctx, const swv_clean_params_t* P, int64
                                      hipMemcpyDeviceToHost, s));
             CLEAN_HIP(hipStreamSynchronize(s));
             total += found;
-            // the model tree of every component so far, from the cross-referenced pixels
             const auto t0 = std::chrono::steady_clock::now();
-            kj.resize((size_t)total);
-            for (int64_t i = 0; i < total; ++i) kj[(size_t)i] = xref[(size_t)comp_pix[i]];
-            if (S.tree) {
-                (void)swv_tree_destroy(S.tree);   // the stream is idle here
-                S.tree = nullptr;
+            int64_t leaves = 0;
+            if (P->predictor == SWV_PREDICT_TREE) {
+                // the model tree of every component so far, from the cross-referenced pixels
+                kj.resize((size_t)total);
+                for (int64_t i = 0; i < total; ++i) kj[(size_t)i] = xref[(size_t)comp_pix[i]];
+                if (S.tree) {
+                    (void)swv_tree_destroy(S.tree);   // the stream is idle here
+                    S.tree = nullptr;
+                }
+                CLEAN_RC(swv_tree_build_pixels(P->J, P->ra_p, P->dec_p, total, kj.data(),
+                                               comp_val, &S.tree));
+                swv_tree_stats_t ts;
+                (void)swv_tree_stats(S.tree, &ts);
+                leaves = ts.n_leaves;
+            } else {
+                // the model image: components summed per pixel in list order
+                std::fill(model.begin(), model.end(), 0.0);
+                for (int64_t i = 0; i < total; ++i) model[(size_t)comp_pix[i]] += comp_val[i];
+                if (P->predictor == SWV_PREDICT_DIRECT) {
+                    ml.clear();
+                    mm.clear();
+                    mf.clear();
+                    for (int64_t p = 0; p < n_pix; ++p)
+                        if (model[(size_t)p] != 0.0) {
+                            const int64_t iy = p / nx, ix = p - iy * nx;
+                            ml.push_back((double)(ix - nx / 2) * P->cell);
+                            mm.push_back((double)(iy - ny / 2) * P->cell);
+                            mf.push_back(model[(size_t)p]);
+                        }
+                    leaves = (int64_t)mf.size();
+                    for (const auto* a : {&ml, &mm, &mf}) {
+                        const size_t k = (a == &ml ? 0 : a == &mm ? 1 : 2);
+                        CLEAN_HIP(hipMemcpyAsync(d_model + k * (size_t)n_pix, a->data(),
+                                                 8 * a->size(), hipMemcpyHostToDevice, s));
+                    }
+                } else {
+                    for (int64_t p = 0; p < n_pix; ++p) leaves += model[(size_t)p] != 0.0;
+                    CLEAN_HIP(hipMemcpyAsync(d_model, model.data(), 8 * (size_t)n_pix,
+                                             hipMemcpyHostToDevice, s));
+                }
             }
-            CLEAN_RC(swv_tree_build_pixels(P->J, P->ra_p, P->dec_p, total, kj.data(), comp_val,
-                                           &S.tree));
             const double ms_build =
                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
                     .count();
             CLEAN_HIP(hipEventRecord(S.ev[0], s));
-            CLEAN_RC(swv_predict_tree(ctx, S.tree, n_vis, u, v, w, P->sign, SWV_FP64, vis_model));
+            if (P->predictor == SWV_PREDICT_TREE)
+                CLEAN_RC(swv_predict_tree(ctx, S.tree, n_vis, u, v, w, P->sign, SWV_FP64,
+                                          vis_model));
+            else if (P->predictor == SWV_PREDICT_DEGRID)
+                CLEAN_RC(swv_predict_degrid(ctx, nx, ny, P->cell, d_model, n_vis, u, v, w,
+                                            P->support, P->sign, vis_model, nullptr));
+            else
+                CLEAN_RC(swv_predict_direct(ctx, n_vis, u, v, w, leaves, d_model,
+                                            d_model + n_pix, d_model + 2 * n_pix, P->sign,
+                                            SWV_FP64, vis_model));
             double ms_predict = 0.0, ms_image = 0.0;
             CLEAN_RC(lap(&ms_predict));
             CLEAN_RC(swv_residual_chi2(ctx, n_vis, vis_obs, vis_model, 1.0, S.p[2], d_chi2));
@@ -514,10 +568,8 @@ extern "C" int swv_wavelet_clean(swv_ctx ctx, const swv_clean_params_t* P, int64
             CLEAN_HIP(hipMemcpyAsync(&chi2, d_chi2, 8, hipMemcpyDeviceToHost, s));
             CLEAN_RC(lap(&ms_image));
             if (stats) {
-                swv_tree_stats_t ts;
-                (void)swv_tree_stats(S.tree, &ts);
                 stats->found[cyc] = found;
-                stats->leaves[cyc] = ts.n_leaves;
+                stats->leaves[cyc] = leaves;
                 stats->chi2[cyc] = chi2;
                 stats->ms_minor[cyc] = ms_minor;
                 stats->ms_build[cyc] = ms_build;

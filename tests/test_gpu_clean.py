@@ -205,6 +205,28 @@ def test_wavelet_clean_small_vs_oracle(env, small):
     np.testing.assert_allclose(abc, oc.fit_clean_beam(ref["beam"]), rtol=1e-9)
 
 
+@pytest.mark.parametrize("predictor", ["degrid", "direct"])
+def test_clean_small_other_predictors_vs_oracle(env, small, predictor):
+    """The same loop with the conventional (FFT + degridding, W = 10) and the
+    exact (direct) predictor against the oracle's loop."""
+    torch, swv = env
+    S, u, v, w, vis = small
+    n = S.n_pix
+    got = swv.wavelet_clean(dev(u, torch), dev(v, torch), dev(w, torch), dev_c(vis, torch), n,
+                            n, S.cell, S.J, S.ra_p, S.dec_p, S.gain, 0.0, S.minor_iter,
+                            S.n_major, predictor=predictor, support=10)
+    ref = oc.wavelet_clean(u, v, w, vis, n, n, S.cell, S.J, S.ra_p, S.dec_p, S.gain, 0.0,
+                           S.minor_iter, S.n_major, predictor=predictor, support=10)
+    note(f"clean_small {predictor}: cycles {got['cycles']}")
+    assert np.array_equal(got["pix"], ref["pix"])
+    np.testing.assert_allclose(got["val"], ref["val"], rtol=1e-9, atol=1e-12)
+    ymax = np.abs(vis).sum() / u.size
+    assert np.abs(host(got["residual"]) - ref["residual"]).max() <= 1e-10 * ymax
+    for cg, cr in zip(got["cycles"], ref["cycles"]):
+        assert cg["found"] == cr["found"] and cg["leaves"] == cr["leaves"]
+        assert abs(cg["chi2"] - cr["chi2"]) <= 1e-9 * cr["chi2"]
+
+
 def test_clean7_full_size(env):
     """The seven-source workload at full size: 707,616 rows, 256 x 256 pixels,
     two major cycles of 300 Hogbom iterations at J = 9.  Checked: the dirty
