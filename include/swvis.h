@@ -253,7 +253,10 @@ int swv_grad_direct(swv_ctx ctx, int64_t n_vis, const double* u, const double* v
  * is (2 ny - 1, 2 nx - 1) pixel offsets with the zero offset at
  * (nx - 1, ny - 1). */
 
-#define SWV_HOGBOM_ABS 1   /* take the peak of |I| instead of I */
+#define SWV_HOGBOM_ABS 1     /* take the peak of |I| instead of I */
+#define SWV_HOGBOM_SINGLE 2  /* run the cycle in one workgroup (the grid-wide form is
+                                otherwise used from 16,384 pixels where the device
+                                supports cooperative launches) */
 
 /* Directions of a grid: l, m, nm1 [nx * ny] DEVICE.  cx, cy is the pixel of
  * the phase centre.  Directions off the unit disk (l^2 + m^2 >= 1) get
@@ -283,8 +286,14 @@ int swv_dirty_image(swv_ctx ctx, int64_t n_vis, const double* u, const double* v
  * comp_val[n] = gain * C_n and subtracts comp_val[n] * beam shifted to p_n from
  * every pixel (one product, one subtraction: the result does not depend on
  * the device).  comp_pix, comp_val [max_iter] DEVICE; *n_found DEVICE
- * receives the number of components.  Image and beam must be finite.  One
- * workgroup runs the whole cycle; the call does not synchronise. */
+ * receives the number of components.  Image and beam must be finite.  From
+ * 16,384 pixels up to 64 workgroups (about four pixels per thread, more
+ * beyond 262,144 pixels) run the cycle under a cooperative launch, the workgroups exchanging
+ * their peaks once per iteration (SWV_HOGBOM_SINGLE, or a device that cannot
+ * launch cooperatively, keeps it in one workgroup); both give the same bits.
+ * Every wait in the exchange is bounded: should one ever run out, the cycle
+ * stops and *n_found is -1 (the image is then partly updated).  Uses 64 bytes
+ * per workgroup of context workspace.  The call does not synchronise. */
 int swv_hogbom(swv_ctx ctx, int nx, int ny, double* image, const double* beam, double gain,
                double threshold, int64_t max_iter, int flags, int64_t* comp_pix,
                double* comp_val, int64_t* n_found);

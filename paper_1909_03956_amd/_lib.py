@@ -11,6 +11,7 @@ SWV_FP64, SWV_F32C = 0, 1
 SWV_ROUTE_DIRECT, SWV_ROUTE_TREE = 0, 1
 SWV_MAX_LEVEL = 29
 SWV_HOGBOM_ABS = 1
+SWV_HOGBOM_SINGLE = 2
 PREDICTORS = {"tree": 0, "degrid": 1, "direct": 2}
 SWV_CLEAN_MAX_CYCLES = 64
 # kernel families of the tuning table (swv_tune_get / swv_tune_set)

@@ -8,7 +8,8 @@ import ctypes as C
 import numpy as np
 import torch
 
-from ._lib import (PREDICTORS, SWV_F32C, SWV_FP64, SWV_HOGBOM_ABS, CleanParams, CleanStats,
+from ._lib import (PREDICTORS, SWV_F32C, SWV_FP64, SWV_HOGBOM_ABS, SWV_HOGBOM_SINGLE,
+                   CleanParams, CleanStats,
                    DegridStats, Instance, PlanStats, TreeStats, check, lib)
 
 PRECISIONS = {"fp64": SWV_FP64, "f32c": SWV_F32C}
@@ -417,10 +418,13 @@ def dirty_beam(u, v, w, nx: int, ny: int, cell: float, sign: int = -1):
                        int(ny) - 1, sign)
 
 
-def hogbom(image, beam, gain: float, threshold: float, max_iter: int, absolute=False):
+def hogbom(image, beam, gain: float, threshold: float, max_iter: int, absolute=False,
+           single_workgroup=False):
     """Hogbom minor cycle (Eqs. 4, 5) on a (ny, nx) float64 image, updated in
     place to the residual.  Returns (pixel ids, component values g C_n) as
-    device tensors; waits for the kernel to learn their number."""
+    device tensors; waits for the kernel to learn their number.
+    single_workgroup keeps a large image's cycle in one workgroup (the same
+    bits as the grid-wide form)."""
     if not isinstance(image, torch.Tensor) or image.dim() != 2:
         raise ValueError("image must be a 2-D tensor")
     dev = image.device
@@ -432,9 +436,12 @@ def hogbom(image, beam, gain: float, threshold: float, max_iter: int, absolute=F
     val = torch.empty(max(k, 1), dtype=torch.float64, device=dev)
     n = torch.zeros(1, dtype=torch.int64, device=dev)
     check(lib().swv_hogbom(context(dev).handle, nx, ny, _ptr(image), _ptr(beam), float(gain),
-                           float(threshold), k, SWV_HOGBOM_ABS if absolute else 0, _ptr(pix),
+                           float(threshold), k, (SWV_HOGBOM_ABS if absolute else 0) |
+                           (SWV_HOGBOM_SINGLE if single_workgroup else 0), _ptr(pix),
                            _ptr(val), _ptr(n)))
     found = int(n.item())
+    if found < 0:
+        raise RuntimeError("the grid-wide Hogbom cycle timed out waiting for a workgroup")
     return pix[:found], val[:found]
 
 

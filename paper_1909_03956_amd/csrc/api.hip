@@ -138,7 +138,7 @@ void ctx_release(swv_ctx ctx) {
         DeviceGuard g(ctx->device);
         (void)hipStreamSynchronize(ctx->stream);
         for (DevBuf* b : {&ctx->comp, &ctx->partial, &ctx->partial2, &ctx->grid, &ctx->ones,
-                          &ctx->degrid})
+                          &ctx->degrid, &ctx->hog})
             if (b->p) (void)hipFree(b->p);
         destroy_fft_plan(ctx->fft_plan);
         if (ctx->d_status) (void)hipFree(ctx->d_status);

@@ -34,6 +34,7 @@ struct swv_ctx_s {
     swv::DevBuf grid;       // image-grid directions and adjoint output (dirty images)
     swv::DevBuf ones;       // unit visibilities (dirty beam)
     swv::DevBuf degrid;     // w planes and image scratch of the degridding predictor
+    swv::DevBuf hog;        // per-workgroup peaks of the grid-wide Hogbom cycle
     void* fft_plan = nullptr;   // batched 2-D FFT plan of the degridding predictor
     int fft_shape[3] = {0, 0, 0};
     int* d_status = nullptr;  // deferred-error bits raised by kernels

@@ -1,6 +1,7 @@
 // Clean loop (sections 2.1, 2.2, 3.5): image grids, dirty images and the
 // dirty beam from the exact adjoint, the Hogbom minor cycle (Eqs. 4, 5), the
 // clean image (Eq. 6) and the major-cycle driver around the tree predictor.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -184,6 +185,169 @@ __global__ __launch_bounds__(kHogBlock) void k_hogbom(
     if (tid == 0) *n_found = it;
 }
 
+// The same minor cycle spread over G workgroups, all resident at once (a
+// cooperative launch: the runtime refuses a grid that could not be).  Global
+// thread g owns pixels g, g + G B, ...  Each iteration a workgroup publishes
+// its peak in its slot (key, value, index, then the iteration number with
+// release order) and gathers every workgroup's slot of that iteration
+// (acquire loads of the iteration number, then the data): the gather is the
+// barrier, with no shared counter.  Every workgroup reduces the G peaks in
+// the same total order, so all take the same decision.  Slots alternate
+// between two buffers: a workgroup can only reuse a buffer after every other
+// one has published the next iteration, i.e. finished reading it.  Every wait
+// is bounded: after kHogSpinLimit polls the workgroup gives up, the cycle
+// ends and *n_found is set to -1.
+constexpr int kHogGridBlock = 256;
+constexpr int kHogGridWaves = kHogGridBlock / 64;
+constexpr int kHogSpinLimit = 1 << 22;
+
+// Block-wide best (key, val, idx): wave butterflies, then every thread
+// reduces the per-wave results in wave order.
+__device__ __forceinline__ void block_best(double& key, double& val, int& idx, double* sk,
+                                           double* sv, int* si) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double k2 = __shfl_xor(key, off, 64);
+        const double v2 = __shfl_xor(val, off, 64);
+        const int i2 = __shfl_xor(idx, off, 64);
+        if (ahead(k2, i2, key, idx)) {
+            key = k2;
+            val = v2;
+            idx = i2;
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();   // the previous reader of these slots is done
+    if (lane == 0) {
+        sk[wave] = key;
+        sv[wave] = val;
+        si[wave] = idx;
+    }
+    __syncthreads();
+    key = sk[0];
+    val = sv[0];
+    idx = si[0];
+    for (int q = 1; q < kHogGridWaves; ++q)
+        if (ahead(sk[q], si[q], key, idx)) {
+            key = sk[q];
+            val = sv[q];
+            idx = si[q];
+        }
+}
+
+// slot layout: [buffer][workgroup][key, val, idx, iteration + 1] as 64-bit words
+__device__ __forceinline__ void publish(unsigned long long* slot, double key, double val,
+                                        int idx, int64_t it) {
+    __hip_atomic_store(slot + 0, (unsigned long long)__double_as_longlong(key), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(slot + 1, (unsigned long long)__double_as_longlong(val), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(slot + 2, (unsigned long long)(unsigned)idx, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(slot + 3, (unsigned long long)(it + 1), __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool ABS>
+__global__ __launch_bounds__(kHogGridBlock) void k_hogbom_grid(
+    double* __restrict__ img, const double* __restrict__ beam, int nx, int ny, double gain,
+    double threshold, int64_t max_iter, int64_t* __restrict__ comp_pix,
+    double* __restrict__ comp_val, int64_t* __restrict__ n_found,
+    unsigned long long* __restrict__ slots) {
+    __shared__ double sk[kHogGridWaves], sv[kHogGridWaves];
+    __shared__ int si[kHogGridWaves];
+    __shared__ int s_timeout;
+    const int G = (int)gridDim.x;
+    const int n = nx * ny;
+    const int64_t bw = 2 * (int64_t)nx - 1;
+    const int stride = G * kHogGridBlock;
+    const int g0 = (int)blockIdx.x * kHogGridBlock + (int)threadIdx.x;
+    const int y0 = g0 / nx, x0 = g0 - (g0 / nx) * nx;
+    const int sy = stride / nx, sx = stride - sy * nx;
+    if (threadIdx.x == 0) s_timeout = 0;
+
+    double key = -HUGE_VAL, val = 0.0;
+    int idx = INT_MAX;
+    for (int p = g0; p < n; p += stride) {
+        const double x = img[p];
+        const double k = ABS ? fabs(x) : x;
+        if (k > key) {
+            key = k;
+            val = x;
+            idx = p;
+        }
+    }
+    int64_t it = 0;   // the peaks being exchanged belong to the image after `it` components
+    for (;;) {
+        block_best(key, val, idx, sk, sv, si);
+        unsigned long long* buf = slots + (size_t)(it & 1) * 4 * G;
+        if (threadIdx.x == 0) publish(buf + 4 * (size_t)blockIdx.x, key, val, idx, it);
+        // gather: thread b waits for workgroup b's slot of this iteration
+        key = -HUGE_VAL;
+        val = 0.0;
+        idx = INT_MAX;
+        for (int b = threadIdx.x; b < G; b += kHogGridBlock) {
+            const unsigned long long* sl = buf + 4 * (size_t)b;
+            int spins = 0;
+            while (__hip_atomic_load(sl + 3, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) !=
+                   (unsigned long long)(it + 1)) {
+                if (++spins > kHogSpinLimit) {
+                    s_timeout = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            const double k2 = __longlong_as_double(
+                (long long)__hip_atomic_load(sl + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            const double v2 = __longlong_as_double(
+                (long long)__hip_atomic_load(sl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            const int i2 = (int)(unsigned)__hip_atomic_load(sl + 2, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+            if (ahead(k2, i2, key, idx)) {
+                key = k2;
+                val = v2;
+                idx = i2;
+            }
+        }
+        block_best(key, val, idx, sk, sv, si);   // its barriers also publish s_timeout
+        if (s_timeout) {
+            if (threadIdx.x == 0) *n_found = -1;
+            return;
+        }
+        if (it >= max_iter || !(key > threshold)) break;   // the same in every workgroup
+        const double gc = gain * val;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            comp_pix[it] = idx;
+            comp_val[it] = gc;
+        }
+        ++it;
+        const int py = idx / nx, px = idx - (idx / nx) * nx;
+        const double* B = beam + (int64_t)(ny - 1 - py) * bw + (nx - 1 - px);
+        key = -HUGE_VAL;
+        val = 0.0;
+        idx = INT_MAX;
+        int y = y0, x = x0;
+        for (int p = g0; p < n; p += stride) {
+            const double t = gc * B[(int64_t)y * bw + x];
+            const double r = img[p] - t;
+            img[p] = r;
+            const double k = ABS ? fabs(r) : r;
+            if (k > key) {
+                key = k;
+                val = r;
+                idx = p;
+            }
+            x += sx;
+            y += sy;
+            while (x >= nx) {
+                x -= nx;
+                ++y;
+            }
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n_found = it;
+}
+
 // --------------------------------------------------------------- restore ---
 // Components are staged through LDS in tiles (pixel split into row and
 // column once per component); each thread sums its pixel's terms in list
@@ -219,6 +383,21 @@ __global__ __launch_bounds__(kGridBlock) void k_restore(
 }
 
 unsigned grid_blocks(int64_t n) { return (unsigned)((n + kGridBlock - 1) / kGridBlock); }
+
+__global__ void k_zero_u64(int64_t n, unsigned long long* p) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// Below this many pixels one workgroup is as fast as an exchange per iteration.
+constexpr int kHogGridMinPixels = 16384;
+constexpr int kHogGridMaxBlocks = 64;
+
+bool coop_supported(int device) {
+    int v = 0;
+    return hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, device) == hipSuccess &&
+           v != 0;
+}
 
 int check_grid(int nx, int ny, double cell) {
     if (nx < 1 || ny < 1 || nx > 32768 || ny > 32768 || (int64_t)nx * ny > (1 << 30))
@@ -308,8 +487,31 @@ extern "C" int swv_hogbom(swv_ctx ctx, int nx, int ny, double* image, const doub
         return fail(SWV_EINVAL, "swv_hogbom: null component arrays");
     if (!std::isfinite(gain) || std::isnan(threshold))
         return fail(SWV_EDOMAIN, "swv_hogbom: gain must be finite, threshold a number");
-    if (flags & ~SWV_HOGBOM_ABS) return fail(SWV_EINVAL, "swv_hogbom: unknown flags %d", flags);
+    if (flags & ~(SWV_HOGBOM_ABS | SWV_HOGBOM_SINGLE))
+        return fail(SWV_EINVAL, "swv_hogbom: unknown flags %d", flags);
     CLEAN_GUARD(ctx);
+    const int n = nx * ny;
+    if (n >= kHogGridMinPixels && !(flags & SWV_HOGBOM_SINGLE) && coop_supported(ctx->device)) {
+        // about four pixels per thread, at most kHogGridMaxBlocks workgroups: the
+        // exchange (every workgroup polls every slot) grows with their square
+        int G = (n + 4 * kHogGridBlock - 1) / (4 * kHogGridBlock);
+        G = G < kHogGridMaxBlocks ? G : kHogGridMaxBlocks;
+        G = G < ctx->n_cu ? G : ctx->n_cu;
+        CLEAN_RC(ensure(ctx, ctx->hog, 64 * (size_t)G));
+        unsigned long long* slots = (unsigned long long*)ctx->hog.p;
+        // iteration numbers start from a clean slate (a fill kernel, no memset)
+        k_zero_u64<<<(unsigned)((8 * G + 255) / 256), 256, 0, ctx->stream>>>(8 * (int64_t)G, slots);
+        CLEAN_HIP(hipGetLastError());
+        void* args[] = {&image, (void*)&beam, &nx, &ny, &gain, &threshold, &max_iter, &comp_pix,
+                        &comp_val, &n_found, &slots};
+        const void* fn = (flags & SWV_HOGBOM_ABS) ? (const void*)k_hogbom_grid<true>
+                                                  : (const void*)k_hogbom_grid<false>;
+        const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(kHogGridBlock), args, 0,
+                                                        ctx->stream);
+        if (e == hipSuccess) return SWV_OK;
+        // a grid that cannot be resident at once is refused before it starts
+        (void)hipGetLastError();
+    }
     if (flags & SWV_HOGBOM_ABS)
         k_hogbom<true><<<1, kHogBlock, 0, ctx->stream>>>(image, beam, nx, ny, gain, threshold,
                                                          max_iter, comp_pix, comp_val, n_found);
@@ -496,6 +698,8 @@ extern "C" int swv_wavelet_clean(swv_ctx ctx, const swv_clean_params_t* P, int64
             CLEAN_HIP(hipMemcpyAsync(&found, d_found, 8, hipMemcpyDeviceToHost, s));
             double ms_minor = 0.0;
             CLEAN_RC(lap(&ms_minor));   // synchronises: `found` is valid
+            if (found < 0)
+                return fail(SWV_EHIP, "swv_wavelet_clean: the grid-wide minor cycle timed out");
             if (found == 0) break;
             CLEAN_HIP(hipMemcpyAsync(comp_pix + total, d_pix + total, 8 * (size_t)found,
                                      hipMemcpyDeviceToHost, s));

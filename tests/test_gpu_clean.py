@@ -44,10 +44,10 @@ def _image_like(rng, ny, nx, beam, n_src=6, quantum=None):
     return img
 
 
-def _hogbom_gpu(torch, swv, img, beam, gain, thr, k, absolute):
+def _hogbom_gpu(torch, swv, img, beam, gain, thr, k, absolute, single=False):
     t_img = torch.as_tensor(img.copy(), device="cuda")
     t_beam = torch.as_tensor(beam, device="cuda")
-    pix, val = swv.hogbom(t_img, t_beam, gain, thr, k, absolute)
+    pix, val = swv.hogbom(t_img, t_beam, gain, thr, k, absolute, single_workgroup=single)
     return host(t_img), host(pix), host(val)
 
 
@@ -147,6 +147,25 @@ def test_hogbom_full_size_bitwise(env):
     assert got_pix.size == S.minor_iter
     assert np.array_equal(got_pix, ref_pix) and np.array_equal(got_val, ref_val)
     assert np.array_equal(got_img, ref_img)
+
+
+@pytest.mark.parametrize("ny,nx", [(256, 256), (128, 129), (181, 181), (3, 6000), (16384, 1)])
+def test_hogbom_grid_and_single_workgroup_agree(env, ny, nx):
+    """From 16,384 pixels the cycle runs grid-wide (one workgroup per compute
+    unit, a grid barrier per iteration); forced into one workgroup it gives
+    the same bits, and both equal the oracle, ties included."""
+    torch, swv = env
+    rng = np.random.default_rng(ny + 3 * nx)
+    beam = _beam_like(rng, ny, nx, quantum=1 / 64)
+    img = _image_like(rng, ny, nx, beam, n_src=5, quantum=1 / 16)
+    for gain, thr, k, absolute in ((0.2, 0.0, 120, False), (0.5, 0.1, 200, True)):
+        note(f"hogbom grid/single {ny}x{nx} gain={gain} k={k} abs={absolute}")
+        g = _hogbom_gpu(torch, swv, img, beam, gain, thr, k, absolute)
+        o = _hogbom_gpu(torch, swv, img, beam, gain, thr, k, absolute, single=True)
+        ref_img, ref_pix, ref_val = oc.hogbom(img, beam, gain, thr, k, absolute)
+        for got_img, got_pix, got_val in (g, o):
+            assert np.array_equal(got_pix, ref_pix) and np.array_equal(got_val, ref_val)
+            assert np.array_equal(got_img, ref_img)
 
 
 def test_hogbom_argument_errors(env):
