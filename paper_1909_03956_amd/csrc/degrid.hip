@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <hipfft/hipfft.h>
 
+#include <algorithm>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -211,14 +212,11 @@ constexpr DegridFn kDegrid[] = {
     launch_degrid_w<9>, launch_degrid_w<10>, launch_degrid_w<11>, launch_degrid_w<12>,
     launch_degrid_w<13>, launch_degrid_w<14>, launch_degrid_w<15>, launch_degrid_w<16>};
 
-__global__ __launch_bounds__(kDgBlock) void k_minmax(int64_t n, const double* __restrict__ x,
-                                                     double* __restrict__ out) {
-    __shared__ double smin[kDgBlock], smax[kDgBlock];
-    double lo = HUGE_VAL, hi = -HUGE_VAL;
-    for (int64_t i = threadIdx.x; i < n; i += kDgBlock) {
-        lo = fmin(lo, x[i]);
-        hi = fmax(hi, x[i]);
-    }
+// w range: kMinmaxBlocks partial (min, max) pairs, then one block combines them.
+constexpr int kMinmaxBlocks = 512;
+
+__device__ __forceinline__ void block_minmax(double& lo, double& hi, double* smin,
+                                             double* smax) {
     smin[threadIdx.x] = lo;
     smax[threadIdx.x] = hi;
     __syncthreads();
@@ -229,9 +227,40 @@ __global__ __launch_bounds__(kDgBlock) void k_minmax(int64_t n, const double* __
         }
         __syncthreads();
     }
+    lo = smin[0];
+    hi = smax[0];
+}
+
+__global__ __launch_bounds__(kDgBlock) void k_minmax_partial(int64_t n,
+                                                             const double* __restrict__ x,
+                                                             double* __restrict__ part) {
+    __shared__ double smin[kDgBlock], smax[kDgBlock];
+    double lo = HUGE_VAL, hi = -HUGE_VAL;
+    for (int64_t i = (int64_t)blockIdx.x * kDgBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kDgBlock) {
+        lo = fmin(lo, x[i]);
+        hi = fmax(hi, x[i]);
+    }
+    block_minmax(lo, hi, smin, smax);
     if (threadIdx.x == 0) {
-        out[0] = smin[0];
-        out[1] = smax[0];
+        part[2 * blockIdx.x] = lo;
+        part[2 * blockIdx.x + 1] = hi;
+    }
+}
+
+__global__ __launch_bounds__(kDgBlock) void k_minmax_final(int n_part,
+                                                           const double* __restrict__ part,
+                                                           double* __restrict__ out) {
+    __shared__ double smin[kDgBlock], smax[kDgBlock];
+    double lo = HUGE_VAL, hi = -HUGE_VAL;
+    for (int i = threadIdx.x; i < n_part; i += kDgBlock) {
+        lo = fmin(lo, part[2 * i]);
+        hi = fmax(hi, part[2 * i + 1]);
+    }
+    block_minmax(lo, hi, smin, smax);
+    if (threadIdx.x == 0) {
+        out[0] = lo;
+        out[1] = hi;
     }
 }
 
@@ -285,10 +314,12 @@ extern "C" int swv_predict_degrid(swv_ctx ctx, int nx, int ny, double cell, cons
     const hipStream_t s = ctx->stream;
     const auto t0 = std::chrono::steady_clock::now();
     // w range of the rows
-    int rc = ensure(ctx, ctx->partial2, 256);
+    int rc = ensure(ctx, ctx->partial2, 16 * (kMinmaxBlocks + 1));
     if (rc) return rc;
     double* d_mm = (double*)ctx->partial2.p;
-    k_minmax<<<1, kDgBlock, 0, s>>>(n_vis, w, d_mm);
+    const int nb = (int)std::min<int64_t>(kMinmaxBlocks, (n_vis + kDgBlock - 1) / kDgBlock);
+    k_minmax_partial<<<nb, kDgBlock, 0, s>>>(n_vis, w, d_mm + 2);
+    k_minmax_final<<<1, kDgBlock, 0, s>>>(nb, d_mm + 2, d_mm);
     double mm[2];
     hipError_t e = hipMemcpyAsync(mm, d_mm, 16, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
