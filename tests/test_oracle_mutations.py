@@ -128,3 +128,121 @@ def test_wrong_south_face_offset_caught(monkeypatch):
     monkeypatch.setattr(sp, "ang2pix_xyz", bad)
     with pytest.raises(AssertionError):
         TS.test_round_trip_every_pixel(3)
+
+
+# ------------------------------------------------- clean loop, degridding --
+from oracle import clean as oc  # noqa: E402
+from oracle import degrid as od  # noqa: E402
+
+from . import test_oracle_clean as TC  # noqa: E402
+from . import test_oracle_degrid as TG  # noqa: E402
+
+
+def _hogbom_variant(mirror=False, record_peak=False, last_tie=False, add=False):
+    def bad(image, beam, gain, threshold, max_iter, absolute=False):
+        I = np.array(image, dtype=np.float64, copy=True)
+        ny, nx = I.shape
+        B = np.asarray(beam, np.float64)
+        pix, val = [], []
+        for _ in range(int(max_iter)):
+            key = np.abs(I) if absolute else I
+            flat = key.ravel()
+            p = int(flat.size - 1 - np.argmax(flat[::-1])) if last_tie else int(np.argmax(flat))
+            if not flat[p] > threshold:
+                break
+            py, px = divmod(p, nx)
+            gC = gain * I.flat[p]
+            win = B[ny - 1 - py:2 * ny - 1 - py, nx - 1 - px:2 * nx - 1 - px]
+            if mirror:
+                win = win[::-1, ::-1]
+            I = I + gC * win if add else I - gC * win
+            pix.append(p)
+            val.append(I.flat[p] / gain if record_peak else gC)
+        return I, np.asarray(pix, np.int64), np.asarray(val, np.float64)
+    return bad
+
+
+@pytest.mark.parametrize("kw,pin", [
+    ({"mirror": True}, TC.test_hogbom_model_plus_residual_gives_back_the_image),
+    ({"record_peak": True}, TC.test_hogbom_single_source_is_geometric),
+    ({"last_tie": True}, lambda: TC.test_hogbom_delta_beam_gain_one_sorts_pixels(False)),
+    ({"add": True}, TC.test_hogbom_single_source_is_geometric),
+])
+def test_hogbom_mutations_caught(monkeypatch, kw, pin):
+    monkeypatch.setattr(oc, "hogbom", _hogbom_variant(**kw))
+    with pytest.raises(AssertionError):
+        pin()
+
+
+def test_dirty_image_without_normalisation_caught(monkeypatch):
+    monkeypatch.setattr(oc, "dirty_image",
+                        lambda u, v, w, y, l, m, nm1, sign=-1:
+                        ov.adjoint(u, v, w, y, l, m, nm1, sign).real)
+    with pytest.raises(AssertionError):
+        TC.test_dirty_image_of_unit_source_peaks_on_its_pixel(TC.SMALL.uvw())
+
+
+def test_dirty_beam_without_w_term_caught(monkeypatch):
+    orig = oc.dirty_image
+
+    def beam_no_w(u, v, w, nx, ny, cell, sign=-1):
+        bl, bm, bn, inside = oc.image_grid(2 * nx - 1, 2 * ny - 1, cell, nx - 1, ny - 1)
+        b = np.zeros(bl.shape[0])
+        b[inside] = orig(u, v, np.zeros_like(w), np.ones(u.size, complex), bl[inside],
+                         bm[inside], bn[inside], sign)
+        return b.reshape(2 * ny - 1, 2 * nx - 1)
+    monkeypatch.setattr(oc, "dirty_beam", beam_no_w)
+    with pytest.raises(AssertionError):
+        TC.test_dirty_beam_is_the_image_of_a_centre_source(TC.SMALL.uvw())
+
+
+def test_clean_beam_swapped_axes_caught(monkeypatch):
+    orig = oc.fit_clean_beam
+    monkeypatch.setattr(oc, "fit_clean_beam", lambda beam: orig(beam)[::-1])
+    with pytest.raises(AssertionError):
+        TC.test_fit_clean_beam_recovers_a_sampled_gaussian()
+
+
+def test_restore_wrong_sign_caught(monkeypatch):
+    orig = oc.restore
+    monkeypatch.setattr(oc, "restore", lambda nx, ny, p, v, abc, residual=None:
+                        orig(nx, ny, p, v, (abc[0], -abc[1], abc[2]), residual))
+    with pytest.raises(AssertionError):
+        TC.test_restore_linear_peaked_symmetric()
+
+
+def test_cross_reference_wrong_frame_caught(monkeypatch):
+    orig = oc.cross_reference
+    monkeypatch.setattr(oc, "cross_reference",
+                        lambda J, ra, dec, l, m: orig(J, ra, -dec, l, m))
+    with pytest.raises(AssertionError):
+        TC.test_cross_reference_and_tree_from_pixels()
+
+
+def test_degrid_missing_w_correction_caught(monkeypatch):
+    orig = od.es_hat
+    # the w direction's correction is the only call with per-pixel (2-D) arguments
+    monkeypatch.setattr(od, "es_hat", lambda f, W, n_quad=od.N_QUAD:
+                        np.ones_like(np.asarray(f, float)) * orig(np.zeros(1), W, n_quad)[0]
+                        if np.ndim(f) == 2 else orig(f, W, n_quad))
+    with pytest.raises(AssertionError):
+        TG.test_wide_field_w_term(TG.TRACK.uvw())
+
+
+def test_degrid_wrong_fft_direction_caught(monkeypatch):
+    orig_fft2, orig_ifft2 = np.fft.fft2, np.fft.ifft2
+    monkeypatch.setattr(od.np.fft, "fft2", lambda a: orig_ifft2(a) * a.size)
+    with pytest.raises(AssertionError):
+        TG.test_error_falls_with_support(TG.TRACK.uvw())
+    monkeypatch.setattr(od.np.fft, "fft2", orig_fft2)
+
+
+def test_degrid_missing_centring_phase_caught(monkeypatch):
+    orig = od.predict_degrid
+
+    def bad(image, cell, u, v, w, W=10, sign=-1):
+        P = od.plan(image.shape[1], image.shape[0], cell, w, W)
+        return orig(image, cell, u, v, w, W, sign) * np.exp(-sign * 2j * np.pi * np.asarray(w) * P["c"])
+    monkeypatch.setattr(od, "predict_degrid", bad)
+    with pytest.raises(AssertionError):
+        TG.test_wide_field_w_term(TG.TRACK.uvw())
