@@ -288,3 +288,53 @@ def test_clean7_full_size(env):
     frac = out["val"][near].sum() / np.abs(out["val"]).sum()
     note(f"clean7: {frac:.3f} of the component flux lies within 1.5 pixels of a source")
     assert frac > 0.5
+
+
+def test_wavelet_clean_edge_cases(env, small):
+    """No cycles, no iterations, a threshold above every peak, absolute
+    peaks (against the oracle), and argument errors of the driver."""
+    torch, swv = env
+    S, u, v, w, vis = small
+    n = S.n_pix
+    U, V, W, Y = dev(u, torch), dev(v, torch), dev(w, torch), dev_c(vis, torch)
+    common = (U, V, W, Y, n, n, S.cell, S.J, S.ra_p, S.dec_p)
+    out = swv.wavelet_clean(*common, gain=0.1, threshold=0.0, minor_iter=10, n_major=0)
+    assert out["pix"].size == 0 and out["cycles"] == []
+    l, m, nm1, _ = oc.image_grid(n, n, S.cell)
+    dirty = oc.dirty_image(u, v, w, vis, l, m, nm1).reshape(n, n)
+    ymax = np.abs(vis).sum() / u.size
+    assert np.abs(host(out["residual"]) - dirty).max() <= 1e-12 * ymax
+    assert np.all(host(out["vis_model"]) == 0)
+    out = swv.wavelet_clean(*common, minor_iter=0, n_major=3)
+    assert out["pix"].size == 0 and out["cycles"] == []
+    out = swv.wavelet_clean(*common, threshold=1e6, minor_iter=50, n_major=3)
+    assert out["pix"].size == 0 and out["cycles"] == []
+    got = swv.wavelet_clean(*common, gain=0.3, minor_iter=40, n_major=2, absolute=True)
+    ref = oc.wavelet_clean(u, v, w, vis, n, n, S.cell, S.J, S.ra_p, S.dec_p, 0.3, 0.0, 40, 2,
+                           absolute=True)
+    assert np.array_equal(got["pix"], ref["pix"])
+    np.testing.assert_allclose(got["val"], ref["val"], rtol=1e-9, atol=1e-12)
+    with pytest.raises(swv.SwvError, match="SWV_EDOMAIN"):
+        swv.wavelet_clean(*common[:6], 0.3, S.J, S.ra_p, S.dec_p)    # grid off the disk
+    with pytest.raises(swv.SwvError, match="SWV_EINVAL"):
+        swv.wavelet_clean(*common, n_major=65)
+    with pytest.raises(swv.SwvError, match="SWV_EINVAL"):
+        swv.wavelet_clean(*common, predictor="degrid", support=1)
+
+
+def test_restore_of_the_loop_output(env, small):
+    """Eq. 6 on the loop's components with the clean beam fitted to its own
+    dirty beam, against the oracle on the oracle's loop output."""
+    torch, swv = env
+    S, u, v, w, vis = small
+    n = S.n_pix
+    got = swv.wavelet_clean(dev(u, torch), dev(v, torch), dev(w, torch), dev_c(vis, torch), n,
+                            n, S.cell, S.J, S.ra_p, S.dec_p, S.gain, 0.0, S.minor_iter, 1)
+    abc = swv.fit_clean_beam(host(got["beam"]))
+    img = host(swv.restore(n, n, torch.as_tensor(got["pix"], device="cuda"),
+                           dev(got["val"], torch), abc, got["residual"]))
+    ref = oc.wavelet_clean(u, v, w, vis, n, n, S.cell, S.J, S.ra_p, S.dec_p, S.gain, 0.0,
+                           S.minor_iter, 1)
+    rimg = oc.restore(n, n, ref["pix"], ref["val"], oc.fit_clean_beam(ref["beam"]),
+                      ref["residual"])
+    assert np.abs(img - rimg).max() <= 1e-9 * np.abs(ref["val"]).sum()
