@@ -65,6 +65,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-clean", action="store_true",
                    help="skip the clean-loop measurement after the step")
+    p.add_argument("--batched", action="store_true",
+                   help="time the 256-instance batched workload (1.29e9 rows) as captured "
+                        "graphs of the batched plans, direct and tree routes, and exit")
     p.add_argument("--clean-only", action="store_true",
                    help="run only the clean loop on the seven-source workload (two calls) "
                         "and the predictor comparison, and print their JSON blocks")
@@ -376,6 +379,63 @@ def run_compare(swv, torch, np, dev, configs):
     return out
 
 
+def run_batched(swv, torch, np, dev, configs):
+    """The batched workload: 64 channels x 4 pointings of the 256-antenna array,
+    2M-8M unflagged rows each (1.29e9 in all), made on the device; one plan per
+    route (direct, tree) over all 256 instances, captured as a graph; each
+    graph launched once warm and then timed three times."""
+    B = configs.BatchedWorkload()
+    ra, dec = configs.CFG2.ra_p, configs.CFG2.dec_p
+
+    def D(x):
+        return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+    insts = {"direct": [], "tree": []}
+    keep = []
+    rows = terms = leaves = 0
+    t0 = time.perf_counter()
+    for inst in B.instances:
+        kept, l, m, f = B.instance_rows_kept(inst)
+        u, v, w = B.instance_uvw_torch(inst, kept, dev)
+        out_d = torch.empty(kept.size, dtype=torch.complex128, device=dev)
+        out_t = torch.empty(kept.size, dtype=torch.complex128, device=dev)
+        tree = swv.Tree(inst.J, ra, dec, l, m, f)
+        insts["direct"].append(dict(route="direct", u=u, v=v, w=w, l=D(l), m=D(m), flux=D(f),
+                                    out=out_d))
+        insts["tree"].append(dict(route="tree", tree=tree, u=u, v=v, w=w, out=out_t))
+        keep.append(tree)
+        rows += kept.size
+        terms += kept.size * inst.n_comp
+        leaves += kept.size * (tree.stats()["n_leaves"] + tree.stats()["n_internal"])
+    torch.cuda.synchronize()
+    log(f"batched workload made in {time.perf_counter() - t0:.1f} s: {len(B.instances)} "
+        f"instances, {rows} rows")
+    out = {"workload": "cfg4: 64 channels (0.95-1.75 GHz) x 4 pointings of the 256-antenna "
+                       "20 km array, 2M-8M unflagged rows per instance, N_C 100-20,000, J 7-10",
+           "instances": len(B.instances), "rows": rows, "terms": terms,
+           "tree_nodes_x_rows": leaves}
+    for name in ("direct", "tree"):
+        plan = swv.BatchPlan(insts[name])
+        graph = plan.capture()
+        graph.launch()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            graph.launch()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        out[name] = {"ms": round(ms, 2), "Gvis_terms_per_s": round(terms / (ms * 1e-3) / 1e9, 1),
+                     "Grows_per_s": round(rows / (ms * 1e-3) / 1e9, 3), "plan": plan.stats()}
+        log(f"batched {name}: {ms:.1f} ms")
+        graph.close()
+        plan.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -397,6 +457,9 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.batched:
+        print(json.dumps({"batched": run_batched(swv, torch, np, dev, configs)}), flush=True)
+        return
     if args.clean_only:
         print(json.dumps({"clean_loop": run_clean(swv, torch, np, dev, configs),
                           "predictor_comparison": run_compare(swv, torch, np, dev, configs)}),
