@@ -304,9 +304,9 @@ __global__ __launch_bounds__(BLOCK) void k_grad_partial(
             for (int i = 0; i < CPL; ++i) {
                 double c, q;
                 cis2pi_q(reduced_phase(uj, vj, wj, L[i], M[i], N[i]), c, q);
-                const double zr = fma(q, y4i, yr * c);
+                // Re z goes straight into its sum: two FMAs, no product of its own
+                z0[i] = fma(c, yr, fma(q, y4i, z0[i]));
                 const double zi = fma(q, y4r, -(yi * c));
-                z0[i] += zr;
                 zu[i] = fma(uj, zi, zu[i]);
                 zv[i] = fma(vj, zi, zv[i]);
                 zw[i] = fma(wj, zi, zw[i]);
