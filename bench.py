@@ -575,23 +575,22 @@ def main():
         extra_routes[f"tree_J{max(TREE_LEVELS)}_fp64"]["ms"] /
         extra_routes[f"tree_J{max(TREE_LEVELS)}_f32c"]["ms"], 3)
     # Eq. 16: the same model visibilities as the direct sum over the tree's
-    # merged leaves at their pixel centres (the identity the oracle pins)
-    lv = Tx.leaves()
-    LL, LM, LF = D(lv["l"]), D(lv["m"]), D(lv["flux"])
+    # merged leaves at their pixel centres (swv_predict_tree_leaves)
+    n_leaves = Tx.stats()["n_leaves"]
     out_l = torch.empty(n_vis, dtype=torch.complex128, device=dev)
-    swv.predict_direct(U, V, Wt, LL, LM, LF, out=out_l)
+    Tx.predict_leaves(U, V, Wt, out=out_l)
     times = []
     for _ in range(max(3, args.steps // 2)):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        swv.predict_direct(U, V, Wt, LL, LM, LF, out=out_l)
+        Tx.predict_leaves(U, V, Wt, out=out_l)
         e1.record()
         e1.synchronize()
         times.append(e0.elapsed_time(e1))
     ms = float(np.median(times))
     diff = float((out_l - vt[max(TREE_LEVELS)]).abs().max()) / float(np.abs(f).sum())
     extra_routes[f"tree_J{max(TREE_LEVELS)}_as_leaf_sum"] = {
-        "ms": round(ms, 4), "leaves": int(lv["pix"].size),
+        "ms": round(ms, 4), "leaves": int(n_leaves),
         "Gvis_terms_per_s": round(n_vis * n_comp / (ms * 1e-3) / 1e9, 2),
         "max_diff_vs_tree": float(f"{diff:.3e}")}
     Tx.close()

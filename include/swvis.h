@@ -184,6 +184,18 @@ int swv_tree_set_flux(swv_tree tree, const double* leaf_flux);
 int swv_predict_tree(swv_ctx ctx, swv_tree tree, int64_t n_vis, const double* u,
                      const double* v, const double* w, int sign, int prec, void* vis_out);
 
+/* The same model visibilities in the form of Eq. 16: the direct sum over the
+ * tree's merged leaves at their pixel centres,
+ *     vis_out[j] = sum_k F_k exp(s 2 pi i B_j . (s_k - P)),
+ * which Eq. 17 equals exactly (the wavelet terms of every level collapse onto
+ * the leaves they were built from).  One term per leaf instead of one per
+ * node; SWV_FP64 or SWV_F32C as in swv_predict_direct.  The leaves are copied
+ * to the device on first use with this context's device (32 bytes each) and
+ * refreshed by swv_tree_set_flux.  Arguments as swv_predict_tree. */
+int swv_predict_tree_leaves(swv_ctx ctx, swv_tree tree, int64_t n_vis, const double* u,
+                            const double* v, const double* w, int sign, int prec,
+                            void* vis_out);
+
 int swv_tree_destroy(swv_tree tree);
 
 /* ------------------------------------------------------ sphere pixels --- */

@@ -95,6 +95,7 @@ SIGNATURES = {
     "swv_tree_level": [_vp, _int, _vp, _vp, _vp, _vp],
     "swv_predict_tree": [_vp, _vp, _i64, _vp, _vp, _vp, _int, _int, _vp],
     "swv_tree_set_flux": [_vp, _vp],
+    "swv_predict_tree_leaves": [_vp, _vp, _i64, _vp, _vp, _vp, _int, _int, _vp],
     "swv_tree_destroy": [_vp],
     "swv_ang2pix": [_int, _dbl, _dbl, _i64, _vp, _vp, _vp],
     "swv_pixel_centres": [_int, _dbl, _dbl, _i64, _vp, _vp, _vp, _vp],

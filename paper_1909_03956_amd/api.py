@@ -253,6 +253,25 @@ class Tree:
                                      _ptr(out)))
         return out
 
+    def predict_leaves(self, u, v, w, sign: int = -1, prec="fp64", out=None):
+        """The same model visibilities as predict() in the form of Eq. 16: the
+        direct sum over the merged leaves at their pixel centres."""
+        u = _dev_f64(u, "u")
+        dev = u.device
+        v, w = _dev_f64(v, "v", dev), _dev_f64(w, "w", dev)
+        n = u.numel()
+        if v.numel() != n or w.numel() != n:
+            raise ValueError("length mismatch")
+        p = _prec(prec)
+        dt = torch.complex128 if p == SWV_FP64 else torch.complex64
+        if out is None:
+            out = torch.empty(n, dtype=dt, device=dev)
+        elif out.dtype != dt or out.numel() != n or not out.is_contiguous() or out.device != dev:
+            raise ValueError("out has the wrong dtype, size or device")
+        check(lib().swv_predict_tree_leaves(context(dev).handle, self._h, n, _ptr(u), _ptr(v),
+                                            _ptr(w), sign, p, _ptr(out)))
+        return out
+
     def close(self):
         if self._h:
             lib().swv_tree_destroy(self._h)

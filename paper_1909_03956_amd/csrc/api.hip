@@ -114,6 +114,40 @@ int upload_tree(swv_ctx ctx, swv_tree t, const TRec** out) {
     return SWV_OK;
 }
 
+static std::vector<Comp> packed_leaves(swv_tree t) {
+    const size_t n = t->leaf_pix.size();
+    std::vector<Comp> c(n);
+    for (size_t k = 0; k < n; ++k)
+        c[k] = Comp{t->leaf_l[k], t->leaf_m[k], t->leaf_nm1[k], t->leaf_flux[k]};
+    return c;
+}
+
+static int upload_leaves(swv_ctx ctx, swv_tree t, const Comp** out) {
+    auto it = t->device_leaves.find(ctx->device);
+    if (it != t->device_leaves.end()) {
+        *out = (const Comp*)it->second;
+        return SWV_OK;
+    }
+    const std::vector<Comp> c = packed_leaves(t);
+    void* p = nullptr;
+    const size_t bytes = c.size() * sizeof(Comp);
+    hipError_t e = hipMalloc(&p, bytes < 32 ? 32 : bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SWV_ENOMEM, "tree leaves upload: %s", hipGetErrorString(e));
+    }
+    if (bytes) {
+        e = hipMemcpy(p, c.data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(p);
+            return hip_fail(e, "tree leaves upload");
+        }
+    }
+    t->device_leaves[ctx->device] = p;
+    *out = (const Comp*)p;
+    return SWV_OK;
+}
+
 int tree_walker(swv_tree t, int preferred) {
     const bool level_ok = t->J <= kTreeMaxJ;
     const bool branch_ok = t->max_branching + 1 <= kTreeMaxSeg;
@@ -362,11 +396,12 @@ int swv_tree_set_flux(swv_tree t, const double* leaf_flux) {
         if (!std::isfinite(leaf_flux[k]))
             return fail(SWV_EDOMAIN, "swv_tree_set_flux: flux %zu is not finite", k);
     TRY_BEGIN
-    for (auto& kv : t->device_records) {   // device copies may still be read
-        DeviceGuard g(kv.first);
-        hipError_t e = hipDeviceSynchronize();
-        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    }
+    for (auto* copies : {&t->device_records, &t->device_leaves})
+        for (auto& kv : *copies) {   // device copies may still be read
+            DeviceGuard g(kv.first);
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        }
     const size_t n_rec = t->records.size();
     std::copy(leaf_flux, leaf_flux + n, t->leaf_flux.begin());
     build_coefficients(t);
@@ -376,6 +411,15 @@ int swv_tree_set_flux(swv_tree t, const double* leaf_flux) {
         hipError_t e = hipMemcpy(kv.second, t->records.data(), n_rec * sizeof(TRec),
                                  hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "swv_tree_set_flux upload");
+    }
+    if (!t->device_leaves.empty()) {
+        const std::vector<Comp> c = packed_leaves(t);
+        for (auto& kv : t->device_leaves) {
+            DeviceGuard g(kv.first);
+            hipError_t e = hipMemcpy(kv.second, c.data(), c.size() * sizeof(Comp),
+                                     hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(e, "swv_tree_set_flux upload");
+        }
     }
     return SWV_OK;
     TRY_END
@@ -409,13 +453,38 @@ int swv_predict_tree(swv_ctx ctx, swv_tree t, int64_t n_vis, const double* u, co
     TRY_END
 }
 
+int swv_predict_tree_leaves(swv_ctx ctx, swv_tree t, int64_t n_vis, const double* u,
+                            const double* v, const double* w, int sign, int prec,
+                            void* vis_out) {
+    CHECK_CTX(ctx);
+    if (!t) return fail(SWV_EINVAL, "swv_predict_tree_leaves: null tree");
+    if (n_vis < 0) return fail(SWV_EINVAL, "swv_predict_tree_leaves: negative n_vis");
+    NEED(u, n_vis); NEED(v, n_vis); NEED(w, n_vis); NEED(vis_out, n_vis);
+    int rc = check_sign_prec(sign, prec, true);
+    if (rc) return rc;
+    if (n_vis == 0) return SWV_OK;
+    TRY_BEGIN
+    GUARD(ctx);
+    const Comp* comp = nullptr;
+    rc = upload_leaves(ctx, t, &comp);
+    if (rc) return rc;
+    const int fam = prec == SWV_FP64 ? kFamDirect64 : kFamDirect32;
+    const int sc = size_class(n_vis);
+    HIPCALL(launch_direct(ctx->stream, prec, ctx->per_lane[fam][sc], ctx->block[fam][sc], n_vis,
+                          u, v, w, comp, (int64_t)t->leaf_pix.size(), sign, vis_out,
+                          ctx->d_status));
+    return SWV_OK;
+    TRY_END
+}
+
 int swv_tree_destroy(swv_tree t) {
     if (!t) return SWV_OK;
-    for (auto& kv : t->device_records) {
-        DeviceGuard g(kv.first);
-        (void)hipDeviceSynchronize();
-        (void)hipFree(kv.second);
-    }
+    for (auto* copies : {&t->device_records, &t->device_leaves})
+        for (auto& kv : *copies) {
+            DeviceGuard g(kv.first);
+            (void)hipDeviceSynchronize();
+            (void)hipFree(kv.second);
+        }
     delete t;
     return SWV_OK;
 }

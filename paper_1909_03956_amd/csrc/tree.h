@@ -38,6 +38,9 @@ struct swv_tree_s {
     double build_seconds = 0;
     // device copies of `records`, one per HIP device id
     std::map<int, void*> device_records;
+    // device copies of the leaves packed as direct-sum components (l, m, n - 1,
+    // flux), one per HIP device id (swv_predict_tree_leaves)
+    std::map<int, void*> device_leaves;
 };
 
 namespace swv {

@@ -304,3 +304,52 @@ def test_tree_f32c_out_dtype_checked(env):
     x = dev(np.ones(4), torch)
     with pytest.raises(ValueError):
         t.predict(x, x, x, prec="f32c", out=torch.empty(4, dtype=torch.complex128, device="cuda"))
+
+
+# ------------------------------------------------ Eq. 16 form (leaf sum) --
+@pytest.mark.parametrize("J", [8, 10])
+def test_leaf_sum_equals_tree_and_oracle(env, J):
+    """swv_predict_tree_leaves (Eq. 16) against the traversal at every cfg2
+    row and against the oracle's snapped direct sum on sampled rows."""
+    torch, swv = env
+    W = configs.CFG2
+    u, v, w = W.track.uvw()
+    U, V, Wt = dev(u, torch), dev(v, torch), dev(w, torch)
+    l, m, f = W.components()
+    t = swv.Tree(J, W.ra_p, W.dec_p, l, m, f)
+    vt = t.predict(U, V, Wt)
+    vl = t.predict_leaves(U, V, Wt)
+    swv.synchronize()
+    d = (vt - vl).abs().max().item() / float(np.abs(f).sum())
+    rows = configs.sample_rows(u.size, 2048, seed=J + 50)
+    ref_t = ot.build_tree(J, W.ra_p, W.dec_p, l, m, f)
+    ref = ot.predict_snapped(ref_t, u[rows], v[rows], w[rows])
+    e_max, _ = errors(host(vl[torch.as_tensor(rows, device="cuda")]), ref, f.sum())
+    note(f"cfg2 J={J} leaf sum: vs traversal {d:.3e}, vs oracle {e_max:.3e}")
+    assert d <= TOL64 and e_max <= TOL64
+    v32 = host(t.predict_leaves(U, V, Wt, prec="f32c"))
+    assert v32.dtype == np.complex64
+    assert errors(v32[rows], ref, f.sum())[0] <= 1e-6
+
+
+def test_leaf_sum_follows_set_flux_and_needs_no_walker(env):
+    torch, swv = env
+    # a tree the traversals do not support (16 nested branchings) still sums
+    l, m = _nested_components(14)
+    rng = np.random.default_rng(8)
+    f = rng.lognormal(-3, 1, l.size)
+    t = swv.Tree(29, 0.3, 0.4, l, m, f)
+    assert t.stats()["max_branching"] == 16
+    u, v, w = (rng.uniform(-4.6e5, 4.6e5, 700) for _ in range(3))
+    U, V, Wt = dev(u, torch), dev(v, torch), dev(w, torch)
+    got = host(t.predict_leaves(U, V, Wt))
+    rt = ot.build_tree(29, 0.3, 0.4, l, m, f)
+    bound = fp64_row_bound(u, v, w, rt.leaf_l, rt.leaf_m, rt.leaf_nm1, rt.leaf_flux)
+    assert np.all(np.abs(got - ot.predict_snapped(rt, u, v, w)) <= bound)
+    # new leaf fluxes reach the device copy of the leaves
+    f2 = rng.lognormal(-3, 1, t.stats()["n_leaves"])
+    t.set_leaf_flux(f2)
+    rt.leaf_flux = f2
+    got2 = host(t.predict_leaves(U, V, Wt))
+    bound2 = fp64_row_bound(u, v, w, rt.leaf_l, rt.leaf_m, rt.leaf_nm1, f2)
+    assert np.all(np.abs(got2 - ot.predict_snapped(rt, u, v, w)) <= bound2)
