@@ -292,6 +292,15 @@ def run_clean(swv, torch, np, dev, configs):
                         "ms_predict": [round(c["ms_predict"], 4) for c in o["cycles"]],
                         "model_pixels": [c["leaves"] for c in o["cycles"]],
                         "residual_rms": float(f"{float(o['residual'].std()):.6g}")}
+    # the wavelet clean with FP32-compensated images (beam and residual images)
+    t0 = time.perf_counter()
+    o = swv.wavelet_clean(*args, image_prec="f32c")
+    others["tree_f32c_images"] = {
+        "wall_ms": round(1e3 * (time.perf_counter() - t0), 2),
+        "beam_ms": round(o["ms_beam"], 3),
+        "ms_image": [round(c["ms_image"], 4) for c in o["cycles"]],
+        "chi2": [round(c["chi2"], 4) for c in o["cycles"]],
+        "residual_rms": float(f"{float(o['residual'].std()):.6g}")}
     cyc = out["cycles"]
     iters = sum(c["found"] for c in cyc)
     ms_minor = sum(c["ms_minor"] for c in cyc)

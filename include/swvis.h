@@ -283,11 +283,13 @@ int swv_image_grid(swv_ctx ctx, int nx, int ny, int cx, int cy, double cell, dou
  * Pixels whose direction is off the unit disk are 0.  y [n_vis] DEVICE
  * complex128; img_out [nx * ny] DEVICE FP64.  With y = NULL the visibilities
  * are all 1: on the beam grid (cx = nx' - 1 of an nx' image) that is the
- * dirty beam B_D, the image of a unit source at the phase centre.  Uses
- * 40 * nx * ny bytes of device scratch plus the adjoint's workspace. */
+ * dirty beam B_D, the image of a unit source at the phase centre.  prec is
+ * the adjoint's: SWV_FP64, or SWV_F32C (FP32 phasors and Kahan sums, about
+ * twice as fast, relative error up to ~1e-6).  Uses 40 * nx * ny bytes of
+ * device scratch plus the adjoint's workspace. */
 int swv_dirty_image(swv_ctx ctx, int64_t n_vis, const double* u, const double* v,
                     const double* w, const void* y, int nx, int ny, int cx, int cy,
-                    double cell, int sign, double* img_out);
+                    double cell, int sign, int prec, double* img_out);
 
 /* Hogbom minor cycle (section 2.1, Eqs. 4 and 5) on image [ny][nx] (DEVICE,
  * updated in place to the residual) with beam [2 ny - 1][2 nx - 1] (DEVICE,
@@ -352,6 +354,9 @@ typedef struct {
     int predictor;        /* SWV_PREDICT_TREE (the wavelet clean), SWV_PREDICT_DEGRID or
                              SWV_PREDICT_DIRECT */
     int support;          /* kernel width W of SWV_PREDICT_DEGRID */
+    int image_prec;       /* precision of the dirty image and every residual image:
+                             SWV_FP64 or SWV_F32C (see swv_dirty_image); the dirty
+                             beam is always FP64 */
 } swv_clean_params_t;
 
 /* Model-visibility predictor of the major cycles.  TREE: the tree of every

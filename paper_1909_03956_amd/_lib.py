@@ -59,7 +59,7 @@ class CleanParams(C.Structure):
                 ("ra_p", C.c_double), ("dec_p", C.c_double), ("gain", C.c_double),
                 ("threshold", C.c_double), ("minor_iter", C.c_int64), ("n_major", C.c_int),
                 ("flags", C.c_int), ("sign", C.c_int), ("predictor", C.c_int),
-                ("support", C.c_int)]
+                ("support", C.c_int), ("image_prec", C.c_int)]
 
 
 _NC = SWV_CLEAN_MAX_CYCLES
@@ -117,7 +117,8 @@ SIGNATURES = {
     "swv_tune_set": [_vp, _int, _int, _int, _int],
     "swv_measure_peaks": [_vp, _vp],
     "swv_image_grid": [_vp, _int, _int, _int, _int, _dbl, _vp, _vp, _vp],
-    "swv_dirty_image": [_vp, _i64, _vp, _vp, _vp, _vp, _int, _int, _int, _int, _dbl, _int, _vp],
+    "swv_dirty_image": [_vp, _i64, _vp, _vp, _vp, _vp, _int, _int, _int, _int, _dbl, _int, _int,
+                        _vp],
     "swv_hogbom": [_vp, _int, _int, _vp, _vp, _dbl, _dbl, _i64, _int, _vp, _vp, _vp],
     "swv_cross_reference": [_int, _dbl, _dbl, _int, _int, _dbl, _vp],
     "swv_tree_build_pixels": [_int, _dbl, _dbl, _i64, _vp, _vp, _pvp],

@@ -412,9 +412,11 @@ def image_grid(nx: int, ny: int, cell: float, cx=None, cy=None, device=None):
     return l, m, nm1
 
 
-def dirty_image(u, v, w, y, nx: int, ny: int, cell: float, cx=None, cy=None, sign: int = -1):
+def dirty_image(u, v, w, y, nx: int, ny: int, cell: float, cx=None, cy=None, sign: int = -1,
+                prec="fp64"):
     """(1 / N_vis) Re sum_j conj(e_jp) y_j on an (ny, nx) grid; y None means
-    unit visibilities.  Returns a (ny, nx) float64 tensor."""
+    unit visibilities; prec "f32c" takes the adjoint's FP32-compensated form.
+    Returns a (ny, nx) float64 tensor."""
     u, v, w, dev = _uvw(u, v, w)
     yp = C.c_void_p(0)
     if y is not None:
@@ -426,15 +428,16 @@ def dirty_image(u, v, w, y, nx: int, ny: int, cell: float, cx=None, cy=None, sig
     cy = int(ny) // 2 if cy is None else int(cy)
     out = torch.empty((int(ny), int(nx)), dtype=torch.float64, device=dev)
     check(lib().swv_dirty_image(context(dev).handle, u.numel(), _ptr(u), _ptr(v), _ptr(w), yp,
-                                int(nx), int(ny), cx, cy, float(cell), int(sign), _ptr(out)))
+                                int(nx), int(ny), cx, cy, float(cell), int(sign), _prec(prec),
+                                _ptr(out)))
     return out
 
 
-def dirty_beam(u, v, w, nx: int, ny: int, cell: float, sign: int = -1):
+def dirty_beam(u, v, w, nx: int, ny: int, cell: float, sign: int = -1, prec="fp64"):
     """Dirty beam of an (ny, nx) image: the (2 ny - 1, 2 nx - 1) image of a
     unit source at the phase centre, zero offset at (ny - 1, nx - 1)."""
     return dirty_image(u, v, w, None, 2 * int(nx) - 1, 2 * int(ny) - 1, cell, int(nx) - 1,
-                       int(ny) - 1, sign)
+                       int(ny) - 1, sign, prec)
 
 
 def hogbom(image, beam, gain: float, threshold: float, max_iter: int, absolute=False,
@@ -528,11 +531,12 @@ def predict_degrid(image, u, v, w, cell: float, support: int = 10, sign: int = -
 def wavelet_clean(u, v, w, vis_obs, nx: int, ny: int, cell: float, J: int, ra_p: float,
                   dec_p: float, gain: float = 0.1, threshold: float = 0.0, minor_iter: int = 100,
                   n_major: int = 1, absolute=False, sign: int = -1, predictor: str = "tree",
-                  support: int = 10):
+                  support: int = 10, image_prec="fp64"):
     """Cotton-Schwab cleaning with the wavelet predictor (sections 2.2, 3.5);
     predictor "degrid" (FFT + degridding of the model image, kernel width
     `support`) or "direct" (direct sum over the model pixels) runs the same
-    loop as conventional or exact clean.  Returns a dict: pix, val (numpy, all
+    loop as conventional or exact clean; image_prec "f32c" forms the dirty and
+    residual images with the FP32-compensated adjoint (the beam stays FP64).  Returns a dict: pix, val (numpy, all
     components in order), residual and beam (device images), vis_model
     (device complex128) and per-cycle stats."""
     if predictor not in PREDICTORS:
@@ -545,7 +549,7 @@ def wavelet_clean(u, v, w, vis_obs, nx: int, ny: int, cell: float, J: int, ra_p:
     P = CleanParams(int(nx), int(ny), float(cell), int(J), float(ra_p), float(dec_p),
                     float(gain), float(threshold), int(minor_iter), int(n_major),
                     SWV_HOGBOM_ABS if absolute else 0, int(sign), PREDICTORS[predictor],
-                    int(support))
+                    int(support), _prec(image_prec))
     beam = torch.empty((2 * int(ny) - 1, 2 * int(nx) - 1), dtype=torch.float64, device=dev)
     resid = torch.empty((int(ny), int(nx)), dtype=torch.float64, device=dev)
     vm = torch.empty(n, dtype=torch.complex128, device=dev)

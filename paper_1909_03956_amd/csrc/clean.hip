@@ -443,12 +443,14 @@ extern "C" int swv_image_grid(swv_ctx ctx, int nx, int ny, int cx, int cy, doubl
 
 extern "C" int swv_dirty_image(swv_ctx ctx, int64_t n_vis, const double* u, const double* v,
                                const double* w, const void* y, int nx, int ny, int cx, int cy,
-                               double cell, int sign, double* img_out) {
+                               double cell, int sign, int prec, double* img_out) {
     CLEAN_CHECK_CTX(ctx);
     CLEAN_RC(check_grid(nx, ny, cell));
     if (n_vis < 1) return fail(SWV_EINVAL, "swv_dirty_image: no visibilities");
     if (!u || !v || !w || !img_out) return fail(SWV_EINVAL, "swv_dirty_image: null argument");
     if (sign != 1 && sign != -1) return fail(SWV_EDOMAIN, "sign must be +1 or -1 (got %d)", sign);
+    if (prec != SWV_FP64 && prec != SWV_F32C)
+        return fail(SWV_EINVAL, "swv_dirty_image: unsupported precision %d", prec);
     CLEAN_GUARD(ctx);
     const int64_t n = (int64_t)nx * ny;
     CLEAN_RC(ensure(ctx, ctx->grid, 40 * (size_t)n));
@@ -469,7 +471,7 @@ extern "C" int swv_dirty_image(swv_ctx ctx, int64_t n_vis, const double* u, cons
     }
     k_grid<<<grid_blocks(n), kGridBlock, 0, ctx->stream>>>(n, nx, cx, cy, cell, gl, gm, gn);
     CLEAN_HIP(hipGetLastError());
-    CLEAN_RC(swv_adjoint(ctx, n_vis, u, v, w, yy, n, gl, gm, gn, sign, SWV_FP64, gx));
+    CLEAN_RC(swv_adjoint(ctx, n_vis, u, v, w, yy, n, gl, gm, gn, sign, prec, gx));
     k_real_image<<<grid_blocks(n), kGridBlock, 0, ctx->stream>>>(n, gx, nx, cx, cy, cell,
                                                                  (double)n_vis, img_out);
     CLEAN_HIP(hipGetLastError());
@@ -638,6 +640,9 @@ extern "C" int swv_wavelet_clean(swv_ctx ctx, const swv_clean_params_t* P, int64
     if (P->predictor != SWV_PREDICT_TREE && P->predictor != SWV_PREDICT_DEGRID &&
         P->predictor != SWV_PREDICT_DIRECT)
         return fail(SWV_EINVAL, "swv_wavelet_clean: unknown predictor %d", P->predictor);
+    if (P->image_prec != SWV_FP64 && P->image_prec != SWV_F32C)
+        return fail(SWV_EINVAL, "swv_wavelet_clean: unsupported image precision %d",
+                    P->image_prec);
     if (P->predictor == SWV_PREDICT_DEGRID && (P->support < 2 || P->support > 16))
         return fail(SWV_EINVAL, "swv_wavelet_clean: support %d outside 2 .. 16", P->support);
     if (!std::isfinite(P->gain) || std::isnan(P->threshold))
@@ -675,11 +680,12 @@ extern "C" int swv_wavelet_clean(swv_ctx ctx, const swv_clean_params_t* P, int64
         };
         double scratch_ms = 0.0;
         CLEAN_HIP(hipEventRecord(S.ev[0], s));
+        // the beam once, in FP64 (its FP32C form is no faster at this many pixels)
         CLEAN_RC(swv_dirty_image(ctx, n_vis, u, v, w, nullptr, 2 * nx - 1, 2 * ny - 1, nx - 1,
-                                 ny - 1, P->cell, P->sign, beam));
+                                 ny - 1, P->cell, P->sign, SWV_FP64, beam));
         CLEAN_RC(lap(stats ? &stats->ms_beam : &scratch_ms));
         CLEAN_RC(swv_dirty_image(ctx, n_vis, u, v, w, vis_obs, nx, ny, nx / 2, ny / 2, P->cell,
-                                 P->sign, residual));
+                                 P->sign, P->image_prec, residual));
         CLEAN_RC(lap(stats ? &stats->ms_dirty : &scratch_ms));
         CLEAN_HIP(hipMemsetAsync(vis_model, 0, 16 * (size_t)n_vis, s));
         int64_t total = 0;
@@ -767,7 +773,7 @@ extern "C" int swv_wavelet_clean(swv_ctx ctx, const swv_clean_params_t* P, int64
             CLEAN_RC(lap(&ms_predict));
             CLEAN_RC(swv_residual_chi2(ctx, n_vis, vis_obs, vis_model, 1.0, S.p[2], d_chi2));
             CLEAN_RC(swv_dirty_image(ctx, n_vis, u, v, w, S.p[2], nx, ny, nx / 2, ny / 2,
-                                     P->cell, P->sign, residual));
+                                     P->cell, P->sign, P->image_prec, residual));
             double chi2 = 0.0;
             CLEAN_HIP(hipMemcpyAsync(&chi2, d_chi2, 8, hipMemcpyDeviceToHost, s));
             CLEAN_RC(lap(&ms_image));

@@ -338,3 +338,31 @@ def test_restore_of_the_loop_output(env, small):
     rimg = oc.restore(n, n, ref["pix"], ref["val"], oc.fit_clean_beam(ref["beam"]),
                       ref["residual"])
     assert np.abs(img - rimg).max() <= 1e-9 * np.abs(ref["val"]).sum()
+
+
+def test_f32c_images(env, small):
+    """The FP32-compensated dirty image and beam against the oracle (1e-6 bar),
+    and the whole loop with FP32C images against the oracle's FP64 loop."""
+    torch, swv = env
+    S, u, v, w, vis = small
+    n = S.n_pix
+    U, V, W, Y = dev(u, torch), dev(v, torch), dev(w, torch), dev_c(vis, torch)
+    img = host(swv.dirty_image(U, V, W, Y, n, n, S.cell, prec="f32c")).ravel()
+    l, m, nm1, _ = oc.image_grid(n, n, S.cell)
+    ref = oc.dirty_image(u, v, w, vis, l, m, nm1)
+    e = np.abs(img - ref).max() / (np.abs(vis).sum() / u.size)
+    beam = host(swv.dirty_beam(U, V, W, n, n, S.cell, prec="f32c"))
+    eb = np.abs(beam - oc.dirty_beam(u, v, w, n, n, S.cell)).max()
+    note(f"clean_small f32c dirty image E_max={e:.2e}, beam {eb:.2e}")
+    assert e <= 1e-6 and eb <= 1e-6
+    got = swv.wavelet_clean(U, V, W, Y, n, n, S.cell, S.J, S.ra_p, S.dec_p, S.gain, 0.0,
+                            S.minor_iter, S.n_major, image_prec="f32c")
+    ref = oc.wavelet_clean(u, v, w, vis, n, n, S.cell, S.J, S.ra_p, S.dec_p, S.gain, 0.0,
+                           S.minor_iter, S.n_major)
+    same = np.mean(got["pix"] == ref["pix"])
+    note(f"clean_small f32c loop: {same:.3f} of the components on the oracle's pixels; "
+         f"chi2 {[c['chi2'] for c in got['cycles']]} vs {[c['chi2'] for c in ref['cycles']]}")
+    assert same >= 0.9
+    assert abs(got["val"].sum() - ref["val"].sum()) <= 1e-4 * np.abs(ref["val"]).sum()
+    for cg, cr in zip(got["cycles"], ref["cycles"]):
+        assert abs(cg["chi2"] - cr["chi2"]) <= 1e-3 * cr["chi2"]
