@@ -454,10 +454,11 @@ extern "C" int swv_dirty_image(swv_ctx ctx, int64_t n_vis, const double* u, cons
     CLEAN_GUARD(ctx);
     const int64_t n = (int64_t)nx * ny;
     CLEAN_RC(ensure(ctx, ctx->grid, 40 * (size_t)n));
-    double* gl = (double*)ctx->grid.p;
+    // the complex adjoint output first, so that it is 16-byte aligned for any n
+    double2* gx = (double2*)ctx->grid.p;
+    double* gl = (double*)(gx + n);
     double* gm = gl + n;
     double* gn = gm + n;
-    double2* gx = (double2*)(gn + n);
     const double2* yy = (const double2*)y;
     if (!yy) {
         if (ctx->ones.n < 16 * (size_t)n_vis) {
