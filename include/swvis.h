@@ -445,7 +445,8 @@ int swv_predict_degrid(swv_ctx ctx, int nx, int ny, double cell, const double* i
 /* One prediction instance (a channel x pointing), all pointers DEVICE except
  * `tree`.  route SWV_ROUTE_DIRECT uses (n_comp, l, m, flux); SWV_ROUTE_TREE
  * uses `tree`.  vis_out is complex128 (SWV_FP64) or complex64 (SWV_F32C,
- * direct route only). */
+ * either route; the library cannot check the buffer's type: a complex64
+ * buffer under SWV_FP64 is written past its end). */
 typedef struct {
     int route;
     int prec;
@@ -471,7 +472,8 @@ typedef struct {
     int block_threads;
 } swv_plan_stats_t;
 
-/* Plans one persistent launch per route over many instances: packs every
+/* Plans one persistent launch per route (and, for trees, per precision) over
+ * many instances: packs every
  * instance's components (direct) and uploads every tree, splits each
  * instance into visibility tiles and orders the (instance, tile) work items
  * by decreasing cost (longest-processing-time first).  Workgroups take items

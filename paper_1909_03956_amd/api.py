@@ -600,7 +600,7 @@ class BatchPlan:
     """One persistent launch per route over many prediction instances.
 
     instances: dicts with keys route ("direct" | "tree"), u, v, w (float64 GPU
-    tensors), out (complex128, or complex64 for a "f32c" direct instance),
+    tensors), out (complex128, or complex64 for a "f32c" instance),
     sign (default -1), prec (default "fp64"), and l, m, flux (float64 GPU
     tensors, direct) or tree (a Tree).  The tensors and trees must outlive the
     plan; the plan keeps references to them."""
@@ -620,6 +620,9 @@ class BatchPlan:
             I = arr[k]
             I.route = ROUTES[d.get("route", "direct")]
             I.prec = _prec(d.get("prec", "fp64"))
+            want = torch.complex128 if I.prec == SWV_FP64 else torch.complex64
+            if out.dtype != want or out.device != u.device:
+                raise TypeError(f"instance {k}: out must be {want} on {u.device}")
             I.sign = int(d.get("sign", -1))
             I.n_vis = n
             I.u, I.v, I.w = _ptr(u).value, _ptr(v).value, _ptr(w).value

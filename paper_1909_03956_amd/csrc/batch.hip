@@ -21,11 +21,12 @@ struct swv_plan_s {
     BatchInst* d_direct = nullptr;
     BatchInst* d_tree = nullptr;
     WorkItem* d_items_direct = nullptr;
-    WorkItem* d_items_tree = nullptr;
-    unsigned n_items_direct = 0, n_items_tree = 0;
+    WorkItem* d_items_tree = nullptr;     // FP64 tree instances
+    WorkItem* d_items_tree32 = nullptr;   // F32C tree instances
+    unsigned n_items_direct = 0, n_items_tree = 0, n_items_tree32 = 0;
     Comp* d_pack = nullptr;
-    unsigned* d_counters = nullptr;  // [0] direct, [1] tree
-    int vpl = 2, block = 256, grid_direct = 0, grid_tree = 0, max_comp = 0;
+    unsigned* d_counters = nullptr;  // [0] direct, [1] tree FP64, [2] tree F32C
+    int vpl = 2, block = 256, grid_direct = 0, grid_tree = 0, grid_tree32 = 0, max_comp = 0;
     int jmax = 1, smax = 1;           // largest J and segment depth of the trees
     int tree_walker = 0, tree_depth = 1;
     int tile_rows = 0;
@@ -66,7 +67,8 @@ void plan_release(swv_plan p) {
         DeviceGuard g(ctx->device);
         (void)hipStreamSynchronize(ctx->stream);
         for (void* q : {(void*)p->d_direct, (void*)p->d_tree, (void*)p->d_items_direct,
-                        (void*)p->d_items_tree, (void*)p->d_pack, (void*)p->d_counters})
+                        (void*)p->d_items_tree,
+                        (void*)p->d_items_tree32, (void*)p->d_pack, (void*)p->d_counters})
             if (q) (void)hipFree(q);
     }
     delete p;
@@ -75,7 +77,8 @@ void plan_release(swv_plan p) {
 
 void free_plan_device(swv_plan p) {
     for (void* q : {(void*)p->d_direct, (void*)p->d_tree, (void*)p->d_items_direct,
-                    (void*)p->d_items_tree, (void*)p->d_pack, (void*)p->d_counters})
+                    (void*)p->d_items_tree,
+                        (void*)p->d_items_tree32, (void*)p->d_pack, (void*)p->d_counters})
         if (q) (void)hipFree(q);
 }
 
@@ -84,14 +87,19 @@ hipError_t enqueue_plan(swv_plan p, hipStream_t s) {
     hipError_t e = launch_batch_ingest(s, p->d_direct, (int)p->direct.size(), p->max_comp,
                                        p->d_pack, p->ctx->d_status);
     if (e != hipSuccess) return e;
-    e = launch_reset_counters(s, p->d_counters, 2);
+    e = launch_reset_counters(s, p->d_counters, 3);
     if (e != hipSuccess) return e;
     e = launch_batch_direct(s, p->vpl, p->block, p->grid_direct, p->d_direct, p->d_pack,
                             p->d_items_direct, p->n_items_direct, p->d_counters,
                             p->ctx->d_status);
     if (e != hipSuccess) return e;
-    return launch_batch_tree(s, p->tree_walker, p->tree_depth, p->grid_tree, p->scales, p->d_tree, p->d_items_tree,
-                             p->n_items_tree, p->d_counters + 1, p->ctx->d_status);
+    e = launch_batch_tree(s, p->tree_walker, p->tree_depth, SWV_FP64, p->grid_tree, p->scales,
+                          p->d_tree, p->d_items_tree, p->n_items_tree, p->d_counters + 1,
+                          p->ctx->d_status);
+    if (e != hipSuccess) return e;
+    return launch_batch_tree(s, p->tree_walker, p->tree_depth, SWV_F32C, p->grid_tree32,
+                             p->scales, p->d_tree, p->d_items_tree32, p->n_items_tree32,
+                             p->d_counters + 2, p->ctx->d_status);
 }
 
 int check_instance(const swv_instance& I, int k) {
@@ -111,8 +119,8 @@ int check_instance(const swv_instance& I, int k) {
             return fail(SWV_EINVAL, "instance %d: null component pointer", k);
     } else {
         if (!I.tree) return fail(SWV_EINVAL, "instance %d: null tree", k);
-        if (I.prec != SWV_FP64)
-            return fail(SWV_ENOTSUP, "instance %d: the tree route is FP64 only", k);
+        if (I.prec != SWV_FP64 && I.prec != SWV_F32C)
+            return fail(SWV_EINVAL, "instance %d: bad precision %d", k, I.prec);
         if (tree_walker(I.tree, 1) < 0)
             return fail(SWV_ENOTSUP,
                         "instance %d: J = %d with %d nested branchings: above the compiled "
@@ -203,7 +211,8 @@ int swv_batch_plan(swv_ctx ctx, int n, const swv_instance* inst, swv_plan* out) 
 
         // persistent grids: as many blocks as stay resident
         p->grid_direct = ctx->n_cu * batch_direct_blocks_per_cu(p->vpl, p->block);
-        p->grid_tree = ctx->n_cu * batch_tree_blocks_per_cu(p->tree_walker, p->tree_depth);
+        p->grid_tree = ctx->n_cu * batch_tree_blocks_per_cu(p->tree_walker, p->tree_depth, SWV_FP64);
+        p->grid_tree32 = ctx->n_cu * batch_tree_blocks_per_cu(p->tree_walker, p->tree_depth, SWV_F32C);
         const int64_t waves = (int64_t)p->grid_direct * (p->block / 64);
         // about 16 items per resident wave, in whole wave tiles, at most 64 of them
         const int64_t unit = 64LL * p->vpl;
@@ -233,18 +242,23 @@ int swv_batch_plan(swv_ctx ctx, int n, const swv_instance* inst, swv_plan* out) 
         };
         const std::vector<WorkItem> wd = make_items(p->direct, cost_per_row_direct, tile);
         const int64_t tree_tile = std::max<int64_t>(64, tile / p->vpl / 64 * 64);
-        const std::vector<WorkItem> wt = make_items(p->tree, cost_per_row_tree, tree_tile);
-        if (wd.size() > 0xffffffffull || wt.size() > 0xffffffffull) {
+        // tree items by precision (one launch each), keeping the cost order
+        std::vector<WorkItem> wt, wt32;
+        for (const WorkItem& it : make_items(p->tree, cost_per_row_tree, tree_tile))
+            (p->tree[(size_t)it.inst].prec == SWV_F32C ? wt32 : wt).push_back(it);
+        if (wd.size() > 0xffffffffull || wt.size() > 0xffffffffull || wt32.size() > 0xffffffffull) {
             delete p;
             return fail(SWV_ENOTSUP, "swv_batch_plan: too many work items");
         }
         p->n_items_direct = (unsigned)wd.size();
         p->n_items_tree = (unsigned)wt.size();
+        p->n_items_tree32 = (unsigned)wt32.size();
 
         int rc = dev_upload(p->direct, &p->d_direct);
         if (!rc) rc = dev_upload(p->tree, &p->d_tree);
         if (!rc) rc = dev_upload(wd, &p->d_items_direct);
         if (!rc) rc = dev_upload(wt, &p->d_items_tree);
+        if (!rc) rc = dev_upload(wt32, &p->d_items_tree32);
         if (!rc) {
             std::vector<Comp> none;
             none.resize((size_t)std::max<int64_t>(off, 1));
@@ -256,7 +270,7 @@ int swv_batch_plan(swv_ctx ctx, int n, const swv_instance* inst, swv_plan* out) 
             }
         }
         if (!rc) {
-            hipError_t e = hipMalloc((void**)&p->d_counters, 2 * sizeof(unsigned));
+            hipError_t e = hipMalloc((void**)&p->d_counters, 3 * sizeof(unsigned));
             if (e != hipSuccess) {
                 (void)hipGetLastError();
                 p->d_counters = nullptr;
@@ -284,7 +298,7 @@ int swv_batch_plan(swv_ctx ctx, int n, const swv_instance* inst, swv_plan* out) 
 int swv_plan_stats(swv_plan p, swv_plan_stats_t* out) {
     if (!p || !out) return fail(SWV_EINVAL, "swv_plan_stats: null argument");
     out->n_instances = p->n_inst;
-    out->n_items = (int64_t)p->n_items_direct + p->n_items_tree;
+    out->n_items = (int64_t)p->n_items_direct + p->n_items_tree + p->n_items_tree32;
     out->total_terms = p->total_terms;
     out->tile_rows = p->tile_rows;
     out->grid_blocks = p->grid_direct;

@@ -88,7 +88,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch_direct(const BatchInst* __restr
     }
 }
 
-template <int JMAX, int WALKER>
+// PREC: SWV_FP64 (complex128 out) or SWV_F32C (FP32 leaf phasors, complex64
+// out), exactly as the single-instance tree kernel writes them.
+template <int JMAX, int WALKER, int PREC>
 __global__ __launch_bounds__(kBatchTreeBlock) void k_batch_tree(
     TreeArgs scales, const BatchInst* __restrict__ inst, const WorkItem* __restrict__ items,
     unsigned n_items, unsigned* __restrict__ counter, int* __restrict__ status) {
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(kBatchTreeBlock) void k_batch_tree(
         const double* u = IN[ii].u;
         const double* v = IN[ii].v;
         const double* w = IN[ii].w;
-        double2* out = (double2*)IN[ii].out;
+        void* out = IN[ii].out;
         const TRec* rec = IN[ii].rec;
         const int n_roots = IN[ii].n_roots, J = IN[ii].J;
         const double s4 = 4.0 * IN[ii].sgn;
@@ -117,11 +119,14 @@ __global__ __launch_bounds__(kBatchTreeBlock) void k_batch_tree(
             const int64_t j = jr < limit ? jr : limit - 1;
             const double U = u[j], V = v[j], W = w[j];
             double Vr, Vi;
-            tree_row<JMAX, WALKER, LDSL, kBatchTreeBlock>(rec, n_roots, J, scales, (LdsPtr)sums, U, V, W,
-                                                           Vr, Vi);
+            tree_row<JMAX, WALKER, LDSL, kBatchTreeBlock, PREC == SWV_F32C>(
+                rec, n_roots, J, scales, (LdsPtr)sums, U, V, W, Vr, Vi);
             if (jr < limit) {
                 if (!isfinite(U + V + W)) atomicOr(status, kStatusNonFinite);
-                out[jr] = make_double2(Vr, s4 * Vi);
+                if constexpr (PREC == SWV_F32C)
+                    ((float2*)out)[jr] = make_float2((float)Vr, (float)(s4 * Vi));
+                else
+                    ((double2*)out)[jr] = make_double2(Vr, s4 * Vi);
             }
         }
     }
@@ -145,10 +150,10 @@ int batch_direct_blocks_per_cu(int vpl, int block) {
     return 1;
 }
 
-template <int JMAX, int WALKER>
+template <int JMAX, int WALKER, int PREC>
 static int tree_occupancy() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_tree<JMAX, WALKER>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_tree<JMAX, WALKER, PREC>,
                                                      kBatchTreeBlock, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
@@ -160,8 +165,10 @@ static int tree_occupancy() {
     X(1, 1) X(2, 1) X(3, 1) X(4, 1) X(5, 1) X(6, 1) X(7, 1) X(8, 1) X(9, 1) X(10, 1)  \
     X(11, 1) X(12, 1) X(13, 1) X(14, 1) X(15, 1) X(16, 1)
 
-int batch_tree_blocks_per_cu(int walker, int depth) {
-#define SWV_OCC_T(D, W) if (walker == W && depth == D) return tree_occupancy<D, W>();
+int batch_tree_blocks_per_cu(int walker, int depth, int prec) {
+#define SWV_OCC_T(D, W)                                                                  \
+    if (walker == W && depth == D)                                                       \
+        return prec == SWV_F32C ? tree_occupancy<D, W, SWV_F32C>() : tree_occupancy<D, W, SWV_FP64>();
     SWV_TREE_SHAPES(SWV_OCC_T)
 #undef SWV_OCC_T
     return 1;
@@ -184,16 +191,21 @@ hipError_t launch_batch_direct(hipStream_t s, int vpl, int block, int grid,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_batch_tree(hipStream_t s, int walker, int depth, int grid,
+hipError_t launch_batch_tree(hipStream_t s, int walker, int depth, int prec, int grid,
                              const TreeArgs& scales, const BatchInst* inst,
                              const WorkItem* items, unsigned n_items, unsigned* counter,
                              int* status) {
     if (n_items == 0) return hipSuccess;
     const dim3 g(grid), b(kBatchTreeBlock);
-#define SWV_RUN_T(D, W)                                                                 \
-    if (walker == W && depth == D) {                                                    \
-        k_batch_tree<D, W><<<g, b, 0, s>>>(scales, inst, items, n_items, counter, status); \
-        return hipGetLastError();                                                       \
+#define SWV_RUN_T(D, W)                                                                    \
+    if (walker == W && depth == D) {                                                       \
+        if (prec == SWV_F32C)                                                              \
+            k_batch_tree<D, W, SWV_F32C><<<g, b, 0, s>>>(scales, inst, items, n_items,     \
+                                                         counter, status);                 \
+        else                                                                               \
+            k_batch_tree<D, W, SWV_FP64><<<g, b, 0, s>>>(scales, inst, items, n_items,     \
+                                                         counter, status);                 \
+        return hipGetLastError();                                                          \
     }
     SWV_TREE_SHAPES(SWV_RUN_T)
 #undef SWV_RUN_T

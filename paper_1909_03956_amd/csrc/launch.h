@@ -107,13 +107,14 @@ hipError_t launch_reset_counters(hipStream_t s, unsigned* counters, int n);
 int batch_direct_blocks_per_cu(int vpl, int block);
 // walker / depth as for launch_tree: depth is the largest J (walker 0) or
 // segment depth (walker 1) over the plan's trees.
-int batch_tree_blocks_per_cu(int walker, int depth);
+int batch_tree_blocks_per_cu(int walker, int depth, int prec);
 hipError_t launch_batch_direct(hipStream_t s, int vpl, int block, int grid,
                                const BatchInst* inst, const Comp* pack, const WorkItem* items,
                                unsigned n_items, unsigned* counter, int* status);
-hipError_t launch_batch_tree(hipStream_t s, int walker, int depth, int grid, const TreeArgs& scales,
-                             const BatchInst* inst, const WorkItem* items, unsigned n_items,
-                             unsigned* counter, int* status);
+// prec: the precision of every instance the work items refer to.
+hipError_t launch_batch_tree(hipStream_t s, int walker, int depth, int prec, int grid,
+                             const TreeArgs& scales, const BatchInst* inst, const WorkItem* items,
+                             unsigned n_items, unsigned* counter, int* status);
 constexpr int kBatchTreeBlock = 64;
 
 }  // namespace swv

@@ -252,3 +252,52 @@ def test_batched_workload_full_size(env):
     big = max(range(len(B.instances)), key=lambda k: B.instances[k].n_comp)
     chosen = [(big, "direct"), (3, "tree"), (200, "direct"), (131, "tree")]
     assert _check_instances(B, outs, chosen, torch, "cfg4") <= TOL64
+
+
+def test_batch_f32c_trees_bitwise(env):
+    """Tree instances in FP32C (and FP64, and F32C direct ones) in one plan:
+    every output bitwise equal to the single-instance prediction; the F32C
+    trees within the 1e-6 bar of the oracle."""
+    torch, swv = env
+    rng = np.random.default_rng(21)
+    insts, refs, checks = [], [], []
+    for J, n, k, prec in ((6, 777, 200, "f32c"), (9, 30011, 300, "f32c"), (9, 20000, 120, "fp64"),
+                          (12, 2048, 60, "f32c"), (3, 1, 5, "f32c")):
+        uh, vh, wh = (rng.uniform(-3e4, 3e4, n) for _ in range(3))
+        u, v, w = dev(uh, torch), dev(vh, torch), dev(wh, torch)
+        l, m = rng.uniform(-0.04, 0.04, k), rng.uniform(-0.04, 0.04, k)
+        f = rng.lognormal(-3, 1, k)
+        t = swv.Tree(J, 1.1, 0.4, l, m, f)
+        dt = torch.complex64 if prec == "f32c" else torch.complex128
+        out = torch.full((n,), 7.0, dtype=dt, device="cuda")
+        insts.append(dict(route="tree", prec=prec, tree=t, u=u, v=v, w=w, out=out))
+        refs.append(lambda u=u, v=v, w=w, t=t, p=prec: t.predict(u, v, w, prec=p))
+        checks.append((J, l, m, f, uh, vh, wh, prec))
+    L, M, F = (dev(rng.uniform(-0.04, 0.04, 50), torch) for _ in range(3))
+    ud = dev(rng.uniform(-3e4, 3e4, 5000), torch)
+    od = torch.empty(5000, dtype=torch.complex64, device="cuda")
+    insts.append(dict(route="direct", prec="f32c", u=ud, v=ud, w=ud, l=L, m=M, flux=F.abs(),
+                      out=od))
+    refs.append(lambda: swv.predict_direct(ud, ud, ud, L, M, F.abs(), prec="f32c"))
+    plan = swv.BatchPlan(insts)
+    plan.run()
+    swv.synchronize()
+    assert _mismatches(insts, refs, torch) == []
+    graph = plan.capture()
+    for d in insts:
+        d["out"].fill_(3.0)
+    graph.launch()
+    swv.synchronize()
+    assert _mismatches(insts, refs, torch) == []
+    for d, (J, l, m, f, uh, vh, wh, prec) in zip(insts, checks):
+        if prec != "f32c":
+            continue
+        rt = ot.build_tree(J, 1.1, 0.4, l, m, f)
+        ref = ot.predict_tree(rt, uh, vh, wh)
+        assert errors(host(d["out"]).astype(np.complex128), ref, f.sum())[0] <= 1e-6
+    with pytest.raises(TypeError):
+        swv.BatchPlan([dict(route="tree", prec="f32c", tree=insts[0]["tree"], u=insts[0]["u"],
+                            v=insts[0]["v"], w=insts[0]["w"],
+                            out=torch.empty(777, dtype=torch.complex128, device="cuda"))])
+    graph.close()
+    plan.close()
