@@ -326,7 +326,12 @@ def residual_chi2(vis_obs, vis_model, inv_sigma2: float, out=None):
     n = vis_obs.numel()
     if vis_model.numel() != n:
         raise ValueError("length mismatch")
-    resid = torch.empty_like(vis_obs) if out is None else out
+    if out is None:
+        resid = torch.empty_like(vis_obs)
+    else:
+        resid = _dev_c128(out, "out", dev)
+        if resid.numel() != n or resid.data_ptr() != out.data_ptr():
+            raise ValueError("out must be a contiguous complex128 tensor of the same length")
     chi2 = torch.empty(1, dtype=torch.float64, device=dev)
     ctx = context(dev)
     check(lib().swv_residual_chi2(ctx.handle, n, _ptr(vis_obs), _ptr(vis_model),
