@@ -75,7 +75,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
     const auto* V = uniform_ptr(v + j0);
     const auto* W = uniform_ptr(w + j0);
     const auto* Y = uniform_ptr(y + j0);
-#pragma unroll 2
+#pragma unroll 4
     for (int j = 0; j < nrow; ++j) {
         const double uj = U[j], vj = V[j], wj = W[j];
         const double yr = Y[j].x, yi = Y[j].y;
