@@ -448,7 +448,7 @@ def run_batched(swv, torch, np, dev, configs):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (--gpus "
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (--gpus "
               f"{args.gpus} requested); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.sweep:

@@ -53,7 +53,7 @@ extern "C" {
 #define SWV_EDOMAIN  (-2)  /* l^2 + m^2 >= 1, J outside [1, 29], |sign| != 1, non-finite input */
 #define SWV_ENOMEM   (-3)  /* host or device allocation failed */
 #define SWV_EHIP     (-4)  /* a HIP runtime call failed; the message holds the HIP error text */
-#define SWV_ENOTSUP  (-5)  /* valid request this build does not support */
+#define SWV_ENOTSUP  (-5)  /* valid request the library does not support */
 
 /* Arithmetic forms. */
 #define SWV_FP64  0  /* phase, sincos and sums in FP64; output complex128 */
