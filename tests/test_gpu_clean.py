@@ -366,3 +366,33 @@ def test_f32c_images(env, small):
     assert abs(got["val"].sum() - ref["val"].sum()) <= 1e-4 * np.abs(ref["val"]).sum()
     for cg, cr in zip(got["cycles"], ref["cycles"]):
         assert abs(cg["chi2"] - cr["chi2"]) <= 1e-3 * cr["chi2"]
+
+
+def test_entry_point_argument_errors(env):
+    """Bad arguments to the clean-loop and related entry points come back as
+    status codes before any launch."""
+    torch, swv = env
+    import ctypes as C
+    from paper_1909_03956_amd._lib import SWV_EDOMAIN, SWV_EINVAL, lib
+    L = lib()
+    ctx = swv.context().handle
+    x = torch.zeros(16, dtype=torch.float64, device="cuda")
+    p = C.c_void_p(x.data_ptr())
+    assert L.swv_image_grid(ctx, 0, 4, 0, 0, 0.1, p, p, p) == SWV_EINVAL
+    assert L.swv_image_grid(ctx, 4, 4, 2, 2, -0.1, p, p, p) == SWV_EDOMAIN
+    assert L.swv_image_grid(ctx, 4, 4, 2, 2, 0.1, None, p, p) == SWV_EINVAL
+    assert L.swv_dirty_image(ctx, 0, p, p, p, None, 4, 4, 2, 2, 0.1, -1, 0, p) == SWV_EINVAL
+    assert L.swv_dirty_image(ctx, 4, p, p, p, None, 4, 4, 2, 2, 0.1, 2, 0, p) == SWV_EDOMAIN
+    assert L.swv_dirty_image(ctx, 4, p, p, p, None, 4, 4, 2, 2, 0.1, -1, 7, p) == SWV_EINVAL
+    assert L.swv_hogbom(ctx, 2, 2, p, p, 0.1, 0.0, 3, 8, p, p, p) == SWV_EINVAL   # unknown flag
+    assert L.swv_hogbom(ctx, 2, 2, p, p, 0.1, 0.0, -1, 0, p, p, p) == SWV_EINVAL
+    assert L.swv_hogbom(ctx, 2, 2, p, p, 0.1, float("nan"), 3, 0, p, p, p) == SWV_EDOMAIN
+    abc = (C.c_double * 3)(0.1, 0.0, float("inf"))
+    assert L.swv_restore(ctx, 2, 2, 1, p, p, abc, None, p) == SWV_EDOMAIN
+    assert L.swv_restore(ctx, 2, 2, -1, p, p, abc, None, p) == SWV_EINVAL
+    assert L.swv_predict_tree_leaves(ctx, None, 4, p, p, p, -1, 0, p) == SWV_EINVAL
+    assert L.swv_predict_degrid(ctx, 4, 4, 0.01, p, 4, p, p, p, 1, -1, p, None) == SWV_EINVAL
+    assert L.swv_predict_degrid(ctx, 4, 4, 0.01, p, 4, p, p, p, 8, 0, p, None) == SWV_EDOMAIN
+    assert L.swv_cross_reference(0, 0.0, 0.0, 4, 4, 0.01, p) == SWV_EDOMAIN
+    assert L.swv_fit_clean_beam(0, 4, p, p) == SWV_EINVAL
+    assert b"swv_fit_clean_beam" in L.swv_last_error()
