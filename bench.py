@@ -23,6 +23,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -169,9 +170,24 @@ def cpu_baseline(n_rows: int) -> dict:
 
 
 # ------------------------------------------------------------------ GPU --
-def _sha(path):
-    with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+def source_digest(kernel_file: str) -> str:
+    """SHA-256 (16 hex digits) of a kernel source together with every local
+    header it includes, directly or through other headers, so that a change
+    to any of them marks recorded counters as stale."""
+    csrc = os.path.join(ROOT, "paper_1909_03956_amd", "csrc")
+    seen, todo = [], [kernel_file]
+    while todo:
+        name = todo.pop(0)
+        if name in seen or not os.path.exists(os.path.join(csrc, name)):
+            continue
+        seen.append(name)
+        with open(os.path.join(csrc, name)) as fh:
+            todo += re.findall(r'^\s*#include\s+"([^"]+)"', fh.read(), re.M)
+    h = hashlib.sha256()
+    for name in [seen[0]] + sorted(seen[1:]):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_for(kernel_file: str, per_launch_key: str):
@@ -184,8 +200,7 @@ def traffic_for(kernel_file: str, per_launch_key: str):
         rec = json.load(fh).get(per_launch_key)
     if not rec:
         return None
-    src = os.path.join(ROOT, "paper_1909_03956_amd", "csrc", kernel_file)
-    if rec.get("source_sha") != _sha(src):
+    if rec.get("source_sha") != source_digest(kernel_file):
         return None
     return rec.get("bytes_per_launch")
 
