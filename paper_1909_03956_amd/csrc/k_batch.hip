@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kBatchTreeBlock) void k_batch_tree(
     const auto* IT = uniform_ptr(items);
     const auto* IN = uniform_ptr(inst);
     constexpr int LDSL = tree_lds_levels<JMAX, kBatchTreeBlock>();
-    __shared__ double sums[LDSL > 0 ? LDSL * 8 * kBatchTreeBlock : 1];
+    __shared__ double sums[LDSL > 0 ? LDSL * kSlotDoubles * kBatchTreeBlock : 1];
     for (;;) {
         const unsigned it = next_item(counter);
         if (it >= n_items) break;

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(BLOCK) void k_tree(TreeArgs ta, const double* __res
     const int64_t j = jrow < n_vis ? jrow : n_vis - 1;
     const double U = u[j], V = v[j], W = w[j];
     constexpr int LDSL = tree_lds_levels<JMAX, BLOCK>();
-    __shared__ double sums[LDSL > 0 ? LDSL * 8 * BLOCK : 1];
+    __shared__ double sums[LDSL > 0 ? LDSL * kSlotDoubles * BLOCK : 1];
     double Vr, Vi;
     tree_row<JMAX, WALKER, LDSL, BLOCK, PREC == SWV_F32C>(ta.rec, ta.n_roots, ta.J, ta,
                                                           (LdsPtr)sums, U, V, W, Vr, Vi);

@@ -12,7 +12,7 @@ using RecPtr = const __attribute__((address_space(4))) TRec*;
 using LdsPtr = __attribute__((address_space(3))) double*;
 
 // Open levels (segments) whose running sums stay in registers; the ones above
-// them are kept in LDS (see slot_store).
+// them are kept in LDS (see slot_put).
 constexpr int kTreeRegLevels = 6;
 
 // Running sums of an open node over its finished children:
@@ -70,41 +70,49 @@ __device__ __forceinline__ void close_node(const NodeSums& n, double a, double g
     Vi = fma(g2, s2i, Vi);
 }
 
-// Sums of the open nodes of the top LDSL levels (level walker) or segments
-// (branch walker) are kept in LDS rather than registers: such a node is
-// touched only when one of its few children finishes, and its registers would
-// otherwise stay allocated through every subtree below it, which limits how
-// many waves share a SIMD.  Layout [slot][8][BLOCK]: lane-contiguous, so the
-// accesses are free of bank conflicts.
+// Open nodes of the top LDSL levels (level walker) or segments (branch
+// walker) keep their children's plane-wave coefficients in LDS rather than
+// running sums in registers: such a node is touched only when one of its few
+// children finishes, and its registers would otherwise stay allocated through
+// every subtree below it, which limits how many waves share a SIMD.  A node
+// holds at most three finished children while its last one is walked, so a
+// slot is three complex values (6 doubles, against 8 for the four running
+// sums); the sums are formed when the last child is back, in child order, so
+// they equal the register levels' bit for bit.  Layout [slot][6][BLOCK]:
+// lane-contiguous, so the accesses are free of bank conflicts.
 // The accesses are volatile: otherwise the compiler, seeing the whole inlined
 // walk, forwards each stored value to its reload and keeps it in registers.
+constexpr int kSlotDoubles = 6;
+
 template <int BLOCK>
-__device__ __forceinline__ void slot_store(LdsPtr lds, int slot, const NodeSums& n) {
-    volatile __attribute__((address_space(3))) double* p = lds + slot * 8 * BLOCK + threadIdx.x;
-    p[0 * BLOCK] = n.Sr;
-    p[1 * BLOCK] = n.Si;
-    p[2 * BLOCK] = n.D0r;
-    p[3 * BLOCK] = n.D0i;
-    p[4 * BLOCK] = n.D1r;
-    p[5 * BLOCK] = n.D1i;
-    p[6 * BLOCK] = n.D2r;
-    p[7 * BLOCK] = n.D2i;
+__device__ __forceinline__ void slot_put(LdsPtr lds, int slot, int k, double xr, double xi) {
+    volatile __attribute__((address_space(3))) double* p =
+        lds + (slot * kSlotDoubles + 2 * k) * BLOCK + threadIdx.x;
+    p[0] = xr;
+    p[BLOCK] = xi;
 }
 
 template <int BLOCK>
-__device__ __forceinline__ NodeSums slot_load(LdsPtr lds, int slot) {
+__device__ __forceinline__ void slot_get(LdsPtr lds, int slot, int k, double& xr, double& xi) {
     const volatile __attribute__((address_space(3))) double* p =
-        lds + slot * 8 * BLOCK + threadIdx.x;
-    NodeSums n;
-    n.Sr = p[0 * BLOCK];
-    n.Si = p[1 * BLOCK];
-    n.D0r = p[2 * BLOCK];
-    n.D0i = p[3 * BLOCK];
-    n.D1r = p[4 * BLOCK];
-    n.D1i = p[5 * BLOCK];
-    n.D2r = p[6 * BLOCK];
-    n.D2i = p[7 * BLOCK];
-    return n;
+        lds + (slot * kSlotDoubles + 2 * k) * BLOCK + threadIdx.x;
+    xr = p[0];
+    xi = p[BLOCK];
+}
+
+// Adds the k children kept in a slot to n, in child order; `all` is the
+// node's child mask, whose k lowest set bits name them.
+template <int BLOCK>
+__device__ __forceinline__ void slot_replay(LdsPtr lds, int slot, int k, unsigned all,
+                                            NodeSums& n, bool& first) {
+    for (int q = 0; q < k; ++q) {
+        const int c = __builtin_ctz(all);
+        all &= all - 1;
+        double xr, xi;
+        slot_get<BLOCK>(lds, slot, q, xr, xi);
+        add_child(n, c, xr, xi, first);
+        first = false;
+    }
 }
 
 // sqrt(A_j)/4 of a level known only at run time: the level-1 factor times
@@ -173,25 +181,34 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const Tr
         return;
     }
     if constexpr (LVL < JMAX) {
-        unsigned mask = meta_mask(rec[me].meta);
+        const unsigned all = meta_mask(rec[me].meta);
+        unsigned mask = all;
         NodeSums n;
         bool first = true;
-        while (mask) {
-            const int c = __builtin_ctz(mask);
-            mask &= mask - 1;
-            double xr, xi;
-            walk<LVL + 1, JMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr, Vi);
-            if constexpr (LVL <= LDSL) {
-                // a fresh value every iteration: nothing of this level stays
-                // in registers while the next child's subtree is walked
-                NodeSums m = first ? NodeSums{} : slot_load<BLOCK>(lds, LVL - 1);
-                add_child(m, c, xr, xi, first);
-                if (mask) slot_store<BLOCK>(lds, LVL - 1, m);
-                n = m;
-            } else {
-                add_child(n, c, xr, xi, first);
+        if constexpr (LVL <= LDSL) {
+            // every child but the last waits in the slot (stored when the
+            // next one starts); only the last one's value leaves the loop
+            int k = 0, c = 0;
+            double xr = 0.0, xi = 0.0;
+            while (mask) {
+                if (mask != all) slot_put<BLOCK>(lds, LVL - 1, k++, xr, xi);
+                c = __builtin_ctz(mask);
+                mask &= mask - 1;
+                walk<LVL + 1, JMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr,
+                                                      Vi);
             }
-            first = false;
+            slot_replay<BLOCK>(lds, LVL - 1, k, all, n, first);
+            add_child(n, c, xr, xi, first);
+        } else {
+            while (mask) {
+                const int c = __builtin_ctz(mask);
+                mask &= mask - 1;
+                double xr, xi;
+                walk<LVL + 1, JMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr,
+                                                      Vi);
+                add_child(n, c, xr, xi, first);
+                first = false;
+            }
         }
         close_node(n, ta.scale[LVL], rec[me].a, rec[me].b, rec[me].c, er, ei, Vr, Vi);
     }
@@ -220,20 +237,31 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
     } else {
         if constexpr (D < DMAX) {
             // a terminal node has two or more children: its sums start at zero
-            unsigned mask = meta_mask(mt);
+            const unsigned all = meta_mask(mt);
+            unsigned mask = all;
             NodeSums n{};
-            if constexpr (D <= LDSL) slot_store<BLOCK>(lds, D - 1, n);
-            while (mask) {
-                const int c = __builtin_ctz(mask);
-                mask &= mask - 1;
-                double xr, xi;
-                seg_walk<D + 1, DMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, u, v, w, xr, xi,
-                                                        Vr, Vi);
-                if constexpr (D <= LDSL) {
-                    n = slot_load<BLOCK>(lds, D - 1);
-                    add_child(n, c, xr, xi, false);
-                    if (mask) slot_store<BLOCK>(lds, D - 1, n);
-                } else {
+            if constexpr (D <= LDSL) {
+                // as in the level walker: all children but the last wait in
+                // the slot, and the sums (from zero) are formed at the end
+                int k = 0, c = 0;
+                double xr = 0.0, xi = 0.0;
+                while (mask) {
+                    if (mask != all) slot_put<BLOCK>(lds, D - 1, k++, xr, xi);
+                    c = __builtin_ctz(mask);
+                    mask &= mask - 1;
+                    seg_walk<D + 1, DMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, u, v, w, xr,
+                                                            xi, Vr, Vi);
+                }
+                bool first = false;
+                slot_replay<BLOCK>(lds, D - 1, k, all, n, first);
+                add_child(n, c, xr, xi, false);
+            } else {
+                while (mask) {
+                    const int c = __builtin_ctz(mask);
+                    mask &= mask - 1;
+                    double xr, xi;
+                    seg_walk<D + 1, DMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, u, v, w, xr,
+                                                            xi, Vr, Vi);
                     add_child(n, c, xr, xi, false);
                 }
             }
@@ -255,13 +283,13 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
 template <int JMAX, int BLOCK>
 constexpr int tree_lds_levels() {
     constexpr int want = JMAX > kTreeRegLevels ? JMAX - kTreeRegLevels : 0;
-    constexpr int cap = (64 * 1024) / (8 * 8 * BLOCK);
+    constexpr int cap = (64 * 1024) / (kSlotDoubles * 8 * BLOCK);
     return want < cap ? want : cap;
 }
 
 // V (real, imaginary / 4) of one row: the root loop of the traversal.
 // WALKER 0: level walker up to level JMAX; 1: branch walker up to JMAX segments.
-// lds: the block's [LDSL][8][BLOCK] sum slots.  F32: FP32 phasors at the leaves.
+// lds: the block's [LDSL][6][BLOCK] child slots.  F32: FP32 phasors at the leaves.
 template <int JMAX, int WALKER, int LDSL, int BLOCK, bool F32 = false>
 __device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J,
                                          const TreeArgs& ta, LdsPtr lds, double U, double V,
