@@ -295,9 +295,18 @@ __global__ __launch_bounds__(BLOCK) void k_grad_partial(
         __syncthreads();
         // wave-uniform trip count, kept in scalar registers
         const int nrow = __builtin_amdgcn_readfirstlane(nt);
+        // the next row's LDS reads are issued before this row's arithmetic,
+        // so their latency is hidden behind it (the last row reads itself
+        // again, in bounds)
+        double2 na = rows[0][0], nb = rows[0][1], nc = rows[0][2], nd = rows[0][3];
 #pragma unroll 1
         for (int r = 0; r < nrow; ++r) {
-            const double2 a = rows[r][0], b = rows[r][1], c2 = rows[r][2], d = rows[r][3];
+            const double2 a = na, b = nb, c2 = nc, d = nd;
+            const int rn = r + 1 < nrow ? r + 1 : r;
+            na = rows[rn][0];
+            nb = rows[rn][1];
+            nc = rows[rn][2];
+            nd = rows[rn][3];
             const double uj = a.x, vj = a.y, wj = b.x;
             const double yr = b.y, yi = c2.x, y4r = c2.y, y4i = d.x;
 #pragma unroll

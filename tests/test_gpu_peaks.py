@@ -16,6 +16,11 @@ def test_measured_peaks_plausible():
     assert 10.0 < p["fp32_fma_tflops"] <= 157.3 * 1.05
     assert p["sincos_f32_gops"] > 0
     # one FP64 phasor costs 21 FP64 VALU lane-operations: phasors per second
-    # times 21 cannot beat the FMA stream's lane-operation rate
-    fma_lane_ops = p["fp64_fma_tflops"] * 1e12 / 2
-    assert p["cis2pi_f64_gops"] * 1e9 * 21 <= fma_lane_ops * 1.05
+    # times 21 cannot beat the FP64 lane-operation rate at the top engine
+    # clock (the published 78.6 TFLOP/s over 2 flop per FMA).  The measured
+    # FMA stream is not the bound: it draws the most power of the four
+    # kernels and can run at a lower clock than the phasor kernel after it
+    # (seen: 70.6 TFLOP/s against 1,789 G phasors/s, 1.06x its lane rate).
+    assert p["cis2pi_f64_gops"] * 1e9 * 21 <= 78.6e12 / 2 * 1.02
+    # and within a power-throttling margin of the measured stream
+    assert p["cis2pi_f64_gops"] * 1e9 * 21 <= p["fp64_fma_tflops"] * 1e12 / 2 * 1.2
