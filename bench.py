@@ -170,11 +170,11 @@ def cpu_baseline(n_rows: int) -> dict:
 
 
 # ------------------------------------------------------------------ GPU --
-def source_digest(kernel_file: str) -> str:
+def source_digest(kernel_file: str, csrc: str | None = None) -> str:
     """SHA-256 (16 hex digits) of a kernel source together with every local
     header it includes, directly or through other headers, so that a change
     to any of them marks recorded counters as stale."""
-    csrc = os.path.join(ROOT, "paper_1909_03956_amd", "csrc")
+    csrc = csrc or os.path.join(ROOT, "paper_1909_03956_amd", "csrc")
     seen, todo = [], [kernel_file]
     while todo:
         name = todo.pop(0)
@@ -190,17 +190,18 @@ def source_digest(kernel_file: str) -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel_file: str, per_launch_key: str):
+def traffic_for(kernel_file: str, per_launch_key: str, path: str | None = None,
+                csrc: str | None = None):
     """HBM bytes per launch from the committed counter summary, or None if the
     kernel source changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    path = path or os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh).get(per_launch_key)
     if not rec:
         return None
-    if rec.get("source_sha") != source_digest(kernel_file):
+    if rec.get("source_sha") != source_digest(kernel_file, csrc):
         return None
     return rec.get("bytes_per_launch")
 

@@ -1,0 +1,63 @@
+"""Host-side logic of bench.py, on the CPU: the one-GPU guard, the source
+digest that marks recorded counters as stale, and the oracle's CPU baseline
+record on a small sample."""
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def _tree(tmp_path, files):
+    for name, text in files.items():
+        (tmp_path / name).write_text(text)
+    return str(tmp_path)
+
+
+def test_source_digest_follows_included_headers(tmp_path):
+    d = _tree(tmp_path, {"k.hip": '#include "a.h"\nkernel\n', "a.h": '#include "b.h"\n',
+                         "b.h": "x\n", "other.h": "y\n"})
+    h0 = bench.source_digest("k.hip", d)
+    (tmp_path / "other.h").write_text("z\n")           # not included: no change
+    assert bench.source_digest("k.hip", d) == h0
+    (tmp_path / "b.h").write_text("x2\n")              # included through a.h
+    h1 = bench.source_digest("k.hip", d)
+    assert h1 != h0
+    (tmp_path / "k.hip").write_text('#include "a.h"\nkernel2\n')
+    assert bench.source_digest("k.hip", d) not in (h0, h1)
+
+
+def test_traffic_is_null_once_the_source_changes(tmp_path):
+    d = _tree(tmp_path, {"k.hip": '#include "a.h"\n', "a.h": "x\n"})
+    rec = tmp_path / "traffic.json"
+    rec.write_text(json.dumps({"k_x": {"bytes_per_launch": 123,
+                                       "source_sha": bench.source_digest("k.hip", d)}}))
+    assert bench.traffic_for("k.hip", "k_x", str(rec), d) == 123
+    assert bench.traffic_for("k.hip", "k_missing", str(rec), d) is None
+    (tmp_path / "a.h").write_text("x changed\n")
+    assert bench.traffic_for("k.hip", "k_x", str(rec), d) is None
+
+
+def test_committed_traffic_record_names_every_kernel():
+    with open(os.path.join(ROOT, "profiles", "hbm_traffic.json")) as fh:
+        rec = json.load(fh)
+    for key in ("k_direct_f64", "k_tree_J10", "k_adjoint", "k_grad_partial"):
+        assert rec[key]["bytes_per_launch"] > 0 and len(rec[key]["source_sha"]) == 16
+
+
+def test_cpu_baseline_record_on_a_small_sample():
+    b = bench.cpu_baseline(64)
+    assert b["kind"] == "oracle" and b["unit"] == bench.UNIT
+    assert 1 <= b["cores"] <= bench.CPU_SHARE
+    assert b["value"] > 0 and b["cpu_seconds"] > 0
+    assert "64 seeded rows" in b["sample"]
