@@ -107,6 +107,58 @@ def test_small_trees_every_depth(env, J):
     assert np.all(np.abs(got - ref) <= bound + (J + 2) * 4e-16 * np.abs(f).sum())
 
 
+def _spine_pixels(J, base, counts, rng):
+    """Level-J pixel ids of a tree whose spine node at level j has counts[j-1]
+    children (a random subset of the four), one of which continues the spine;
+    the others end in one-child chains down to level J."""
+    pix, node = [], base                     # level-1 pixel: the base pixel
+    for j in range(1, J):
+        cs = rng.choice(4, counts[j - 1], replace=False)
+        for c in cs[1:]:
+            p = 4 * node + int(c)
+            for _ in range(J - j - 1):
+                p = 4 * p + int(rng.integers(4))
+            pix.append(p)
+        node = 4 * node + int(cs[0])
+    pix.append(node)
+    return pix
+
+
+@pytest.mark.parametrize("J,walker", [(10, 1), (10, 2), (12, 2), (15, 2)])
+def test_every_child_count_on_the_lds_levels(env, J, walker):
+    """The top levels (segments) of a deep traversal keep their finished
+    children in LDS and form the sums when the last child returns; spines
+    whose nodes have 1, 2, 3 and 4 children at every depth cover every count
+    of kept children, with both walkers, against the oracle."""
+    torch, swv = env
+    rng = np.random.default_rng(7 * J + walker)
+    pix = []
+    for base, shift in ((4, 0), (5, 1), (6, 2), (7, 3)):
+        counts = [1 + (j + shift) % 4 for j in range(J - 1)]
+        pix += _spine_pixels(J, base, counts, rng)
+    flux = rng.normal(size=len(pix))
+    ra, dec = 1.0, 0.3
+    t = swv.Tree.from_pixels(J, ra, dec, pix, flux)
+    st = t.stats()
+    nv = 333
+    u, v, w = (rng.uniform(-2e4, 2e4, nv) for _ in range(3))
+    got = host(_with_walker(swv, walker, lambda: t.predict(dev(u, torch), dev(v, torch),
+                                                           dev(w, torch))))
+    swv.synchronize()
+    from oracle import clean as oc
+    rt = oc.tree_from_pixels(J, ra, dec, pix, flux)
+    ref = ot.predict_tree(rt, u, v, w)
+    kids = {}
+    for j in range(1, 5):                    # children per node on the top four levels
+        parents = t.level(j + 1)["pix"] // 4
+        kids[j] = sorted(set(np.unique(parents, return_counts=True)[1].tolist()))
+    note(f"J={J} walker={walker}: {st['n_leaves']} leaves, max_branching="
+         f"{st['max_branching']}, children per node on levels 1-4: {kids}")
+    assert all(kids[j] == [1, 2, 3, 4] for j in (1, 2, 3, 4))
+    bound = fp64_row_bound(u, v, w, rt.leaf_l, rt.leaf_m, rt.leaf_nm1, rt.leaf_flux)
+    assert np.all(np.abs(got - ref) <= bound + (J + 2) * 4e-16 * np.abs(flux).sum())
+
+
 def test_empty_tree_gives_zero(env):
     _, got = _tree_run(env, 7, 0.0, 0.5, np.zeros(0), np.zeros(0), np.zeros(0),
                        np.ones(100), np.ones(100), np.ones(100))
