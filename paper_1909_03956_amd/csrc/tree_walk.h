@@ -15,31 +15,35 @@ using LdsPtr = __attribute__((address_space(3))) double*;
 // them are kept in LDS (see slot_put).
 constexpr int kTreeRegLevels = 6;
 
-// Running sums of an open node over its finished children:
-//   S = sum_c eta_{j+1,c},   D^m = sum_c s^m_c eta_{j+1,c}   (m = 0, 1, 2).
+// Running sums of an open node over its finished children, the D^m taken
+// relative to the node's first child c0:
+//   S = sum_c eta_{j+1,c},   D^m = s^m_{c0} sum_c s^m_c eta_{j+1,c}   (m = 0, 1, 2),
+// so the first child's coefficient enters every sum as it is, and the sign
+// s^m_{c0} moves to the node's scale factor when it closes.  With s = +-1 and
+// rounding symmetric in sign, each value is the plain sum times s^m_{c0}
+// exactly, so sigma comes out the same bit for bit.
 struct NodeSums {
     double Sr, Si, D0r, D0i, D1r, D1i, D2r, D2i;
 };
 
-// Takes child c's plane-wave coefficient x into the sums: the first child
-// sets them (S = x, D^m = s^m_c x), later ones add to them.  `first` is the
-// same for every lane, so this is a scalar branch, and no sums need zeroing.
-__device__ __forceinline__ void add_child(NodeSums& n, int c, double xr, double xi, bool first) {
-    // Eq. 10 signs of child c: gamma^0 (+-+-), gamma^1 (++--), gamma^2 (+--+),
-    // chosen as scalars
-    const double s0 = (c & 1) ? -1.0 : 1.0;
-    const double s1 = (c & 2) ? -1.0 : 1.0;
-    const double s2 = ((c ^ (c >> 1)) & 1) ? -1.0 : 1.0;
+// Eq. 10 signs: gamma^0 (+-+-), gamma^1 (++--), gamma^2 (+--+) over the
+// children c = 0..3; s^m_c s^m_{c0} is the sign of child c ^ c0.
+__device__ __forceinline__ double sign0(int c) { return (c & 1) ? -1.0 : 1.0; }
+__device__ __forceinline__ double sign1(int c) { return (c & 2) ? -1.0 : 1.0; }
+__device__ __forceinline__ double sign2(int c) { return ((c ^ (c >> 1)) & 1) ? -1.0 : 1.0; }
+
+// Takes child c's plane-wave coefficient x into the sums of a node whose
+// first child is c0: the first child sets them all to x, later ones add
+// with the signs of c ^ c0.  `first` is the same for every lane, so this is
+// a scalar branch, and no sums need zeroing.
+__device__ __forceinline__ void add_child(NodeSums& n, int c, int c0, double xr, double xi,
+                                          bool first) {
     if (first) {
-        n.Sr = xr;
-        n.Si = xi;
-        n.D0r = s0 * xr;
-        n.D0i = s0 * xi;
-        n.D1r = s1 * xr;
-        n.D1i = s1 * xi;
-        n.D2r = s2 * xr;
-        n.D2i = s2 * xi;
+        n.Sr = n.D0r = n.D1r = n.D2r = xr;
+        n.Si = n.D0i = n.D1i = n.D2i = xi;
     } else {
+        const int r = c ^ c0;
+        const double s0 = sign0(r), s1 = sign1(r), s2 = sign2(r);
         n.Sr += xr;
         n.Si += xi;
         n.D0r = fma(s0, xr, n.D0r);
@@ -51,17 +55,22 @@ __device__ __forceinline__ void add_child(NodeSums& n, int c, double xr, double 
     }
 }
 
-// Closes a node at level j (a = sqrt(A_j)/4, g = gamma^m_j): eta_j (Eq. 9 on
-// the plane wave) goes to the parent, sigma^m_j (Eq. 10 on the plane wave) is
-// formed and gamma^m_j sigma^m_j added to V (Eq. 17).
-__device__ __forceinline__ void close_node(const NodeSums& n, double a, double g0, double g1,
-                                           double g2, double& er, double& ei, double& Vr,
-                                           double& Vi) {
+// Closes a node at level j whose first child is c0 (a = sqrt(A_j)/4,
+// g = gamma^m_j): eta_j (Eq. 9 on the plane wave) goes to the parent,
+// sigma^m_j = s^m_{c0} a D^m (Eq. 10 on the plane wave) is formed and
+// gamma^m_j sigma^m_j added to V (Eq. 17).
+__device__ __forceinline__ void close_node(const NodeSums& n, int c0, double a, double g0,
+                                           double g1, double g2, double& er, double& ei,
+                                           double& Vr, double& Vi) {
+    // sign choices on a wave-uniform value: scalar selects, no arithmetic
+    const double a0 = (c0 & 1) ? -a : a;
+    const double a1 = (c0 & 2) ? -a : a;
+    const double a2 = ((c0 ^ (c0 >> 1)) & 1) ? -a : a;
     er = 0.25 * n.Sr;
     ei = 0.25 * n.Si;
-    const double s0r = a * n.D0r, s0i = a * n.D0i;
-    const double s1r = a * n.D1r, s1i = a * n.D1i;
-    const double s2r = a * n.D2r, s2i = a * n.D2i;
+    const double s0r = a0 * n.D0r, s0i = a0 * n.D0i;
+    const double s1r = a1 * n.D1r, s1i = a1 * n.D1i;
+    const double s2r = a2 * n.D2r, s2i = a2 * n.D2i;
     Vr = fma(g0, s0r, Vr);
     Vi = fma(g0, s0i, Vi);
     Vr = fma(g1, s1r, Vr);
@@ -100,17 +109,17 @@ __device__ __forceinline__ void slot_get(LdsPtr lds, int slot, int k, double& xr
     xi = p[BLOCK];
 }
 
-// Adds the k children kept in a slot to n, in child order; `all` is the
-// node's child mask, whose k lowest set bits name them.
+// Adds the k children kept in a slot to n, in child order, relative to
+// child c0; `all` is the node's child mask, whose k lowest set bits name them.
 template <int BLOCK>
-__device__ __forceinline__ void slot_replay(LdsPtr lds, int slot, int k, unsigned all,
+__device__ __forceinline__ void slot_replay(LdsPtr lds, int slot, int k, unsigned all, int c0,
                                             NodeSums& n, bool& first) {
     for (int q = 0; q < k; ++q) {
         const int c = __builtin_ctz(all);
         all &= all - 1;
         double xr, xi;
         slot_get<BLOCK>(lds, slot, q, xr, xi);
-        add_child(n, c, xr, xi, first);
+        add_child(n, c, c0, xr, xi, first);
         first = false;
     }
 }
@@ -123,9 +132,8 @@ __device__ __forceinline__ double level_factor(const TreeArgs& ta, int j) {
 }
 
 // Closes a node whose only child c returned x: eta_j = x / 4 and
-// sigma^m_j = (s^m_c a) x -- equal bit for bit to close_node after add_child
-// (a (s^m_c x)), since a product with +-1 is exact -- then gamma^m_j sigma^m_j
-// is added to V.
+// sigma^m_j = (s^m_c a) x -- close_node after add_child with c0 = c, the
+// same operations -- then gamma^m_j sigma^m_j is added to V.
 __device__ __forceinline__ void close_single(int c, double a, double g0, double g1, double g2,
                                              double& er, double& ei, double& Vr, double& Vi) {
     const double xr = er, xi = ei;
@@ -182,6 +190,7 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const Tr
     }
     if constexpr (LVL < JMAX) {
         const unsigned all = meta_mask(rec[me].meta);
+        const int c0 = __builtin_ctz(all);
         unsigned mask = all;
         NodeSums n;
         bool first = true;
@@ -197,8 +206,8 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const Tr
                 walk<LVL + 1, JMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr,
                                                       Vi);
             }
-            slot_replay<BLOCK>(lds, LVL - 1, k, all, n, first);
-            add_child(n, c, xr, xi, first);
+            slot_replay<BLOCK>(lds, LVL - 1, k, all, c0, n, first);
+            add_child(n, c, c0, xr, xi, first);
         } else {
             while (mask) {
                 const int c = __builtin_ctz(mask);
@@ -206,11 +215,11 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const Tr
                 double xr, xi;
                 walk<LVL + 1, JMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr,
                                                       Vi);
-                add_child(n, c, xr, xi, first);
+                add_child(n, c, c0, xr, xi, first);
                 first = false;
             }
         }
-        close_node(n, ta.scale[LVL], rec[me].a, rec[me].b, rec[me].c, er, ei, Vr, Vi);
+        close_node(n, c0, ta.scale[LVL], rec[me].a, rec[me].b, rec[me].c, er, ei, Vr, Vi);
     }
 }
 
@@ -236,13 +245,17 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
         leaf_wave<false, F32>(rec, term, u, v, w, er, ei);
     } else {
         if constexpr (D < DMAX) {
-            // a terminal node has two or more children: its sums start at zero
+            // a terminal node has two or more children.  Its sums start at
+            // zero and take every child with its own signs (c0 = 0: the
+            // plain sums); the level walker's first-child form costs this
+            // walker more in scalar registers than it saves
             const unsigned all = meta_mask(mt);
             unsigned mask = all;
             NodeSums n{};
+            bool first = false;
             if constexpr (D <= LDSL) {
                 // as in the level walker: all children but the last wait in
-                // the slot, and the sums (from zero) are formed at the end
+                // the slot, and the sums are formed at the end
                 int k = 0, c = 0;
                 double xr = 0.0, xi = 0.0;
                 while (mask) {
@@ -252,9 +265,8 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
                     seg_walk<D + 1, DMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, u, v, w, xr,
                                                             xi, Vr, Vi);
                 }
-                bool first = false;
-                slot_replay<BLOCK>(lds, D - 1, k, all, n, first);
-                add_child(n, c, xr, xi, false);
+                slot_replay<BLOCK>(lds, D - 1, k, all, 0, n, first);
+                add_child(n, c, 0, xr, xi, false);
             } else {
                 while (mask) {
                     const int c = __builtin_ctz(mask);
@@ -262,10 +274,10 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
                     double xr, xi;
                     seg_walk<D + 1, DMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, u, v, w, xr,
                                                             xi, Vr, Vi);
-                    add_child(n, c, xr, xi, false);
+                    add_child(n, c, 0, xr, xi, false);
                 }
             }
-            close_node(n, level_factor(ta, meta_level(mt)), rec[term].a, rec[term].b,
+            close_node(n, 0, level_factor(ta, meta_level(mt)), rec[term].a, rec[term].b,
                        rec[term].c, er, ei, Vr, Vi);
         }
     }
