@@ -55,10 +55,14 @@ __device__ __forceinline__ void add_child(NodeSums& n, int c, int c0, double xr,
     }
 }
 
-// Closes a node at level j whose first child is c0 (a = sqrt(A_j)/4,
-// g = gamma^m_j): eta_j (Eq. 9 on the plane wave) goes to the parent,
-// sigma^m_j = s^m_{c0} a D^m (Eq. 10 on the plane wave) is formed and
-// gamma^m_j sigma^m_j added to V (Eq. 17).
+// Closes a node at level j whose first child is c0 (g = gamma^m_j): its sum
+// T_j goes to the parent, sigma^m_j = s^m_{c0} a D^m (Eq. 10 on the plane
+// wave) is formed with a = (sqrt(A_j)/4) 4^-(J-j-1) (the children's sums are
+// T_{j+1} = 4^(J-j-1) eta_{j+1}) and gamma^m_j sigma^m_j added to V (Eq. 17).
+// Passing T_j = sum over the leaves below of eta_J instead of eta_j = T_j /
+// 4^(J-j) (Eq. 9 on the plane wave) moves every quarter into the scale
+// factors as exact powers of two: the same sigma bit for bit, two fewer
+// products per node.
 __device__ __forceinline__ void close_node(const NodeSums& n, int c0, double a, double g0,
                                            double g1, double g2, double& er, double& ei,
                                            double& Vr, double& Vi) {
@@ -66,8 +70,8 @@ __device__ __forceinline__ void close_node(const NodeSums& n, int c0, double a, 
     const double a0 = (c0 & 1) ? -a : a;
     const double a1 = (c0 & 2) ? -a : a;
     const double a2 = ((c0 ^ (c0 >> 1)) & 1) ? -a : a;
-    er = 0.25 * n.Sr;
-    ei = 0.25 * n.Si;
+    er = n.Sr;
+    ei = n.Si;
     const double s0r = a0 * n.D0r, s0i = a0 * n.D0i;
     const double s1r = a1 * n.D1r, s1i = a1 * n.D1i;
     const double s2r = a2 * n.D2r, s2i = a2 * n.D2i;
@@ -124,14 +128,22 @@ __device__ __forceinline__ void slot_replay(LdsPtr lds, int slot, int k, unsigne
     }
 }
 
-// sqrt(A_j)/4 of a level known only at run time: the level-1 factor times
-// 2^(1-j), the same value the host stores for every level, with no load that
-// waits on the record.
-__device__ __forceinline__ double level_factor(const TreeArgs& ta, int j) {
-    return ldexp(ta.scale[1], 1 - j);
+// a 2^e for a normal a and a normal result: e is added to the exponent
+// field, an exact operation that stays on the scalar unit for wave-uniform
+// operands.
+__device__ __forceinline__ double pow2_scale(double a, int e) {
+    return __longlong_as_double(__double_as_longlong(a) + ((long long)e << 52));
 }
 
-// Closes a node whose only child c returned x: eta_j = x / 4 and
+// The scale a of close_node at level j of a depth-J tree:
+// (sqrt(A_j)/4) 4^-(J-j-1) = (sqrt(A_1)/4) 2^(j+3-2J), from the level-1 factor
+// the host stores (sqrt(A_j)/4 halves from level to level) with no load that
+// waits on the record.
+__device__ __forceinline__ double level_factor(const TreeArgs& ta, int j, int J) {
+    return pow2_scale(ta.scale[1], j + 3 - 2 * J);
+}
+
+// Closes a node whose only child c returned its sum x: T_j = x and
 // sigma^m_j = (s^m_c a) x -- close_node after add_child with c0 = c, the
 // same operations -- then gamma^m_j sigma^m_j is added to V.
 __device__ __forceinline__ void close_single(int c, double a, double g0, double g1, double g2,
@@ -140,8 +152,6 @@ __device__ __forceinline__ void close_single(int c, double a, double g0, double 
     const double a0 = (c & 1) ? -a : a;
     const double a1 = (c & 2) ? -a : a;
     const double a2 = ((c ^ (c >> 1)) & 1) ? -a : a;
-    er = 0.25 * xr;
-    ei = 0.25 * xi;
     const double s0r = a0 * xr, s0i = a0 * xi;
     const double s1r = a1 * xr, s1i = a1 * xi;
     const double s2r = a2 * xr, s2i = a2 * xi;
@@ -219,7 +229,8 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const Tr
                 first = false;
             }
         }
-        close_node(n, c0, ta.scale[LVL], rec[me].a, rec[me].b, rec[me].c, er, ei, Vr, Vi);
+        close_node(n, c0, pow2_scale(ta.scale[LVL], 2 * (LVL + 1 - J)), rec[me].a, rec[me].b,
+                   rec[me].c, er, ei, Vr, Vi);
     }
 }
 
@@ -277,7 +288,7 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
                     add_child(n, c, 0, xr, xi, false);
                 }
             }
-            close_node(n, 0, level_factor(ta, meta_level(mt)), rec[term].a, rec[term].b,
+            close_node(n, 0, level_factor(ta, meta_level(mt), J), rec[term].a, rec[term].b,
                        rec[term].c, er, ei, Vr, Vi);
         }
     }
@@ -285,7 +296,7 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
     for (int i = run - 1; i >= 0; --i) {
         const int me = first + i;
         const unsigned long long mm = rec[me].meta;
-        close_single(__builtin_ctz(meta_mask(mm)), level_factor(ta, meta_level(mm)), rec[me].a,
+        close_single(__builtin_ctz(meta_mask(mm)), level_factor(ta, meta_level(mm), J), rec[me].a,
                      rec[me].b, rec[me].c, er, ei, Vr, Vi);
     }
 }
@@ -317,7 +328,9 @@ __device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J,
             walk<1, JMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, U, V, W, er, ei, Vr, Vi);
         else
             seg_walk<1, JMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, U, V, W, er, ei, Vr, Vi);
-        const double A1lam = rec[root].a;  // A_1 lambda_1
+        // A_1 lambda_1 eta_1 with eta_1 = T_1 / 4^(J-1); ldexp, as A_1 lambda_1
+        // may be zero
+        const double A1lam = ldexp(rec[root].a, -2 * (J - 1));
         Vr = fma(A1lam, er, Vr);
         Vi = fma(A1lam, ei, Vi);
     }
