@@ -46,9 +46,14 @@ FLOPS = {
     "direct_fp64": 5 + 2 + 34 + 4,            # MAC: 2 FMA                      -> 45
     "adjoint": 5 + 2 + 34 + 8,                # complex MAC: 4 FMA               -> 49
     "grad": 5 + 2 + 34 + 6 + 1 + 6,           # z = conj(y) e; Re z; 3 FMA on Im z -> 54
-    "tree_leaf": 5 + 2 + 34 + 14,             # + running sums S, D^0..2 (2 add, 6 FMA)
-    "tree_node": 20 + 14,                     # eta, sigma, gamma sigma; + parent sums
-    "tree_root": 20 + 4,                      # level-1 node: + A_1 lambda_1 eta_1
+    # Haar analysis of the plane wave and Eq. 17 (section 2.4): a node with k
+    # children forms S and D^0..2 from k-1 complex additions each (the signs
+    # +-1 are not arithmetic), then eta = S/4 (2), sigma^m = (sqrt(A_j)/4) D^m
+    # (6) and gamma^m sigma^m into V (3 complex x real MACs, 12)
+    "tree_leaf": 5 + 2 + 34,                  # eta_J at the leaf
+    "tree_node": 2 + 6 + 12,                  # eta, sigma, gamma sigma
+    "tree_child": 2 + 6,                      # every child after a node's first: S, D^0..2
+    "tree_root": 4,                           # A_1 lambda_1 eta_1 into V
 }
 
 
@@ -653,10 +658,14 @@ def main():
 
     # roofline of the dominant kernel (largest device time in the step)
     def tree_flops(J):
+        # every node but the level-1 ones is some node's child, and each
+        # internal node has one first child: sum over nodes of (k - 1) is
+        # leaves - roots
         st = tree_stats[J]
         roots = st["nodes_per_level"][0]
         return n_vis * (st["n_leaves"] * FLOPS["tree_leaf"] +
-                        (st["n_internal"] - (roots if J > 1 else 0)) * FLOPS["tree_node"] +
+                        st["n_internal"] * FLOPS["tree_node"] +
+                        (st["n_leaves"] - roots) * FLOPS["tree_child"] +
                         roots * FLOPS["tree_root"])
     flops = {"direct_fp64": n_vis * n_comp * FLOPS["direct_fp64"],
              "adjoint": n_vis * n_pix * FLOPS["adjoint"],
