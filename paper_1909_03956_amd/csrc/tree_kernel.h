@@ -19,13 +19,19 @@
 // a template parameter, so each open level's sums live in their own
 // registers; one call site per level (inside a loop over the set bits of the
 // child mask) keeps the code linear in J.  Roots add A_1 lambda_1 eta_1.
+// Two exact rewritings cut the arithmetic without changing a bit (see
+// tree_walk.h): nodes hand up T_j = 4^(J-j) eta_j, the plain sum of the leaf
+// phasors below, with the quarters moved into the scale factors as powers of
+// two; and the level walker keeps D^m relative to a node's first child, which
+// then enters every sum without a sign product.
 //
 // Deep trees are mostly runs of one-child nodes, so a second traversal (the
 // branch walker) keeps a register set only for open BRANCHING nodes: a run of
 // one-child nodes holds nothing while the subtree below it is walked and is
 // closed bottom-up afterwards.  Its depth parameter is the number of nested
 // branchings, which stays small (a few to a dozen) at any J, so it serves
-// J = 1 .. 29; both traversals perform the same operations in the same order.
+// J = 1 .. 29; both traversals give the same values bit for bit (up to the
+// sign of an exactly-zero intermediate).
 //
 // Imaginary parts are carried divided by 4 (cis2pi_q's convention; every step
 // is linear) and scaled back once at the end.

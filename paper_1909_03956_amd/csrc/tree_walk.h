@@ -15,13 +15,16 @@ using LdsPtr = __attribute__((address_space(3))) double*;
 // them are kept in LDS (see slot_put).
 constexpr int kTreeRegLevels = 6;
 
-// Running sums of an open node over its finished children, the D^m taken
-// relative to the node's first child c0:
-//   S = sum_c eta_{j+1,c},   D^m = s^m_{c0} sum_c s^m_c eta_{j+1,c}   (m = 0, 1, 2),
-// so the first child's coefficient enters every sum as it is, and the sign
+// Running sums of an open node at level j over its finished children, whose
+// values are T_{j+1,c} = 4^(J-j-1) eta_{j+1,c} (the plain sums of the leaf
+// phasors below them, see close_node), the D^m taken relative to the node's
+// first child c0:
+//   S = sum_c T_{j+1,c},   D^m = s^m_{c0} sum_c s^m_c T_{j+1,c}   (m = 0, 1, 2),
+// so the first child's value enters every sum as it is, and the sign
 // s^m_{c0} moves to the node's scale factor when it closes.  With s = +-1 and
 // rounding symmetric in sign, each value is the plain sum times s^m_{c0}
-// exactly, so sigma comes out the same bit for bit.
+// exactly, so sigma comes out the same bit for bit.  (The branch walker
+// passes c0 = 0 and starts its sums at zero.)
 struct NodeSums {
     double Sr, Si, D0r, D0i, D1r, D1i, D2r, D2i;
 };
@@ -32,9 +35,9 @@ __device__ __forceinline__ double sign0(int c) { return (c & 1) ? -1.0 : 1.0; }
 __device__ __forceinline__ double sign1(int c) { return (c & 2) ? -1.0 : 1.0; }
 __device__ __forceinline__ double sign2(int c) { return ((c ^ (c >> 1)) & 1) ? -1.0 : 1.0; }
 
-// Takes child c's plane-wave coefficient x into the sums of a node whose
-// first child is c0: the first child sets them all to x, later ones add
-// with the signs of c ^ c0.  `first` is the same for every lane, so this is
+// Takes child c's value x = T_{j+1,c} into the sums of a node whose first
+// child is c0: the first child sets them all to x, later ones add with the
+// signs of c ^ c0.  `first` is the same for every lane, so this is
 // a scalar branch, and no sums need zeroing.
 __device__ __forceinline__ void add_child(NodeSums& n, int c, int c0, double xr, double xi,
                                           bool first) {
