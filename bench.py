@@ -77,6 +77,11 @@ def parse():
     p.add_argument("--clean-only", action="store_true",
                    help="run only the clean loop on the seven-source workload (two calls) "
                         "and the predictor comparison, and print their JSON blocks")
+    p.add_argument("--precision", action="store_true",
+                   help="time the precision form on its own workload (cfg3: 8,355,840 rows "
+                        "of 100 km baselines, 10,000 components, w-term active): FP64 and "
+                        "FP32-compensated direct sums, speed-up, and the FP32 form's error "
+                        "against the FP64 one on every row; print one JSON line and exit")
     p.add_argument("--profile", action="store_true",
                    help="short run for a profiler: no CPU baseline")
     p.add_argument("--tune", action="store_true",
@@ -409,6 +414,65 @@ def run_compare(swv, torch, np, dev, configs):
     return out
 
 
+def run_precision(swv, torch, np, dev, configs):
+    """The precision form (FP64 phase and reduction, FP32 phasor and products,
+    Kahan-compensated FP32 sums) against the FP64 form on cfg3, the workload
+    named for it: both timed as single launches (median of five after a
+    warm-up), and the FP32 form's error against the FP64 one on every row,
+    relative to the summed flux (its bound against the oracle is a test)."""
+    W = configs.CFG3
+
+    def D(x):
+        return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+    t_in = time.perf_counter()
+    u, v, w = W.track.uvw()
+    l, m, f = W.components()
+    U, V, Wt, L, M, F = D(u), D(v), D(w), D(l), D(m), D(f)
+    n_vis, n_comp = u.size, l.size
+    v64 = torch.empty(n_vis, dtype=torch.complex128, device=dev)
+    v32 = torch.empty(n_vis, dtype=torch.complex64, device=dev)
+    torch.cuda.synchronize()
+    log(f"cfg3 inputs ready in {time.perf_counter() - t_in:.1f} s: {n_vis} rows, "
+        f"{n_comp} components")
+
+    def timed(fn, reps=5):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    ms64 = timed(lambda: swv.predict_direct(U, V, Wt, L, M, F, out=v64))
+    ms32 = timed(lambda: swv.predict_direct(U, V, Wt, L, M, F, prec="f32c", out=v32))
+    err = (v32.to(torch.complex128) - v64).abs()
+    scale = float(np.abs(f).sum())
+    terms = n_vis * n_comp
+    phi = float(torch.max(torch.abs(U) + torch.abs(V) + torch.abs(Wt)).item())
+    out = {"workload": "cfg3: 256-antenna 100 km array, 8 h at dec +30, 1.4 GHz, "
+                       f"{n_vis:,} vis; {n_comp:,} components uniform over 3 deg",
+           "n_vis": n_vis, "n_comp": n_comp, "terms": terms,
+           "max_abs_uvw_sum_wavelengths": round(phi, 1),
+           "fp64": {"ms": round(ms64, 3),
+                    "Gvis_terms_per_s": round(terms / (ms64 * 1e-3) / 1e9, 1),
+                    "fp64_alu_frac": round(terms * FLOPS["direct_fp64"] / (ms64 * 1e-3)
+                                           / (PEAK_FP64_TFLOPS * 1e12), 4)},
+           "f32c": {"ms": round(ms32, 3),
+                    "Gvis_terms_per_s": round(terms / (ms32 * 1e-3) / 1e9, 1)},
+           "speedup_f32c_over_fp64": round(ms64 / ms32, 3),
+           "f32c_vs_fp64": {"E_max": float(f"{float(err.max()) / scale:.3e}"),
+                            "E_rms": float(f"{float(err.pow(2).mean().sqrt()) / scale:.3e}"),
+                            "relative_to": "sum |I_k|, every row"}}
+    log(f"cfg3 direct: FP64 {ms64:.2f} ms, F32C {ms32:.2f} ms "
+        f"({out['speedup_f32c_over_fp64']}x), E_max {out['f32c_vs_fp64']['E_max']}")
+    return out
+
+
 def run_batched(swv, torch, np, dev, configs):
     """The batched workload: 64 channels x 4 pointings of the 256-antenna array,
     2M-8M unflagged rows each (1.29e9 in all), made on the device; one plan per
@@ -489,6 +553,10 @@ def main():
     torch.cuda.set_device(dev)
     if args.batched:
         print(json.dumps({"batched": run_batched(swv, torch, np, dev, configs)}), flush=True)
+        return
+    if args.precision:
+        print(json.dumps({"precision": run_precision(swv, torch, np, dev, configs)}),
+              flush=True)
         return
     if args.clean_only:
         print(json.dumps({"clean_loop": run_clean(swv, torch, np, dev, configs),
