@@ -354,9 +354,9 @@ typedef struct {
     int predictor;        /* SWV_PREDICT_TREE (the wavelet clean), SWV_PREDICT_DEGRID or
                              SWV_PREDICT_DIRECT */
     int support;          /* kernel width W of SWV_PREDICT_DEGRID */
-    int image_prec;       /* precision of the dirty image and every residual image:
-                             SWV_FP64 or SWV_F32C (see swv_dirty_image); the dirty
-                             beam is always FP64 */
+    int image_prec;       /* precision of the dirty beam, the dirty image and every
+                             residual image: SWV_FP64 or SWV_F32C (see
+                             swv_dirty_image) */
 } swv_clean_params_t;
 
 /* Model-visibility predictor of the major cycles.  TREE: the tree of every

@@ -540,8 +540,9 @@ def wavelet_clean(u, v, w, vis_obs, nx: int, ny: int, cell: float, J: int, ra_p:
     """Cotton-Schwab cleaning with the wavelet predictor (sections 2.2, 3.5);
     predictor "degrid" (FFT + degridding of the model image, kernel width
     `support`) or "direct" (direct sum over the model pixels) runs the same
-    loop as conventional or exact clean; image_prec "f32c" forms the dirty and
-    residual images with the FP32-compensated adjoint (the beam stays FP64).  Returns a dict: pix, val (numpy, all
+    loop as conventional or exact clean; image_prec "f32c" forms the dirty
+    beam, the dirty image and the residual images with the FP32-compensated
+    adjoint.  Returns a dict: pix, val (numpy, all
     components in order), residual and beam (device images), vis_model
     (device complex128) and per-cycle stats."""
     if predictor not in PREDICTORS:

@@ -61,11 +61,31 @@ void tune_defaults(swv_ctx ctx) {
 
 int size_class(int64_t rows) { return rows < (int64_t(1) << 20) ? 0 : 1; }
 
-// Rows per chunk so that tiles x chunks gives one full round of resident blocks.
+// Rows per chunk.  Chunks come in groups of 8 with one chunk of each group on
+// each XCD (the block order of the row-chunked kernels), so the chunk count is
+// 8q: an XCD then runs q x tiles blocks in rounds of n_cu x blocks_per_cu / 8,
+// each block doing 1/(8q) of the rows, and the time goes as rounds / q.  q is
+// the smallest minimiser of that, searched up to about 8 rounds per XCD
+// (which also bounds the partial sums, one set per chunk) or one full round,
+// whichever is more.  A count that is not a multiple of 8 would leave the last
+// group's chunks on some XCDs only.
 int64_t choose_chunk(int64_t n_rows, int64_t tiles, int n_cu, int blocks_per_cu) {
     if (n_rows <= 0) return 1;
-    int64_t want = ((int64_t)n_cu * blocks_per_cu + tiles - 1) / tiles;
-    if (want < 1) want = 1;
+    if (tiles < 1) tiles = 1;
+    const int64_t per_xcd = std::max<int64_t>(1, (int64_t)n_cu * blocks_per_cu / 8);
+    const int64_t q_fill = (per_xcd + tiles - 1) / tiles;           // one round or more
+    const int64_t q_rounds = 8 * per_xcd / tiles;                   // about 8 rounds
+    const int64_t q_rows = std::max<int64_t>(1, n_rows / (8 * 64));  // chunks of >= 64 rows
+    const int64_t q_max = std::min<int64_t>(std::max<int64_t>(q_fill, q_rounds), q_rows);
+    int64_t best_q = 1, best_rounds = (tiles + per_xcd - 1) / per_xcd;
+    for (int64_t q = 2; q <= q_max; ++q) {
+        const int64_t rounds = (q * tiles + per_xcd - 1) / per_xcd;
+        if (rounds * best_q < best_rounds * q) {   // rounds / q < best_rounds / best_q
+            best_q = q;
+            best_rounds = rounds;
+        }
+    }
+    const int64_t want = 8 * best_q;
     int64_t chunk = (n_rows + want - 1) / want;
     if (chunk < 64) chunk = 64;
     if (chunk > (int64_t(1) << 30)) chunk = int64_t(1) << 30;  // rows per chunk fit an int

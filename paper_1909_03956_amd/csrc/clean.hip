@@ -681,9 +681,9 @@ extern "C" int swv_wavelet_clean(swv_ctx ctx, const swv_clean_params_t* P, int64
         };
         double scratch_ms = 0.0;
         CLEAN_HIP(hipEventRecord(S.ev[0], s));
-        // the beam once, in FP64 (its FP32C form is no faster at this many pixels)
+        // the beam once, in the images' precision
         CLEAN_RC(swv_dirty_image(ctx, n_vis, u, v, w, nullptr, 2 * nx - 1, 2 * ny - 1, nx - 1,
-                                 ny - 1, P->cell, P->sign, SWV_FP64, beam));
+                                 ny - 1, P->cell, P->sign, P->image_prec, beam));
         CLEAN_RC(lap(stats ? &stats->ms_beam : &scratch_ms));
         CLEAN_RC(swv_dirty_image(ctx, n_vis, u, v, w, vis_obs, nx, ny, nx / 2, ny / 2, P->cell,
                                  P->sign, P->image_prec, residual));
