@@ -180,10 +180,36 @@ def cpu_baseline(n_rows: int) -> dict:
 
 
 # ------------------------------------------------------------------ GPU --
+def _code_tokens(text: str) -> str:
+    """C/C++ source without its comments and with runs of whitespace folded
+    to one space: what the compiler sees of it."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        ch = text[i]
+        if ch in "\"'":                                  # string or character literal
+            j = i + 1
+            while j < n and text[j] != ch:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(ch)
+            i += 1
+    return re.sub(r"\s+", " ", "".join(out)).strip()
+
+
 def source_digest(kernel_file: str, csrc: str | None = None) -> str:
     """SHA-256 (16 hex digits) of a kernel source together with every local
-    header it includes, directly or through other headers, so that a change
-    to any of them marks recorded counters as stale."""
+    header it includes, directly or through other headers, comments left out,
+    so that a change to the code of any of them marks recorded counters as
+    stale."""
     csrc = csrc or os.path.join(ROOT, "paper_1909_03956_amd", "csrc")
     seen, todo = [], [kernel_file]
     while todo:
@@ -195,8 +221,8 @@ def source_digest(kernel_file: str, csrc: str | None = None) -> str:
             todo += re.findall(r'^\s*#include\s+"([^"]+)"', fh.read(), re.M)
     h = hashlib.sha256()
     for name in [seen[0]] + sorted(seen[1:]):
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(name.encode() + b"\0" + fh.read())
+        with open(os.path.join(csrc, name)) as fh:
+            h.update(name.encode() + b"\0" + _code_tokens(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -37,6 +37,15 @@ def test_source_digest_follows_included_headers(tmp_path):
     assert bench.source_digest("k.hip", d) not in (h0, h1)
 
 
+def test_source_digest_ignores_comments(tmp_path):
+    d = _tree(tmp_path, {"k.hip": '#include "a.h"\nint k; // note\n', "a.h": "int a;\n"})
+    h0 = bench.source_digest("k.hip", d)
+    (tmp_path / "a.h").write_text("/* a header */\nint   a;  // the same code\n")
+    assert bench.source_digest("k.hip", d) == h0
+    (tmp_path / "a.h").write_text('const char* s = "// not a comment";\nint a;\n')
+    assert bench.source_digest("k.hip", d) != h0
+
+
 def test_traffic_is_null_once_the_source_changes(tmp_path):
     d = _tree(tmp_path, {"k.hip": '#include "a.h"\n', "a.h": "x\n"})
     rec = tmp_path / "traffic.json"
