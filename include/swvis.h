@@ -236,7 +236,11 @@ int swv_residual_chi2(swv_ctx ctx, int64_t n_vis, const void* vis_obs, const voi
  * centres, n - 1 given explicitly); img_out [n_pix] DEVICE complex128 for
  * both precisions (SWV_F32C: FP32 sincos and products, Kahan sums per
  * visibility chunk).  Deterministic: fixed chunking and summation order.
- * Uses a workspace of 16 * n_pix * ceil(n_vis / chunk) bytes. */
+ * Uses a workspace of 16 * n_pix * ceil(n_vis / chunk) bytes; the chunk
+ * count is a multiple of 8 (a chunk of every group of 8 per XCD) chosen for
+ * whole rounds of resident blocks on each XCD, at most about 8 rounds, which
+ * keeps the workspace under 128 * (pixels per block) * (resident blocks)
+ * bytes (about 240 MB at the default tiling). */
 int swv_adjoint(swv_ctx ctx, int64_t n_vis, const double* u, const double* v, const double* w,
                 const void* y, int64_t n_pix, const double* l, const double* m,
                 const double* nm1, int sign, int prec, void* img_out);
