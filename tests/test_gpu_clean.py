@@ -276,6 +276,13 @@ def test_clean7_full_size(env):
     rb = oc.dirty_image(u, v, w, np.ones(u.size, np.complex128), bl[bsel], bm[bsel], bn[bsel])
     assert np.abs(beam[bsel] - rb).max() <= TOL64
     assert np.all(beam[~inside] == 0.0)
+    # the FP32-compensated beam and image at full size (8 and 32 row chunks here)
+    beam32 = host(swv.dirty_beam(U, V, W, n, n, S.cell, prec="f32c")).ravel()
+    img32 = host(swv.dirty_image(U, V, W, Y, n, n, S.cell, prec="f32c")).ravel()
+    e32 = np.abs(img32[sel] - ref).max() / (np.abs(vis).sum() / u.size)
+    eb32 = np.abs(beam32[bsel] - rb).max()
+    note(f"clean7 f32c: dirty image E_max={e32:.2e}, beam {eb32:.2e}")
+    assert e32 <= 1e-6 and eb32 <= 1e-6 and np.all(beam32[~inside] == 0.0)
     chi2 = [c["chi2"] for c in out["cycles"]]
     note(f"clean7: cycles {out['cycles']}, beam {out['ms_beam']:.1f} ms, "
          f"dirty {out['ms_dirty']:.1f} ms, flux {out['val'].sum():.3f} Jy")
