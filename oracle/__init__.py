@@ -20,10 +20,14 @@ visibility.adjoint         <A x, y> = <x, A^H y> for random complex x, y;
 visibility.grad_direct     central finite differences of chi^2; flux
     gradient equals -2/sigma^2 Re(A^H r); zero at the true model.
 visibility.residual_chi2   chi^2 of known residuals (closed form).
-sphere.*                   N_j = 12 4^(j-1); the twelve base-pixel centres;
-    nested parent rule k_j = k_J >> 2(J-j); round trip pix -> centre -> pix;
-    equal areas (Monte-Carlo chi^2); frame axes (P -> (alpha_P, delta_P),
-    u east, v north); the recommended-resolution table (tests/golden).
+sphere.*                   (pixels found by descent: base pixel, then the
+    child quarter holding the point, level by level) N_j = 12 4^(j-1); the
+    twelve base-pixel centres; every centre is a closed-form centre of the
+    HEALPix ring scheme; children 0/1/2/3 at the south/east/west/north corner
+    of every pixel, every face row, levels 1-29; nested parent rule
+    k_j = k_J >> 2(J-j); round trip pix -> centre -> pix; equal areas
+    (Monte-Carlo chi^2); frame axes (P -> (alpha_P, delta_P), u east,
+    v north); the recommended-resolution table (tests/golden).
 clean.*                    (the clean loop) unit-source dirty image and beam;
     Hogbom as a sort (gain 1, delta beam), as a geometric series, and
     model + residual = image; cross reference = the tree builder's pixels;

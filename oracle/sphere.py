@@ -11,21 +11,23 @@ Pixelisation (section 3.2).  Twelve equal-area base pixels at level j = 1,
 each split into four equal-area children per level, N_j = 12 * 4^(j-1),
 nested indices so that the parent of k is k >> 2 (section 3.5).  The paper
 bases this on HEALPix (Gorski et al. 2005) with its own software; this is
-the HEALPix NESTED scheme at nside = 2^(j-1), written here from the
-geometry of the HEALPix projection:
+the HEALPix NESTED scheme at nside = 2^(j-1), written from the HEALPix
+projection of the sphere onto a plane (Calabretta & Roukema 2007), in units
+of a quarter turn:
 
 * equatorial zone |z| <= 2/3 (z = cos theta): X = phi/(pi/2), Y = 3z/4;
-* polar caps: sigma = sqrt(3 (1 - |z|)), X = Xc + (X0 - Xc) sigma with
-  Xc the centre of the quarter-turn containing phi, Y = +-(1 - sigma/2).
+* polar caps: sigma = sqrt(3 (1 - |z|)), X = Xc + (phi/(pi/2) - Xc) sigma
+  with Xc the centre of the quarter turn containing phi, Y = +-(1 - sigma/2).
 
-In the (X, Y) plane every base pixel is a square rotated by 45 degrees;
-A = X + Y + 1/2 and B = Y + 1/2 - X are coordinates along its two edges,
-floor(A) and floor(B) identify the base pixel (north: floor A + floor B = 1,
-equatorial 0, south -1) and their fractional parts times nside are the
-in-face indices (ix, iy).  The nested index interleaves the bits of ix (even
-positions) and iy (odd positions) under the face number.  Base pixels 0-3
-are centred at z = 2/3, phi = pi/4 + f pi/2; 4-7 at z = 0, phi = f pi/2;
-8-11 at z = -2/3, phi = pi/4 + f pi/2.
+In that plane every base pixel is a square rotated by 45 degrees (a diamond)
+and the four children of a pixel are the quarters of its diamond at its
+south, east, west and north corners, numbered 0, 1, 2, 3.  A point's pixel
+is found as the paper's section 3.5 builds its tree, from the top: the base
+pixel whose diamond holds it, then level by level the quarter that holds it,
+k <- 4k + c.  A pixel's centre is found the same way, moving from the base
+centre towards corner c of every enclosing diamond.  Base pixels 0-3 are
+centred at z = 2/3, phi = pi/4 + f pi/2; 4-7 at z = 0, phi = f pi/2; 8-11 at
+z = -2/3, phi = pi/4 + f pi/2.
 
 All geometry is evaluated in numpy.longdouble (x86 extended precision) and
 rounded to FP64 once, so a pixel centre is the FP64 rounding of the exact
@@ -104,98 +106,114 @@ def radec_to_xyz(ra, dec):
 
 
 # -------------------------------------------------------- nested pixels ----
-def _interleave(ix, iy, bits):
-    out = np.zeros_like(ix)
-    for b in range(bits):
-        out |= ((ix >> b) & 1) << (2 * b)
-        out |= ((iy >> b) & 1) << (2 * b + 1)
-    return out
+# Centres (X, Y) of the twelve base pixels in the projection plane, in
+# quarter turns: 0-3 the north row, 4-7 the equatorial row, 8-11 the south row.
+BASE_X = np.array([0.5, 1.5, 2.5, 3.5, 0.0, 1.0, 2.0, 3.0, 0.5, 1.5, 2.5, 3.5], dtype=LD)
+BASE_Y = np.array([0.5] * 4 + [0.0] * 4 + [-0.5] * 4, dtype=LD)
+
+# Child c of a pixel is the quarter of its diamond at its c-th corner:
+# 0 south, 1 east, 2 west, 3 north.  Offsets of the child's centre from the
+# parent's, in units of half the parent's half-diagonal.
+CHILD_DX = np.array([0, 1, -1, 0], dtype=LD)
+CHILD_DY = np.array([-1, 0, 0, 1], dtype=LD)
 
 
-def _deinterleave(p, bits):
-    ix = np.zeros_like(p)
-    iy = np.zeros_like(p)
-    for b in range(bits):
-        ix |= ((p >> (2 * b)) & 1) << b
-        iy |= ((p >> (2 * b + 1)) & 1) << b
-    return ix, iy
+def _wrap(dX):
+    """An X difference brought into [-2, 2) (X is periodic with period 4)."""
+    return dX - 4 * np.floor((dX + 2) / 4)
+
+
+def project(xyz):
+    """HEALPix projection of unit vectors (3, K) to the plane (X, Y), in units
+    of a quarter turn, and the quarter q of the polar triangle (-1 in the
+    equatorial zone).  Returns (X, Y, q)."""
+    x, z, zx = (np.asarray(c, dtype=LD) for c in xyz)     # z = cos(theta)
+    t = np.arctan2(x, zx) / (PI_LD / 2)                     # phi in quarter turns
+    t = np.where(t < 0, t + 4, t)
+    t = np.where(t >= 4, t - 4, t)
+    polar = np.abs(z) > LD(2) / LD(3)
+    # sigma^2 = 3 (1 - |z|), with 1 - |z| = sin^2(theta) / (1 + |z|)
+    sig = np.sqrt(LD(3) * (x * x + zx * zx) / (LD(1) + np.abs(z)))
+    q = np.minimum(np.floor(t), 3)
+    X = np.where(polar, q + LD(0.5) + (t - q - LD(0.5)) * sig, t)
+    Y = np.where(polar, np.sign(z) * (LD(1) - sig / 2), LD(0.75) * z)
+    return X, Y, np.where(polar, q, -1).astype(np.int64)
+
+
+def _base_pixel(X, Y, q):
+    """The base pixel holding each plane point.  A polar point lies in the
+    triangle of its quarter.  In the equatorial strip the diamonds tile the
+    plane: a diamond holds the points with edge coordinates a = dX + dY and
+    b = dY - dX in [-1/2, 1/2), so a point on an edge goes to the pixel on
+    its northern side."""
+    face = np.full(X.shape, -1, dtype=np.int64)
+    for f in range(12):
+        dX = _wrap(X - BASE_X[f])
+        dY = Y - BASE_Y[f]
+        a, b = dX + dY, dY - dX
+        inside = (a >= -0.5) & (a < 0.5) & (b >= -0.5) & (b < 0.5)
+        face = np.where((face < 0) & inside, f, face)
+    face = np.where(q >= 0, np.where(Y > 0, q, 8 + q), face)
+    assert np.all(face >= 0), "a point outside every base pixel"
+    return face
 
 
 def ang2pix_xyz(j: int, xyz) -> np.ndarray:
-    """Level-j nested pixel index of xyz unit vectors (3, K)."""
-    nside = 1 << (j - 1)
-    x, y, zx = (np.asarray(c, dtype=LD) for c in xyz)
-    z = y                                   # cos(theta) = sin(dec)
-    s2 = x * x + zx * zx                    # sin^2(theta)
-    phi = np.arctan2(x, zx)
-    phi = np.where(phi < 0, phi + 2 * PI_LD, phi)
-    tt = phi / (PI_LD / 2)                  # quarter turns in [0, 4]
-    tt = np.where(tt >= 4, tt - 4, tt)
-    ns = LD(nside)
+    """Level-j nested pixel index of xyz unit vectors (3, K), by descent: the
+    base pixel holding the point, then j - 1 times the child (k <- 4k + c)
+    whose quarter of the current diamond holds it (sections 3.2, 3.5)."""
+    X, Y, q = project(xyz)
+    face = _base_pixel(X, Y, q)
+    dX = _wrap(X - BASE_X[face])          # offset from the current centre
+    dY = Y - BASE_Y[face]
+    pix = face.copy()
+    h = LD(0.5)                           # half-diagonal of the current diamond
+    for _ in range(j - 1):
+        ne = (dX + dY) >= 0               # north-east half of the diamond
+        nw = (dY - dX) >= 0               # north-west half
+        c = ne.astype(np.int64) + 2 * nw.astype(np.int64)
+        pix = 4 * pix + c
+        dX = dX - CHILD_DX[c] * (h / 2)
+        dY = dY - CHILD_DY[c] * (h / 2)
+        h = h / 2
+    return pix
 
-    # equatorial zone
-    A = tt + LD(0.75) * z + LD(0.5)
-    B = LD(0.75) * z + LD(0.5) - tt
-    Na = np.floor(ns * A).astype(np.int64)
-    Nb = np.floor(ns * B).astype(np.int64)
-    p = np.floor_divide(Na, nside)
-    q = np.floor_divide(Nb, nside)
-    ix_e = Na - p * nside
-    iy_e = Nb - q * nside
-    sgn = p + q
-    face_e = np.where(sgn == 0, 4 + np.mod(p, 4),
-                      np.where(sgn > 0, np.mod(p - 1, 4), 8 + np.mod(p, 4)))
 
-    # polar caps: 1 - |z| = sin^2(theta) / (1 + |z|)
-    az = np.abs(z)
-    sig = np.sqrt(LD(3) * s2 / (LD(1) + az))
-    f = np.minimum(np.floor(tt).astype(np.int64), 3)
-    tp = tt - f
-    north = z > 0
-    a_n = LD(1) - sig * (LD(1) - tp)
-    b_n = LD(1) - sig * tp
-    a_s = sig * tp
-    b_s = sig * (LD(1) - tp)
-    a = np.where(north, a_n, a_s)
-    b = np.where(north, b_n, b_s)
-    ix_p = np.clip(np.floor(ns * a).astype(np.int64), 0, nside - 1)
-    iy_p = np.clip(np.floor(ns * b).astype(np.int64), 0, nside - 1)
-    face_p = np.where(north, f, 8 + f)
+def pixel_plane_centre(j: int, pix):
+    """(X, Y) of the centre of level-j nested pixels: the base centre moved
+    towards corner c of each enclosing diamond, level by level."""
+    pix = np.asarray(pix, dtype=np.int64)
+    face = pix >> (2 * (j - 1))
+    X = BASE_X[face].copy()
+    Y = BASE_Y[face].copy()
+    h = LD(0.5)
+    for lev in range(1, j):
+        c = (pix >> (2 * (j - 1 - lev))) & 3
+        X = X + CHILD_DX[c] * (h / 2)
+        Y = Y + CHILD_DY[c] * (h / 2)
+        h = h / 2
+    return X, Y
 
-    polar = az > LD(2) / LD(3)
-    face = np.where(polar, face_p, face_e)
-    ix = np.where(polar, ix_p, ix_e)
-    iy = np.where(polar, iy_p, iy_e)
-    return face * (nside * nside) + _interleave(ix, iy, j - 1)
+
+def unproject(X, Y):
+    """Inverse of `project` for points inside the base pixels: longdouble xyz
+    unit vectors (3, K)."""
+    X = np.asarray(X, dtype=LD)
+    Y = np.asarray(Y, dtype=LD)
+    polar = np.abs(Y) > LD(0.5)
+    sig = np.where(polar, 2 - 2 * np.abs(Y), LD(1))
+    omz = sig * sig / 3                                   # 1 - |z| in the caps
+    z = np.where(polar, np.sign(Y) * (1 - omz), LD(4) * Y / 3)
+    st = np.where(polar, np.sqrt(omz * (2 - omz)), np.sqrt((1 - z) * (1 + z)))
+    xc = np.floor(X) + LD(0.5)                            # centre of the quarter
+    t = np.where(polar, xc + (X - xc) / sig, X)
+    phi = t * (PI_LD / 2)
+    return np.stack([st * np.sin(phi), z, st * np.cos(phi)])
 
 
 def pix2xyz(j: int, pix) -> np.ndarray:
     """Centre of level-j nested pixels as longdouble xyz unit vectors (3, K)."""
-    nside = 1 << (j - 1)
-    pix = np.asarray(pix, dtype=np.int64)
-    face = pix // (nside * nside)
-    ix, iy = _deinterleave(pix % (nside * nside), j - 1)
-    a = (ix.astype(LD) + LD(0.5)) / LD(nside)
-    b = (iy.astype(LD) + LD(0.5)) / LD(nside)
-    f = np.mod(face, 4).astype(LD)
-    ring = face // 4                         # 0 north, 1 equatorial, 2 south
-
-    # (X, Y) of the centre in the projection plane
-    X = np.where(ring == 1, (a - b) / 2 + f, (a - b) / 2 + f + LD(0.5))
-    Y = np.where(ring == 0, (a + b) / 2,
-                 np.where(ring == 1, (a + b - 1) / 2, (a + b - 2) / 2))
-    polar = np.abs(Y) > LD(0.5)
-    sig = np.where(Y > 0, 2 - (a + b), a + b)          # only used where polar
-    sig = np.where(polar, sig, LD(1))
-    omz = sig * sig / 3                                  # 1 - |z| in the caps
-    z = np.where(polar, np.sign(Y) * (1 - omz), LD(4) * Y / 3)
-    # sin(theta) = sqrt((1 - z)(1 + z)), using 1 - |z| directly in the caps
-    s_pol = np.sqrt(omz * (2 - omz))
-    s_eq = np.sqrt((1 - z) * (1 + z))
-    st = np.where(polar, s_pol, s_eq)
-    tt = np.where(polar, f + LD(0.5) + (a - b) / (2 * sig), X)
-    phi = tt * (PI_LD / 2)
-    return np.stack([st * np.sin(phi), z, st * np.cos(phi)])
+    return unproject(*pixel_plane_centre(j, pix))
 
 
 def xyz_to_uvw_lmn(xyz, ra_p, dec_p):

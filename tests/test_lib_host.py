@@ -110,20 +110,50 @@ def test_max_branching_matches_oracle_levels(swv, J):
     assert t.stats()["max_branching"] == _branching_from_levels(ref)
 
 
-def test_ang2pix_and_centres_match_oracle(swv):
+def _sky_points(n, seed):
+    """Directions (l, m) of the uvw frame covering the near hemisphere of a
+    phase centre, and phase centres spread over the sphere, so that every
+    base pixel (north, equatorial and south rows) is visited."""
+    rng = np.random.default_rng(seed)
+    r = np.sqrt(rng.uniform(0, 0.999, n))
+    a = rng.uniform(0, 2 * np.pi, n)
+    return r * np.cos(a), r * np.sin(a)
+
+
+@pytest.mark.parametrize("ra,dec", [(2.2, -0.4), (0.3, 1.2), (4.0, -1.1), (5.9, 0.05)])
+def test_ang2pix_and_centres_match_oracle(swv, ra, dec):
+    # the library's floor-based pixelisation against the oracle's descent by
+    # containment, at every level of the paper's range (J = 1 .. 29)
     from paper_1909_03956_amd.api import ang2pix, pixel_centres
-    rng = np.random.default_rng(3)
-    ra, dec = 2.2, -0.4
-    l = rng.uniform(-0.5, 0.5, 5000)
-    m = rng.uniform(-0.5, 0.5, 5000)
-    for J in (1, 4, 9, 18, 29):
+    l, m = _sky_points(4000, 3)
+    xyz = sp.lm_to_xyz(l, m, ra, dec)
+    faces = set()
+    for J in range(1, 30):
         pix = ang2pix(J, ra, dec, l, m)
-        ref = sp.ang2pix_xyz(J, sp.lm_to_xyz(l, m, ra, dec))
+        ref = sp.ang2pix_xyz(J, xyz)
         assert np.array_equal(pix, ref), J
+        faces |= set((ref >> (2 * (J - 1))).tolist())
         cl, cm, cn = pixel_centres(J, ra, dec, pix)
         rl, rm, rn = sp.pixel_centres_lmn(J, pix, ra, dec)
         for a, b in ((cl, rl), (cm, rm), (cn, rn)):
             assert np.all(np.abs(a - b) <= 2 * np.spacing(np.abs(b))), J
+    assert len(faces) >= 4
+
+
+def test_library_centres_every_pixel_match_oracle(swv):
+    # every pixel of levels 1..5 (all twelve faces): centres and round trip
+    from paper_1909_03956_amd.api import ang2pix, pixel_centres
+    ra, dec = 0.0, 0.0
+    for J in range(1, 6):
+        pix = np.arange(sp.n_pixels(J), dtype=np.int64)
+        cl, cm, cn = pixel_centres(J, ra, dec, pix)
+        rl, rm, rn = sp.pixel_centres_lmn(J, pix, ra, dec)
+        for a, b in ((cl, rl), (cm, rm), (cn, rn)):
+            assert np.all(np.abs(a - b) <= 2 * np.spacing(np.abs(b)) + 1e-300), J
+        # centres on the phase centre's hemisphere map back to their pixel
+        near = cn > -1
+        back = ang2pix(J, ra, dec, cl[near], cm[near])
+        assert np.array_equal(back, pix[near]), J
 
 
 def test_pixels_in_disk_matches_oracle(swv):

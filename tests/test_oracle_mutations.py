@@ -109,12 +109,54 @@ def test_swapped_sign_rows_caught(monkeypatch, golden):
         TT.test_sign_table_matches_eq10(golden)
 
 
+def _swap_east_west(pix, j, rows):
+    """Pixel ids with children 1 and 2 exchanged at every level inside the
+    base pixels of `rows` (0 north, 1 equatorial, 2 south)."""
+    pix = np.asarray(pix, dtype=np.int64)
+    face = pix >> (2 * (j - 1))
+    low = pix & ((1 << (2 * (j - 1))) - 1)
+    swapped = np.zeros_like(low)
+    for b in range(j - 1):
+        c = (low >> (2 * b)) & 3
+        c = np.where(c == 1, 2, np.where(c == 2, 1, c))
+        swapped |= c << (2 * b)
+    return np.where(np.isin(face // 4, rows), (face << (2 * (j - 1))) | swapped, pix)
+
+
+def _plant_transposition(monkeypatch, rows):
+    orig_a, orig_c = sp.ang2pix_xyz, sp.pixel_plane_centre
+    monkeypatch.setattr(sp, "ang2pix_xyz",
+                        lambda j, xyz: _swap_east_west(orig_a(j, xyz), j, rows))
+    monkeypatch.setattr(sp, "pixel_plane_centre",
+                        lambda j, pix: orig_c(j, _swap_east_west(pix, j, rows)))
+
+
 def test_swapped_in_face_axes_caught(monkeypatch):
-    orig_i, orig_d = sp._interleave, sp._deinterleave
-    monkeypatch.setattr(sp, "_interleave", lambda ix, iy, b: orig_i(iy, ix, b))
-    monkeypatch.setattr(sp, "_deinterleave", lambda p, b: orig_d(p, b)[::-1])
+    # ix and iy transposed in every base pixel
+    _plant_transposition(monkeypatch, [0, 1, 2])
+    TS.test_round_trip_every_pixel(3)         # still a consistent pixelisation
     with pytest.raises(AssertionError):
         TS.test_nested_child_layout()
+
+
+def test_south_face_transposition_caught(monkeypatch):
+    # ix and iy transposed inside the south-row base pixels only, consistently
+    # in ang2pix and the centres: a valid equal-area nested pixelisation that
+    # differs from HEALPix NESTED only in the labels of the southern children,
+    # so V is unchanged but the Eq. 10 coefficients of those nodes are not.
+    _plant_transposition(monkeypatch, [2])
+    for j in (2, 3, 4):
+        TS.test_round_trip_every_pixel(j)
+        TS.test_centres_are_the_ring_scheme_centres(j)
+    TS.test_children_centres_inside_parent(3)
+    TS.test_nested_parent_rule_random_points()
+    TS.test_equal_area_monte_carlo()
+    with pytest.raises(AssertionError):
+        TS.test_nested_child_layout()
+    with pytest.raises(AssertionError):
+        TS.test_level2_children_closed_form()
+    with pytest.raises(AssertionError):
+        TS.test_child_layout_every_pixel(3)
 
 
 def test_wrong_south_face_offset_caught(monkeypatch):

@@ -76,6 +76,45 @@ def test_equal_area_monte_carlo():
     assert abs(chi2 - dof) < 6 * math.sqrt(2 * dof), chi2
 
 
+def _ring_centres(nside):
+    """Pixel centres (z, phi) of the HEALPix ring scheme (Gorski et al. 2005),
+    ring by ring from the north pole: polar ring i < nside holds 4 i centres
+    at z = 1 - i^2 / (3 nside^2), phi = (pi / (2 i)) (k - 1/2); the rings
+    nside <= i <= 3 nside hold 4 nside centres at z = 4/3 - 2 i / (3 nside),
+    phi = (pi / (2 nside)) (k - s/2) with s = (i - nside + 1) mod 2; the
+    southern polar rings mirror the northern ones."""
+    out = []
+    for i in range(1, nside):
+        k = np.arange(1, 4 * i + 1)
+        z = 1 - i * i / (3 * nside * nside)
+        for zz in (z, -z):
+            out += [(zz, p) for p in np.pi / (2 * i) * (k - 0.5)]
+    for i in range(nside, 3 * nside + 1):
+        k = np.arange(1, 4 * nside + 1)
+        s_ = (i - nside + 1) % 2
+        z = 4 / 3 - 2 * i / (3 * nside)
+        out += [(z, p) for p in np.pi / (2 * nside) * (k - s_ / 2)]
+    return np.array(out)
+
+
+@pytest.mark.parametrize("j", [1, 2, 3, 4, 5])
+def test_centres_are_the_ring_scheme_centres(j):
+    # the set of nested centres equals the ring scheme's closed-form centres
+    nside = 1 << (j - 1)
+    c = sp.pix2xyz(j, np.arange(sp.n_pixels(j)))
+    z = np.asarray(c[1], float)
+    phi = np.mod(np.arctan2(np.asarray(c[0], float), np.asarray(c[2], float)), 2 * np.pi)
+    ref = _ring_centres(nside)
+    assert ref.shape[0] == sp.n_pixels(j)
+    got = np.stack([z, phi], 1)
+    # phi within 1e-12 of 2 pi is the same direction as phi = 0
+    got[:, 1] = np.where(got[:, 1] > 2 * np.pi - 1e-12, 0.0, got[:, 1])
+    ref[:, 1] = np.mod(ref[:, 1], 2 * np.pi)
+    key = lambda a: np.lexsort((np.round(a[:, 1], 9), np.round(a[:, 0], 9)))  # noqa: E731
+    g, r = got[key(got)], ref[key(ref)]
+    assert np.max(np.abs(g - r)) < 1e-13
+
+
 @pytest.mark.parametrize("j", [2, 3])
 def test_iso_latitude_rings(j):
     # HEALPix centres lie on 4 nside - 1 rings; polar ring i (1..nside-1
@@ -171,14 +210,64 @@ def test_disk_pixels_are_exactly_those_within_radius():
     assert abs(len(pix) - expect) < 0.25 * expect
 
 
+def _child_layout_violations(j, parents):
+    """Parents at level j whose children 4k + c break the nested layout:
+    child 0 at the southern corner (lowest z), 1 the eastern and 2 the
+    western (equal z, 1 east of 2), 3 the northern (highest z)."""
+    ch = (np.asarray(parents, np.int64)[:, None] * 4 + np.arange(4)).ravel()
+    c = sp.pix2xyz(j + 1, ch)
+    z = np.asarray(c[1], float).reshape(-1, 4)
+    phi = np.arctan2(np.asarray(c[0], float), np.asarray(c[2], float)).reshape(-1, 4)
+    east = np.angle(np.exp(1j * (phi[:, 1] - phi[:, 2])))      # phi_1 - phi_2 in (-pi, pi]
+    ok = (z[:, 0] < z[:, 1]) & (z[:, 1] == z[:, 2]) & (z[:, 2] < z[:, 3]) & (east > 0)
+    return np.asarray(parents)[~ok]
+
+
 def test_nested_child_layout():
     # HEALPix NESTED (Gorski et al. 2005): inside a base pixel the x index
     # grows towards the north-east edge and y towards the north-west edge, so
     # child 0 is the southern corner, 1 the eastern, 2 the western, 3 the
-    # northern one.
-    c = sp.pix2xyz(2, np.arange(4))
-    z = np.asarray(c[1], float)
-    phi = np.arctan2(np.asarray(c[0], float), np.asarray(c[2], float))
-    assert z[0] < z[1] and z[0] < z[2] and z[3] > z[1] and z[3] > z[2]
-    assert phi[1] > phi[0] > phi[2]
-    assert z[1] == pytest.approx(z[2], abs=1e-15)
+    # northern one -- in every base pixel: north row (0-3), equatorial row
+    # (4-7) and south row (8-11).
+    assert _child_layout_violations(1, np.arange(12)).size == 0
+    for face in (0, 4, 8):          # one base pixel per row, spelt out
+        c = sp.pix2xyz(2, 4 * face + np.arange(4))
+        z = np.asarray(c[1], float)
+        phi = np.arctan2(np.asarray(c[0], float), np.asarray(c[2], float))
+        assert z[0] < z[1] and z[0] < z[2] and z[3] > z[1] and z[3] > z[2], face
+        assert np.angle(np.exp(1j * (phi[1] - phi[0]))) > 0, face
+        assert np.angle(np.exp(1j * (phi[0] - phi[2]))) > 0, face
+        assert z[1] == pytest.approx(z[2], abs=1e-15)
+
+
+def test_level2_children_closed_form():
+    # The children of base pixels 0, 4 and 8 at level 2 (nside = 2), from the
+    # ring scheme: north face 0 (centre z = 2/3, phi = pi/4) has its children
+    # at z = 1/3 (south), 2/3 (east, west), 11/12 (north); equatorial face 4
+    # (z = 0, phi = 0) at -1/3, 0, 0, 1/3; south face 8 at -11/12, -2/3, -2/3,
+    # -1/3.  East and west sit pi/8 either side of the face centre's phi.
+    q = np.pi / 8
+    expect = {
+        0: [(1 / 3, 2 * q), (2 / 3, 3 * q), (2 / 3, q), (11 / 12, 2 * q)],
+        4: [(-1 / 3, 0.0), (0.0, q), (0.0, -q), (1 / 3, 0.0)],
+        8: [(-11 / 12, 2 * q), (-2 / 3, 3 * q), (-2 / 3, q), (-1 / 3, 2 * q)],
+    }
+    for face, rows in expect.items():
+        c = sp.pix2xyz(2, 4 * face + np.arange(4))
+        z = np.asarray(c[1], float)
+        phi = np.arctan2(np.asarray(c[0], float), np.asarray(c[2], float))
+        for cc, (ze, pe) in enumerate(rows):
+            assert z[cc] == pytest.approx(ze, abs=1e-15), (face, cc)
+            assert phi[cc] == pytest.approx(pe, abs=1e-15), (face, cc)
+
+
+@pytest.mark.parametrize("j", [1, 2, 3, 4, 5])
+def test_child_layout_every_pixel(j):
+    assert _child_layout_violations(j, np.arange(sp.n_pixels(j))).size == 0
+
+
+@pytest.mark.parametrize("j", [9, 17, 28])
+def test_child_layout_deep_levels(j):
+    rng = np.random.default_rng(j)
+    parents = rng.integers(0, sp.n_pixels(j), 3000, dtype=np.int64)
+    assert _child_layout_violations(j, parents).size == 0
