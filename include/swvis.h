@@ -28,10 +28,14 @@
  *    the kernels detect (non-finite or out-of-domain inputs) and HIP faults
  *    are reported by the next swv_ctx_synchronize() on that context.
  *  - Library objects (swv_ctx, swv_tree, swv_plan, swv_graph) follow
- *    create/destroy pairs.  A plan keeps its context alive and a graph its
- *    plan, so they may be destroyed in any order (memory is released with the
- *    last of them).  A context may be used from one thread at a time; calls
+ *    create/destroy pairs.  A plan keeps its context and its trees alive and
+ *    a graph its plan, so they may be destroyed in any order (memory is
+ *    released with the last of them); a handle must not be used after its
+ *    destroy call.  A context may be used from one thread at a time; calls
  *    that overlap on one stream are ordered by the stream.
+ *  - Destroy every object before the process exits: the destroy calls wait
+ *    for the streams and release device memory while the HIP runtime (and
+ *    any tool attached to it) is still up.
  *  - n = 0 is valid everywhere and enqueues nothing (outputs untouched,
  *    except reductions, which write zero).
  */
@@ -196,6 +200,9 @@ int swv_predict_tree_leaves(swv_ctx ctx, swv_tree tree, int64_t n_vis, const dou
                             const double* v, const double* w, int sign, int prec,
                             void* vis_out);
 
+/* Releases the caller's handle.  A plan made with the tree holds its own
+ * reference (its device records stay valid until the plan and its graphs are
+ * destroyed); the tree is freed with the last reference. */
 int swv_tree_destroy(swv_tree tree);
 
 /* ------------------------------------------------------ sphere pixels --- */

@@ -4,6 +4,7 @@ from __future__ import annotations
 
 import atexit
 import ctypes as C
+import weakref
 
 import numpy as np
 import torch
@@ -14,10 +15,33 @@ from ._lib import (PREDICTORS, SWV_F32C, SWV_FP64, SWV_HOGBOM_ABS, SWV_HOGBOM_SI
 
 PRECISIONS = {"fp64": SWV_FP64, "f32c": SWV_F32C}
 
-# At interpreter exit, objects are collected in no useful order; the process
-# end releases device memory anyway, so finalizers then do nothing.
-_EXITING = [False]
-atexit.register(lambda: _EXITING.__setitem__(0, True))
+# Live library objects by kind.  At interpreter exit they are destroyed in
+# dependency order -- graphs, plans, trees, contexts (and with them the FFT
+# plans of the degridding predictor) -- from an atexit hook, which runs before
+# Python tears down its modules and before the HIP runtime and any tool
+# attached to it shut down.  Finalizers left to module teardown would run in
+# no useful order, and objects never destroyed would be released by the
+# runtime's own exit handlers.
+_LIVE = {kind: weakref.WeakSet() for kind in ("graph", "plan", "tree", "ctx")}
+
+
+def _track(kind, obj):
+    _LIVE[kind].add(obj)
+
+
+def shutdown():
+    """Destroys every live library object in dependency order (registered to
+    run at interpreter exit; safe to call earlier, objects are then closed)."""
+    for kind in ("graph", "plan", "tree", "ctx"):
+        for obj in list(_LIVE[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+    _CONTEXTS.clear()
+
+
+atexit.register(shutdown)
 
 
 def _prec(p) -> int:
@@ -79,6 +103,7 @@ class Context:
         self.stream = stream
         self._h = C.c_void_p()
         check(lib().swv_ctx_create(dev.index, C.c_void_p(stream.cuda_stream), C.byref(self._h)))
+        _track("ctx", self)
 
     @property
     def handle(self):
@@ -117,11 +142,9 @@ class Context:
             self._h = C.c_void_p()
 
     def __del__(self):
-        # skipped at interpreter shutdown (module globals may be gone; the
-        # process exit frees everything); never raises
+        # never raises (at interpreter exit shutdown() has already closed it)
         try:
-            if not _EXITING[0]:
-                self.close()
+            self.close()
         except Exception:
             pass
 
@@ -179,6 +202,7 @@ class Tree:
         self._h = C.c_void_p()
         check(lib().swv_tree_build(int(J), float(ra_p), float(dec_p), l.size, _np_ptr(l),
                                    _np_ptr(m), _np_ptr(flux), C.byref(self._h)))
+        _track("tree", self)
         self.J, self.ra_p, self.dec_p = int(J), float(ra_p), float(dec_p)
 
     @classmethod
@@ -193,6 +217,7 @@ class Tree:
         t._h = C.c_void_p()
         check(lib().swv_tree_build_pixels(int(J), float(ra_p), float(dec_p), pix.size,
                                           _np_ptr(pix), _np_ptr(flux), C.byref(t._h)))
+        _track("tree", t)
         t.J, t.ra_p, t.dec_p = int(J), float(ra_p), float(dec_p)
         return t
 
@@ -278,11 +303,9 @@ class Tree:
             self._h = C.c_void_p()
 
     def __del__(self):
-        # skipped at interpreter shutdown (module globals may be gone; the
-        # process exit frees everything); never raises
+        # never raises (at interpreter exit shutdown() has already closed it)
         try:
-            if not _EXITING[0]:
-                self.close()
+            self.close()
         except Exception:
             pass
 
@@ -339,7 +362,7 @@ def residual_chi2(vis_obs, vis_model, inv_sigma2: float, out=None):
     return resid, chi2
 
 
-def adjoint(u, v, w, y, l, m, nm1, sign: int = -1, prec="fp64"):
+def adjoint(u, v, w, y, l, m, nm1, sign: int = -1, prec="fp64", out=None):
     """x_p = sum_j conj(e_jp) y_j on the pixel set (l, m, n - 1); complex128."""
     u = _dev_f64(u, "u")
     dev = u.device
@@ -349,10 +372,14 @@ def adjoint(u, v, w, y, l, m, nm1, sign: int = -1, prec="fp64"):
     n, P = u.numel(), l.numel()
     if v.numel() != n or w.numel() != n or y.numel() != n or m.numel() != P or nm1.numel() != P:
         raise ValueError("length mismatch")
-    out = torch.empty(P, dtype=torch.complex128, device=dev)
+    if out is None:
+        out = torch.empty(P, dtype=torch.complex128, device=dev)
+    elif (out.dtype != torch.complex128 or out.numel() != P or not out.is_contiguous()
+          or out.device != dev):
+        raise ValueError("out must be a contiguous complex128 tensor of n_pix entries")
     ctx = context(dev)
-    check(lib().swv_adjoint(ctx.handle, n, _ptr(u), _ptr(v), _ptr(w), _ptr(y), P, _ptr(l),
-                            _ptr(m), _ptr(nm1), sign, _prec(prec), _ptr(out)))
+    check(lib().swv_adjoint(ctx.handle, n, _ptr(u), _ptr(v), _ptr(w), _ptr(y), P, _ptr(l), _ptr(m), _ptr(nm1),
+             sign, _prec(prec), _ptr(out)))
     return out
 
 
@@ -583,6 +610,7 @@ class Graph:
         self.plan = plan
         self._h = C.c_void_p()
         check(lib().swv_graph_capture(plan.handle, C.byref(self._h)))
+        _track("graph", self)
 
     def launch(self):
         check(lib().swv_graph_launch(self._h))
@@ -593,11 +621,9 @@ class Graph:
             self._h = C.c_void_p()
 
     def __del__(self):
-        # skipped at interpreter shutdown (module globals may be gone; the
-        # process exit frees everything); never raises
+        # never raises (at interpreter exit shutdown() has already closed it)
         try:
-            if not _EXITING[0]:
-                self.close()
+            self.close()
         except Exception:
             pass
 
@@ -648,6 +674,7 @@ class BatchPlan:
         self.ctx = context(dev if device is None else device)
         self._h = C.c_void_p()
         check(lib().swv_batch_plan(self.ctx.handle, len(instances), arr, C.byref(self._h)))
+        _track("plan", self)
 
     @property
     def handle(self):
@@ -670,11 +697,9 @@ class BatchPlan:
             self._h = C.c_void_p()
 
     def __del__(self):
-        # skipped at interpreter shutdown (module globals may be gone; the
-        # process exit frees everything); never raises
+        # never raises (at interpreter exit shutdown() has already closed it)
         try:
-            if not _EXITING[0]:
-                self.close()
+            self.close()
         except Exception:
             pass
 

@@ -186,6 +186,37 @@ TreeArgs tree_args(swv_tree t, const TRec* d_rec) {
     return a;
 }
 
+int check_adjoint_args(const char* who, swv_ctx ctx, int64_t n_vis, const double* u,
+                       const double* v, const double* w, const void* y, int64_t n_pix,
+                       const double* l, const double* m, const double* nm1, int sign, int prec,
+                       const void* img_out) {
+    if (!ctx) return fail(SWV_EINVAL, "%s: null context", who);
+    if (n_vis < 0 || n_pix < 0) return fail(SWV_EINVAL, "%s: negative size", who);
+    if (n_vis > 0 && (!u || !v || !w || !y))
+        return fail(SWV_EINVAL, "%s: null visibility pointer", who);
+    if (n_pix > 0 && (!l || !m || !nm1 || !img_out))
+        return fail(SWV_EINVAL, "%s: null pixel pointer", who);
+    if (sign != 1 && sign != -1) return fail(SWV_EDOMAIN, "sign must be +1 or -1 (got %d)", sign);
+    if (prec != SWV_FP64 && prec != SWV_F32C)
+        return fail(SWV_EINVAL, "%s: unsupported precision %d", who, prec);
+    return SWV_OK;
+}
+
+AdjointShape adjoint_shape(swv_ctx ctx, int64_t n_vis, int64_t n_pix, int prec) {
+    AdjointShape sh;
+    const int sc = size_class(n_vis);
+    sh.ppl = ctx->per_lane[kFamAdjoint][sc];
+    sh.block = ctx->block[kFamAdjoint][sc];
+    const int64_t tiles = (n_pix + (int64_t)sh.ppl * sh.block - 1) / ((int64_t)sh.ppl * sh.block);
+    sh.chunk = choose_chunk(n_vis, tiles, ctx->n_cu, adjoint_blocks_per_cu(prec, sh.ppl, sh.block));
+    sh.n_chunks = n_vis > 0 ? (n_vis + sh.chunk - 1) / sh.chunk : 0;
+    return sh;
+}
+
+size_t adjoint_partial_bytes(const AdjointShape& sh, int64_t n_pix) {
+    return 16 * (size_t)n_pix * (size_t)(sh.n_chunks > 0 ? sh.n_chunks : 1);
+}
+
 void ctx_release(swv_ctx ctx) {
     if (--ctx->refs > 0) return;
     {
@@ -499,6 +530,7 @@ int swv_predict_tree_leaves(swv_ctx ctx, swv_tree t, int64_t n_vis, const double
 
 int swv_tree_destroy(swv_tree t) {
     if (!t) return SWV_OK;
+    if (--t->refs > 0) return SWV_OK;   // a plan still reads its device records
     for (auto* copies : {&t->device_records, &t->device_leaves})
         for (auto& kv : *copies) {
             DeviceGuard g(kv.first);
@@ -617,26 +649,17 @@ int swv_residual_chi2(swv_ctx ctx, int64_t n_vis, const void* vis_obs, const voi
 int swv_adjoint(swv_ctx ctx, int64_t n_vis, const double* u, const double* v, const double* w,
                 const void* y, int64_t n_pix, const double* l, const double* m,
                 const double* nm1, int sign, int prec, void* img_out) {
-    CHECK_CTX(ctx);
-    if (n_vis < 0 || n_pix < 0) return fail(SWV_EINVAL, "swv_adjoint: negative size");
-    NEED(u, n_vis); NEED(v, n_vis); NEED(w, n_vis); NEED(y, n_vis);
-    NEED(l, n_pix); NEED(m, n_pix); NEED(nm1, n_pix); NEED(img_out, n_pix);
-    if (sign != 1 && sign != -1) return fail(SWV_EDOMAIN, "sign must be +1 or -1 (got %d)", sign);
-    if (prec != SWV_FP64 && prec != SWV_F32C)
-        return fail(SWV_EINVAL, "swv_adjoint: unsupported precision %d", prec);
-    int rc = SWV_OK;
+    int rc = check_adjoint_args("swv_adjoint", ctx, n_vis, u, v, w, y, n_pix, l, m, nm1, sign,
+                                prec, img_out);
+    if (rc) return rc;
     if (n_pix == 0) return SWV_OK;
     TRY_BEGIN
     GUARD(ctx);
-    const int sc = size_class(n_vis);
-    const int ppl = ctx->per_lane[kFamAdjoint][sc], block = ctx->block[kFamAdjoint][sc];
-    const int64_t tiles = (n_pix + (int64_t)ppl * block - 1) / ((int64_t)ppl * block);
-    const int64_t chunk = choose_chunk(n_vis, tiles, ctx->n_cu, adjoint_blocks_per_cu(prec, ppl, block));
-    const int64_t n_chunks = n_vis > 0 ? (n_vis + chunk - 1) / chunk : 0;
-    rc = ensure(ctx, ctx->partial, 16 * (size_t)n_pix * (size_t)(n_chunks > 0 ? n_chunks : 1));
+    const AdjointShape sh = adjoint_shape(ctx, n_vis, n_pix, prec);
+    rc = ensure(ctx, ctx->partial, adjoint_partial_bytes(sh, n_pix));
     if (rc) return rc;
-    HIPCALL(launch_adjoint(ctx->stream, prec, ppl, block, chunk, n_vis, u, v, w, y, n_pix, l, m,
-                           nm1, sign, ctx->partial.p, img_out));
+    HIPCALL(launch_adjoint(ctx->stream, prec, sh.ppl, sh.block, sh.chunk, n_vis, u, v, w, y,
+                           n_pix, l, m, nm1, sign, ctx->partial.p, img_out));
     return SWV_OK;
     TRY_END
 }

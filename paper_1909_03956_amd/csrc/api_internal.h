@@ -71,4 +71,20 @@ int tree_walker(swv_tree t, int preferred);
 // Releases a plan made by the degridding predictor (no-op on NULL).
 void destroy_fft_plan(void* plan);
 
+// Argument checks shared by the adjoint entry points (status code).
+int check_adjoint_args(const char* who, swv_ctx ctx, int64_t n_vis, const double* u,
+                       const double* v, const double* w, const void* y, int64_t n_pix,
+                       const double* l, const double* m, const double* nm1, int sign, int prec,
+                       const void* img_out);
+// Tile shape and row chunking of the adjoint for a problem size; the chunk
+// count fixes the summation order, so two calls with the same shape give the
+// same bits.
+struct AdjointShape {
+    int ppl = 1, block = 64;
+    int64_t chunk = 1, n_chunks = 0;
+};
+AdjointShape adjoint_shape(swv_ctx ctx, int64_t n_vis, int64_t n_pix, int prec);
+// Bytes of per-chunk partial sums the adjoint needs (complex128 per chunk and pixel).
+size_t adjoint_partial_bytes(const AdjointShape& sh, int64_t n_pix);
+
 }  // namespace swv

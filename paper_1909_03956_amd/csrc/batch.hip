@@ -18,6 +18,7 @@ struct swv_plan_s {
     swv_ctx ctx = nullptr;
     int64_t n_inst = 0;
     std::vector<BatchInst> direct, tree;
+    std::vector<swv_tree> trees;      // held (one reference each) while the plan lives
     BatchInst* d_direct = nullptr;
     BatchInst* d_tree = nullptr;
     WorkItem* d_items_direct = nullptr;
@@ -71,6 +72,7 @@ void plan_release(swv_plan p) {
                         (void*)p->d_items_tree32, (void*)p->d_pack, (void*)p->d_counters})
             if (q) (void)hipFree(q);
     }
+    for (swv_tree t : p->trees) (void)swv_tree_destroy(t);   // drops the plan's reference
     delete p;
     ctx_release(ctx);
 }
@@ -290,6 +292,12 @@ int swv_batch_plan(swv_ctx ctx, int n, const swv_instance* inst, swv_plan* out) 
         return fail(SWV_ENOMEM, "swv_batch_plan: host allocation failed");
     }
     ++ctx->refs;  // the plan keeps its context alive
+    // and every tree whose device records it reads
+    for (int k = 0; k < n; ++k)
+        if (inst[k].route == SWV_ROUTE_TREE) {
+            ++inst[k].tree->refs;
+            p->trees.push_back(inst[k].tree);
+        }
     *out = p;
     clear_error();
     return SWV_OK;

@@ -41,6 +41,9 @@ struct swv_tree_s {
     // device copies of the leaves packed as direct-sum components (l, m, n - 1,
     // flux), one per HIP device id (swv_predict_tree_leaves)
     std::map<int, void*> device_leaves;
+    // the caller's handle plus one per plan that reads the device records; the
+    // tree is freed when the last of them is released
+    int refs = 1;
 };
 
 namespace swv {

@@ -301,3 +301,65 @@ def test_batch_f32c_trees_bitwise(env):
                             out=torch.empty(777, dtype=torch.complex128, device="cuda"))])
     graph.close()
     plan.close()
+
+
+def test_plan_keeps_destroyed_tree_alive(env):
+    # the caller's tree handle is destroyed right after planning (the C ABI's
+    # swv_tree_destroy); the plan and its graph hold their own reference, so
+    # their runs still read valid records and predict the same values
+    torch, swv = env
+    from paper_1909_03956_amd._lib import SWV_OK
+    rng = np.random.default_rng(31)
+    n, k = 20000, 150
+    u, v, w = (dev(rng.uniform(-3e4, 3e4, n), torch) for _ in range(3))
+    l, m, f = rng.uniform(-0.03, 0.03, k), rng.uniform(-0.03, 0.03, k), rng.lognormal(-3, 1, k)
+    ref = swv.Tree(9, 1.0, 0.3, l, m, f).predict(u, v, w)
+    t = swv.Tree(9, 1.0, 0.3, l, m, f)
+    out = torch.full((n,), 7.0, dtype=torch.complex128, device="cuda")
+    plan = swv.BatchPlan([dict(route="tree", tree=t, u=u, v=v, w=w, out=out)])
+    graph = plan.capture()
+    assert swv.lib().swv_tree_destroy(t.handle) == SWV_OK   # the caller's reference
+    t._h = type(t._h)()                                     # the wrapper must not release it again
+    plan.run()
+    swv.synchronize()
+    assert torch.equal(out, ref)
+    out.zero_()
+    graph.launch()
+    swv.synchronize()
+    assert torch.equal(out, ref)
+    graph.close()
+    plan.close()   # frees the tree with the plan's reference
+
+
+def test_process_exit_after_every_kind_of_object(env, tmp_path):
+    # a process that leaves contexts (with an FFT plan), trees, plans and
+    # graphs alive and has run a cooperative Hogbom cycle exits normally: the
+    # binding destroys them in dependency order from its exit hook
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = r'''
+import numpy as np, torch
+import paper_1909_03956_amd as swv
+from paper_1909_03956_amd import api
+d = torch.device("cuda", 0)
+rng = np.random.default_rng(1)
+D = lambda x: torch.as_tensor(x, dtype=torch.float64, device=d)
+u, v, w = (D(rng.uniform(-400.0, 400.0, 5000)) for _ in range(3))
+l, m, f = rng.uniform(-0.02, 0.02, 50), rng.uniform(-0.02, 0.02, 50), rng.lognormal(-3, 1, 50)
+t = swv.Tree(8, 0.5, 0.4, l, m, f)
+out = torch.empty(5000, dtype=torch.complex128, device=d)
+plan = swv.BatchPlan([dict(route="tree", tree=t, u=u, v=v, w=w, out=out)])
+g = plan.capture(); g.launch()
+img = torch.zeros((160, 160), dtype=torch.float64, device=d); img[80, 80] = 1.0
+vis, st = swv.predict_degrid(img, u, v, w, 1e-3, support=6)
+beam = torch.zeros((319, 319), dtype=torch.float64, device=d); beam[159, 159] = 1.0
+pix, val = swv.hogbom(img, beam, 0.5, 0.0, 5)
+torch.cuda.synchronize()
+print("live", {k: len(s) for k, s in api._LIVE.items()}, flush=True)
+'''
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=300)
+    note(r.stdout.strip(), r.stderr.strip()[-500:])
+    assert r.returncode == 0, (r.returncode, r.stderr[-2000:])
+    assert "live" in r.stdout

@@ -178,6 +178,28 @@ def _nested_components(j0, J=29, ra=0.3, dec=0.4, l0=0.01, m0=0.003):
     return np.array(ls), np.array(ms)
 
 
+def _oracle_tree_on_library_pixels(J, ra, dec, l, m, f):
+    """The oracle's tree of components that sit on pixel edges (the centre of
+    a level-j pixel is a corner of its descendants), built on the library's
+    choice of pixel for each: where the two pixelisations part, the point must
+    lie within 1e-12 rad of an edge, i.e. a nudge of 1e-12 rad towards the
+    library's pixel centre puts it there for the oracle too (reading C-T7)."""
+    from oracle import clean as oc
+    from oracle import sphere as sp
+    from paper_1909_03956_amd.api import ang2pix
+    lib = ang2pix(J, ra, dec, l, m)
+    ora = sp.ang2pix_xyz(J, sp.lm_to_xyz(l, m, ra, dec))
+    bad = np.nonzero(lib != ora)[0]
+    if bad.size:
+        P = sp.lm_to_xyz(l[bad], m[bad], ra, dec)
+        d = sp.pix2xyz(J, lib[bad]) - P
+        Q = P + sp.LD(1e-12) * d / np.sqrt((d * d).sum(0))
+        Q = Q / np.sqrt((Q * Q).sum(0))
+        assert np.array_equal(sp.ang2pix_xyz(J, Q), lib[bad]), "not an edge tie"
+    note(f"components on edges: {bad.size} of {l.size} assigned across an edge")
+    return oc.tree_from_pixels(J, ra, dec, lib, f)
+
+
 def _with_walker(swv, walker, fn):
     """Runs fn() with the tree traversal forced to `walker` (1 level, 2 branch)."""
     from paper_1909_03956_amd._lib import FAM_TREE
@@ -224,7 +246,7 @@ def test_walkers_bitwise_equal_small_trees(env, J):
     assert torch.equal(a, b)
 
 
-def _deep_case(env, J, l, m, f, nv, seed, scale):
+def _deep_case(env, J, l, m, f, nv, seed, scale, on_edges=False):
     torch, swv = env
     ra, dec = 0.3, 0.4
     rng = np.random.default_rng(seed)
@@ -232,7 +254,8 @@ def _deep_case(env, J, l, m, f, nv, seed, scale):
     t = swv.Tree(J, ra, dec, l, m, f)
     got = host(t.predict(dev(u, torch), dev(v, torch), dev(w, torch)))
     swv.synchronize()
-    rt = ot.build_tree(J, ra, dec, l, m, f)
+    rt = (_oracle_tree_on_library_pixels(J, ra, dec, l, m, f) if on_edges
+          else ot.build_tree(J, ra, dec, l, m, f))
     assert t.stats()["n_leaves"] == rt.n_leaves
     ref = ot.predict_tree(rt, u, v, w)
     snapped = ot.predict_snapped(rt, u, v, w)
@@ -260,7 +283,7 @@ def test_deepest_supported_branching(env):
     f = np.random.default_rng(5).lognormal(-3, 1, l.size)
     torch, swv = env
     assert swv.Tree(29, 0.3, 0.4, l, m, f).stats()["max_branching"] == 15
-    _deep_case(env, 29, l, m, f, 300, 7, 4.6e5)
+    _deep_case(env, 29, l, m, f, 300, 7, 4.6e5, on_edges=True)
 
 
 def test_too_many_branchings_not_supported(env):
@@ -395,7 +418,7 @@ def test_leaf_sum_follows_set_flux_and_needs_no_walker(env):
     u, v, w = (rng.uniform(-4.6e5, 4.6e5, 700) for _ in range(3))
     U, V, Wt = dev(u, torch), dev(v, torch), dev(w, torch)
     got = host(t.predict_leaves(U, V, Wt))
-    rt = ot.build_tree(29, 0.3, 0.4, l, m, f)
+    rt = _oracle_tree_on_library_pixels(29, 0.3, 0.4, l, m, f)
     bound = fp64_row_bound(u, v, w, rt.leaf_l, rt.leaf_m, rt.leaf_nm1, rt.leaf_flux)
     assert np.all(np.abs(got - ot.predict_snapped(rt, u, v, w)) <= bound)
     # new leaf fluxes reach the device copy of the leaves

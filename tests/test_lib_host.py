@@ -300,3 +300,27 @@ def test_fit_clean_beam_matches_oracle(swv):
 
 
 TrackSpecSmall = configs.TrackSpec(27, 1.7e3, 45.0, 2016.0, 4, 1.0e7, seed=731)
+
+
+def test_shutdown_closes_in_dependency_order(monkeypatch):
+    # at interpreter exit the binding destroys graphs, then plans, then trees,
+    # then contexts (the C side releases device memory while the runtime is up)
+    import weakref
+
+    from paper_1909_03956_amd import api
+    order = []
+
+    class Obj:
+        def __init__(self, kind):
+            self.kind = kind
+
+        def close(self):
+            order.append(self.kind)
+
+    objs = [Obj(k) for k in ("ctx", "tree", "graph", "plan", "tree", "ctx", "graph")]
+    live = {k: weakref.WeakSet() for k in ("graph", "plan", "tree", "ctx")}
+    for o in objs:
+        live[o.kind].add(o)
+    monkeypatch.setattr(api, "_LIVE", live)
+    api.shutdown()
+    assert order == ["graph", "graph", "plan", "tree", "tree", "ctx", "ctx"]
