@@ -252,6 +252,24 @@ int swv_adjoint(swv_ctx ctx, int64_t n_vis, const double* u, const double* v, co
                 const void* y, int64_t n_pix, const double* l, const double* m,
                 const double* nm1, int sign, int prec, void* img_out);
 
+/* swv_adjoint for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, the same result bit for bit (the same tiling, row
+ * chunks and summation order), but the per-chunk partial sums live in a fixed
+ * 32 MiB device array that the library holds on every device it runs on
+ * until the process ends, instead of a context workspace.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ * SWV_ENOMEM, before any work is enqueued, if the partial sums,
+ * 16 * n_pix * (row chunks of swv_adjoint) bytes, exceed 32 MiB (e.g. about
+ * 2,000,000 pixel-chunks: 955 pixels over 8.36M rows need 15.6 MB).  All
+ * calls on one device share the array and every call overwrites the part it
+ * uses before reading it: calls that overlap on one device (other streams,
+ * other contexts, other threads) race and must be ordered by the caller. */
+int swv_adjoint_noalloc(swv_ctx ctx, int64_t n_vis, const double* u, const double* v,
+                        const double* w, const void* y, int64_t n_pix, const double* l,
+                        const double* m, const double* nm1, int sign, int prec,
+                        void* img_out);
+
 /* Gradient of  alpha * Re sum_j conj(y_j) V_j(theta)  with respect to the real
  * parameters theta = (flux_k, l_k, m_k) of the direct sum (Eq. 12):
  *     d_flux[k] = alpha Re sum_j conj(y_j) e_jk

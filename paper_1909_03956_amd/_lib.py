@@ -102,6 +102,8 @@ SIGNATURES = {
     "swv_pixels_in_disk": [_int, _dbl, _dbl, _dbl, _i64, _vp, _vp, _vp, _vp, C.POINTER(_i64)],
     "swv_residual_chi2": [_vp, _i64, _vp, _vp, _dbl, _vp, _vp],
     "swv_adjoint": [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _int, _int, _vp],
+    "swv_adjoint_noalloc": [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _int, _int,
+                            _vp],
     "swv_grad_direct": [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _int, _dbl,
                         _vp, _vp, _vp],
     "swv_batch_plan": [_vp, _int, C.POINTER(Instance), _pvp],

@@ -362,8 +362,12 @@ def residual_chi2(vis_obs, vis_model, inv_sigma2: float, out=None):
     return resid, chi2
 
 
-def adjoint(u, v, w, y, l, m, nm1, sign: int = -1, prec="fp64", out=None):
-    """x_p = sum_j conj(e_jp) y_j on the pixel set (l, m, n - 1); complex128."""
+def adjoint(u, v, w, y, l, m, nm1, sign: int = -1, prec="fp64", out=None, noalloc=False):
+    """x_p = sum_j conj(e_jp) y_j on the pixel set (l, m, n - 1); complex128.
+
+    noalloc=True calls swv_adjoint_noalloc, which keeps its partial sums in
+    the library's fixed device array (the same bits; pass `out` as well for a
+    call that allocates nothing)."""
     u = _dev_f64(u, "u")
     dev = u.device
     v, w = _dev_f64(v, "v", dev), _dev_f64(w, "w", dev)
@@ -378,7 +382,8 @@ def adjoint(u, v, w, y, l, m, nm1, sign: int = -1, prec="fp64", out=None):
           or out.device != dev):
         raise ValueError("out must be a contiguous complex128 tensor of n_pix entries")
     ctx = context(dev)
-    check(lib().swv_adjoint(ctx.handle, n, _ptr(u), _ptr(v), _ptr(w), _ptr(y), P, _ptr(l), _ptr(m), _ptr(nm1),
+    fn = lib().swv_adjoint_noalloc if noalloc else lib().swv_adjoint
+    check(fn(ctx.handle, n, _ptr(u), _ptr(v), _ptr(w), _ptr(y), P, _ptr(l), _ptr(m), _ptr(nm1),
              sign, _prec(prec), _ptr(out)))
     return out
 

@@ -293,6 +293,9 @@ int swv_ctx_create(int device, void* stream, swv_ctx* out) {
     }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+    // the fixed scratch of swv_adjoint_noalloc on this device (the device is
+    // current here); a failure is reported by that entry point instead
+    if (noalloc_scratch(device, &c->scratch) != SWV_OK) c->scratch = nullptr;
     tune_defaults(c);
     if (const char* path = getenv("SWV_TUNE_CACHE")) {
         if (path[0] && swv_tune_load(c, path) != SWV_OK) tune_defaults(c);

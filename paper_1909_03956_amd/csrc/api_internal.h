@@ -36,6 +36,7 @@ struct swv_ctx_s {
     swv::DevBuf degrid;     // w planes and image scratch of the degridding predictor
     swv::DevBuf hog;        // per-workgroup peaks of the grid-wide Hogbom cycle
     void* fft_plan = nullptr;   // batched 2-D FFT plan of the degridding predictor
+    void* scratch = nullptr;    // device address of the allocation-free entry points' array
     int fft_shape[3] = {0, 0, 0};
     int* d_status = nullptr;  // deferred-error bits raised by kernels
     int n_cu = 256;
@@ -86,5 +87,12 @@ struct AdjointShape {
 AdjointShape adjoint_shape(swv_ctx ctx, int64_t n_vis, int64_t n_pix, int prec);
 // Bytes of per-chunk partial sums the adjoint needs (complex128 per chunk and pixel).
 size_t adjoint_partial_bytes(const AdjointShape& sh, int64_t n_pix);
+
+// Device address of the fixed scratch array of the allocation-free entry
+// points on `device`, which must be the current device; looked up once per
+// device (hipGetSymbolAddress) and cached.
+int noalloc_scratch(int device, void** out);
+// Its size in bytes.
+size_t noalloc_scratch_bytes();
 
 }  // namespace swv
