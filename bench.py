@@ -55,6 +55,53 @@ FLOPS = {
     "tree_child": 2 + 6,                      # every child after a node's first: S, D^0..2
     "tree_root": 4,                           # A_1 lambda_1 eta_1 into V
 }
+# Of those, the FP64 phasor polynomial (one implementation choice of a
+# complex exponential; a hardware FP64 sincos would need none of them).
+PHASOR_FLOPS = 34
+
+# Algorithmic operations per term of the FP32-compensated forms, by the unit
+# that executes them: the FP64 phase and its exact reduction (1 mul, 2 FMA,
+# rint, sub); the conversion of r to FP32; the hardware sine and cosine; the
+# FP32 side -- direct: per re/im one FMA (the product I c, less the
+# compensation) and 3 additions of the Kahan update; adjoint: per re/im a
+# product and an FMA (conj(e) y) and the 4 operations of a Kahan update.
+F32C_OPS = {
+    "direct_f32c": {"f64": 5, "cvt": 1, "trans": 2, "f32": 8},
+    "adjoint_f32c": {"f64": 5, "cvt": 1, "trans": 2, "f32": 12},
+}
+
+
+def tree_flops_per_row(st: dict) -> int:
+    """Algorithmic flops per visibility row of the tree route over a tree with
+    the given stats: every node but the level-1 ones is some node's child, and
+    each internal node has one first child, so the sum over nodes of (k - 1)
+    is leaves - roots."""
+    roots = st["nodes_per_level"][0]
+    return (st["n_leaves"] * FLOPS["tree_leaf"] + st["n_internal"] * FLOPS["tree_node"] +
+            (st["n_leaves"] - roots) * FLOPS["tree_child"] + roots * FLOPS["tree_root"])
+
+
+def f32c_roofline(kind: str, terms_per_s: float, peaks: dict) -> dict:
+    """Issue-time ceiling of an FP32-compensated kernel from the measured
+    rates of the three units it uses: FP64 lane operations at half the FP64
+    FMA flop rate, FP32 lane operations (conversion included) at half the FP32
+    FMA flop rate, and transcendentals at twice the sine + cosine pair rate.
+    If the units shared one issue port, a term would take at least the sum of
+    the three times; `frac` is the achieved rate against that ceiling and
+    `shares` each unit's busy fraction."""
+    ops = F32C_OPS[kind]
+    r64 = peaks["fp64_fma_tflops"] * 1e12 / 2
+    r32 = peaks["fp32_fma_tflops"] * 1e12 / 2
+    rtr = peaks["sincos_f32_gops"] * 1e9 * 2
+    t_term = {"fp64": ops["f64"] / r64, "fp32": (ops["f32"] + ops["cvt"]) / r32,
+              "trans": ops["trans"] / rtr}
+    ceiling = 1.0 / sum(t_term.values())
+    return {"bound": "alu", "unit": "Gterms/s", "achieved": round(terms_per_s / 1e9, 1),
+            "peak": round(ceiling / 1e9, 1), "frac": round(terms_per_s / ceiling, 4),
+            "shares": {k: round(terms_per_s * v, 4) for k, v in t_term.items()},
+            "ops_per_term": ops,
+            "peak_model": "1 / (n_f64 / R_f64 + n_f32 / R_f32 + n_trans / R_trans), "
+                          "measured rates of this part (measured_peaks)"}
 
 
 def log(*a):
@@ -95,6 +142,10 @@ def parse():
                    help="write the autotuner's table and timings (JSON) to this path")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run one device copy of 1 GiB (HBM counter calibration)")
+    p.add_argument("--no-cfg3", action="store_true",
+                   help="skip the precision-form leg on its own workload (cfg3)")
+    p.add_argument("--no-cfg4", action="store_true",
+                   help="skip the batched leg on its own workload (cfg4)")
     return p.parse_args()
 
 
@@ -440,7 +491,7 @@ def run_compare(swv, torch, np, dev, configs):
     return out
 
 
-def run_precision(swv, torch, np, dev, configs):
+def run_precision(swv, torch, np, dev, configs, peaks=None):
     """The precision form (FP64 phase and reduction, FP32 phasor and products,
     Kahan-compensated FP32 sums) against the FP64 form on cfg3, the workload
     named for it: both timed as single launches (median of five after a
@@ -480,16 +531,31 @@ def run_precision(swv, torch, np, dev, configs):
     scale = float(np.abs(f).sum())
     terms = n_vis * n_comp
     phi = float(torch.max(torch.abs(U) + torch.abs(V) + torch.abs(Wt)).item())
+    if peaks is None:
+        peaks = swv.context(dev).measure_peaks()
+    fl64 = terms * FLOPS["direct_fp64"]
+    ach64 = fl64 / (ms64 * 1e-3) / 1e12
     out = {"workload": "cfg3: 256-antenna 100 km array, 8 h at dec +30, 1.4 GHz, "
                        f"{n_vis:,} vis; {n_comp:,} components uniform over 3 deg",
            "n_vis": n_vis, "n_comp": n_comp, "terms": terms,
            "max_abs_uvw_sum_wavelengths": round(phi, 1),
            "fp64": {"ms": round(ms64, 3),
                     "Gvis_terms_per_s": round(terms / (ms64 * 1e-3) / 1e9, 1),
-                    "fp64_alu_frac": round(terms * FLOPS["direct_fp64"] / (ms64 * 1e-3)
-                                           / (PEAK_FP64_TFLOPS * 1e12), 4)},
+                    "roofline": {"bound": "alu", "kernel": "k_direct_f64",
+                                 "achieved": round(ach64, 2), "peak": PEAK_FP64_TFLOPS,
+                                 "unit": "TFLOP/s", "frac": round(ach64 / PEAK_FP64_TFLOPS, 4),
+                                 "flops_per_launch": fl64, "avg_launch_ms": round(ms64, 4),
+                                 "frac_excl_phasor": round(
+                                     ach64 * (FLOPS["direct_fp64"] - PHASOR_FLOPS) /
+                                     FLOPS["direct_fp64"] / PEAK_FP64_TFLOPS, 4),
+                                 "measured_peak": round(peaks["fp64_fma_tflops"], 2),
+                                 "frac_of_measured": round(ach64 / peaks["fp64_fma_tflops"], 4),
+                                 "traffic": None}},
            "f32c": {"ms": round(ms32, 3),
-                    "Gvis_terms_per_s": round(terms / (ms32 * 1e-3) / 1e9, 1)},
+                    "Gvis_terms_per_s": round(terms / (ms32 * 1e-3) / 1e9, 1),
+                    "roofline": dict(f32c_roofline("direct_f32c", terms / (ms32 * 1e-3), peaks),
+                                     kernel="k_direct_f32c", avg_launch_ms=round(ms32, 4),
+                                     traffic=None)},
            "speedup_f32c_over_fp64": round(ms64 / ms32, 3),
            "f32c_vs_fp64": {"E_max": float(f"{float(err.max()) / scale:.3e}"),
                             "E_rms": float(f"{float(err.pow(2).mean().sqrt()) / scale:.3e}"),
@@ -512,7 +578,7 @@ def run_batched(swv, torch, np, dev, configs):
 
     insts = {"direct": [], "tree": []}
     keep = []
-    rows = terms = leaves = 0
+    rows = terms = leaves = tree_fl = 0
     t0 = time.perf_counter()
     for inst in B.instances:
         kept, l, m, f = B.instance_rows_kept(inst)
@@ -524,9 +590,11 @@ def run_batched(swv, torch, np, dev, configs):
                                     out=out_d))
         insts["tree"].append(dict(route="tree", tree=tree, u=u, v=v, w=w, out=out_t))
         keep.append(tree)
+        st = tree.stats()
         rows += kept.size
         terms += kept.size * inst.n_comp
-        leaves += kept.size * (tree.stats()["n_leaves"] + tree.stats()["n_internal"])
+        leaves += kept.size * (st["n_leaves"] + st["n_internal"])
+        tree_fl += kept.size * tree_flops_per_row(st)
     torch.cuda.synchronize()
     log(f"batched workload made in {time.perf_counter() - t0:.1f} s: {len(B.instances)} "
         f"instances, {rows} rows")
@@ -548,11 +616,56 @@ def run_batched(swv, torch, np, dev, configs):
             e1.synchronize()
             ts.append(e0.elapsed_time(e1))
         ms = float(np.median(ts))
+        fl = terms * FLOPS["direct_fp64"] if name == "direct" else tree_fl
+        ach = fl / (ms * 1e-3) / 1e12
         out[name] = {"ms": round(ms, 2), "Gvis_terms_per_s": round(terms / (ms * 1e-3) / 1e9, 1),
-                     "Grows_per_s": round(rows / (ms * 1e-3) / 1e9, 3), "plan": plan.stats()}
+                     "Grows_per_s": round(rows / (ms * 1e-3) / 1e9, 3), "plan": plan.stats(),
+                     "roofline": {"bound": "alu",
+                                  "kernel": "k_batch_direct" if name == "direct" else "k_batch_tree",
+                                  "achieved": round(ach, 2), "peak": PEAK_FP64_TFLOPS,
+                                  "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4),
+                                  "flops_per_launch": fl, "avg_launch_ms": round(ms, 3),
+                                  "traffic": None}}
         log(f"batched {name}: {ms:.1f} ms")
         graph.close()
         plan.close()
+    # one major cycle of the tree route over every instance: the batched
+    # prediction, then per instance the residual against the direct route's
+    # visibilities (the snapping error), chi^2 and the residual image on the
+    # level-9 pixels within 4 deg; eager launches against the captured graph
+    pix = swv.pixels_in_disk(9, ra, dec, math.radians(4.0))[1:]
+    P = tuple(D(a) for a in pix)
+    cyc = [dict(route="tree", u=d["u"], v=d["v"], w=d["w"], vis_obs=dd["out"], inv_sigma2=1e4,
+                pixels=P, comp_cap=max(1, t.stats()["n_leaves"]), tree_level_cap=10)
+           for d, dd, t in zip(insts["tree"], insts["direct"], keep)]
+    cy = swv.MajorCycle(cyc)
+    for k, t in enumerate(keep):
+        cy.set_tree(k, t)
+
+    def timed_cycle(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+    ms_eager = timed_cycle(cy.run)
+    cy.capture()
+    ms_graph = timed_cycle(cy.launch)
+    chi2 = float(sum(float(o["chi2"].item()) for o in cy.out))
+    out["major_cycle_tree"] = {
+        "steps": "batched tree prediction; per instance residual vs the direct route, chi^2, "
+                 f"residual image on {pix[0].size} level-9 pixels",
+        "kernel_launches": 2 + 4 * len(cyc), "eager_ms": round(ms_eager, 2),
+        "graph_ms": round(ms_graph, 2), "graph_speedup": round(ms_eager / ms_graph, 4),
+        "chi2_sum": float(f"{chi2:.6g}")}
+    log(f"major cycle (tree, 256 instances): eager {ms_eager:.1f} ms, graph {ms_graph:.1f} ms")
+    cy.close()
     return out
 
 
@@ -752,15 +865,7 @@ def main():
 
     # roofline of the dominant kernel (largest device time in the step)
     def tree_flops(J):
-        # every node but the level-1 ones is some node's child, and each
-        # internal node has one first child: sum over nodes of (k - 1) is
-        # leaves - roots
-        st = tree_stats[J]
-        roots = st["nodes_per_level"][0]
-        return n_vis * (st["n_leaves"] * FLOPS["tree_leaf"] +
-                        st["n_internal"] * FLOPS["tree_node"] +
-                        (st["n_leaves"] - roots) * FLOPS["tree_child"] +
-                        roots * FLOPS["tree_root"])
+        return n_vis * tree_flops_per_row(tree_stats[J])
     flops = {"direct_fp64": n_vis * n_comp * FLOPS["direct_fp64"],
              "adjoint": n_vis * n_pix * FLOPS["adjoint"],
              "grad": n_vis * n_comp * FLOPS["grad"]}
@@ -784,6 +889,24 @@ def main():
     for s in flops:
         routes[s]["TFLOP_per_s"] = round(flops[s] / (med[s] * 1e-3) / 1e12, 2)
         routes[s]["fp64_alu_frac"] = round(flops[s] / (med[s] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)
+    # the same fractions without the phasor polynomial's flops (34 per phasor)
+    phasors = {"direct_fp64": n_vis * n_comp, "adjoint": n_vis * n_pix,
+               "grad": n_vis * n_comp}
+    for J in TREE_LEVELS:
+        phasors[f"tree_J{J}"] = n_vis * tree_stats[J]["n_leaves"]
+    for s in flops:
+        routes[s]["fp64_alu_frac_excl_phasor"] = round(
+            (flops[s] - PHASOR_FLOPS * phasors[s]) / (med[s] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)
+    roofline["frac_excl_phasor"] = routes[dom]["fp64_alu_frac_excl_phasor"]
+    routes["direct_f32c"]["roofline"] = dict(
+        f32c_roofline("direct_f32c", n_vis * n_comp / (med["direct_f32c"] * 1e-3), peaks),
+        kernel="k_direct_f32c")
+    # value restricted to the prediction stages (direct FP64, FP32c, trees)
+    pred = ["direct_fp64", "direct_f32c"] + [f"tree_J{J}" for J in TREE_LEVELS]
+    pred_ms = sum(med[s] for s in pred)
+    prediction_only = {"Gvis_terms_per_s": round(sum(terms[s] for s in pred) /
+                                                 (pred_ms * 1e-3) / 1e9, 2),
+                       "ms": round(pred_ms, 3), "stages": pred}
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": UNIT, "n_gpus": 1,
@@ -796,12 +919,19 @@ def main():
                    "n_vis": n_vis, "n_comp": n_comp, "n_pix": int(n_pix),
                    "tree_levels": list(TREE_LEVELS), "terms_per_step": step_terms},
         "routes": routes,
+        "prediction_only": prediction_only,
         "roofline": roofline,
         "measured_peaks": {k: round(v, 2) for k, v in peaks.items()},
         # measured after the timed steps, not part of the step or of value
         "extra_routes": extra_routes,
         "tile_shapes": {f: {"per_lane": pl, "block": bl} for f, (pl, bl) in tuning.items()},
     }
+    if not (args.no_cfg3 or args.profile):
+        log("precision form on its own workload (cfg3) ...")
+        out["precision_cfg3"] = run_precision(swv, torch, np, dev, configs, peaks)
+    if not (args.no_cfg4 or args.profile):
+        log("batched form on its own workload (cfg4) ...")
+        out["batched_cfg4"] = run_batched(swv, torch, np, dev, configs)
     if not (args.no_clean or args.profile):
         log("clean loop on the seven-source workload ...")
         out["clean_loop"] = run_clean(swv, torch, np, dev, configs)

@@ -27,9 +27,9 @@
  *  - Device work is enqueued asynchronously on the context's stream.  Errors
  *    the kernels detect (non-finite or out-of-domain inputs) and HIP faults
  *    are reported by the next swv_ctx_synchronize() on that context.
- *  - Library objects (swv_ctx, swv_tree, swv_plan, swv_graph) follow
- *    create/destroy pairs.  A plan keeps its context and its trees alive and
- *    a graph its plan, so they may be destroyed in any order (memory is
+ *  - Library objects (swv_ctx, swv_tree, swv_plan, swv_graph, swv_cycle)
+ *    follow create/destroy pairs.  A plan or cycle keeps its context alive, a
+ *    plan its trees and a graph its plan, so they may be destroyed in any order (memory is
  *    released with the last of them); a handle must not be used after its
  *    destroy call.  A context may be used from one thread at a time; calls
  *    that overlap on one stream are ordered by the stream.
@@ -525,6 +525,86 @@ int swv_graph_launch(swv_graph graph);
 
 int swv_graph_destroy(swv_graph graph);
 int swv_plan_destroy(swv_plan plan);
+
+/* ------------------------------------------------------ major cycles --- */
+
+typedef struct swv_cycle_s* swv_cycle;
+
+/* One instance (a channel x pointing) of a captured major cycle.  All
+ * pointers DEVICE; FP64 throughout.  route SWV_ROUTE_DIRECT predicts with the
+ * component list set by swv_cycle_set_components, SWV_ROUTE_TREE with the tree
+ * set by swv_cycle_set_tree. */
+typedef struct {
+    int route;
+    int sign;                   /* +1 or -1 */
+    int64_t n_vis;
+    const double* u;            /* [n_vis] */
+    const double* v;
+    const double* w;
+    const void* vis_obs;        /* [n_vis] complex128, observed visibilities */
+    void* vis_model;            /* [n_vis] complex128, written: model visibilities */
+    void* resid;                /* [n_vis] complex128, written: vis_obs - vis_model */
+    double* chi2;               /* one FP64, written: inv_sigma2 * sum |resid|^2 */
+    double inv_sigma2;
+    int64_t n_pix;              /* pixel set of the residual image (0: no image) */
+    const double* pix_l;        /* [n_pix] pixel centres, n - 1 given explicitly */
+    const double* pix_m;
+    const double* pix_nm1;
+    void* image;                /* [n_pix] complex128, written: sum_j conj(e_jp) resid_j */
+    int64_t comp_cap;           /* direct: most components a model may have; tree: most
+                                   leaves */
+    int tree_level_cap;         /* tree: largest J of a model (1 .. 29) */
+    double* d_flux;             /* direct, optional (all three or none): [comp_cap]
+                                   d chi^2 / d(flux, l, m) of the model's components */
+    double* d_l;
+    double* d_m;
+} swv_cycle_instance;
+
+/* A major cycle over many instances (section 2.2 steps 1-3, with the chi^2
+ * gradients beside them), runnable eagerly or as one captured HIP graph:
+ *   1. the model visibilities of every instance in one persistent launch per
+ *      route (as swv_batch_plan: direct sums and wavelet trees, FP64);
+ *   2. per instance the subtract step with chi^2 (swv_residual_chi2), the
+ *      residual image on its pixel set (swv_adjoint of the residuals) and,
+ *      for a direct instance with gradient outputs, the chi^2 gradients of its
+ *      components (swv_grad_direct of the residuals with alpha = -2 inv_sigma2).
+ * The model of each instance may change between cycles within the stated
+ * capacities: its size, pointers and tree records are read on the device, so
+ * a captured graph replays the new model without a new capture.  Grids and
+ * tilings follow the capacities: results are bitwise the same eager and
+ * replayed, and agree with the single calls to their tolerances (the
+ * gradients' summation order follows comp_cap).  The cycle holds a tree
+ * record buffer of 32 (comp_cap J_cap + 12) bytes per tree instance and
+ * workspaces for the largest image and gradient step.  The buffers named by
+ * `inst` must outlive the cycle.  Until a model is set an instance predicts
+ * zero. */
+int swv_cycle_create(swv_ctx ctx, int n, const swv_cycle_instance* inst, swv_cycle* out);
+
+/* Sets the component list of direct instance k for the following cycles:
+ * l, m, flux [n_comp] DEVICE (read on every run), n_comp <= comp_cap.
+ * Gradient entries past n_comp are left untouched. */
+int swv_cycle_set_components(swv_cycle cycle, int k, int64_t n_comp, const double* l,
+                             const double* m, const double* flux);
+
+/* Sets the tree of tree instance k for the following cycles: its records are
+ * copied into the instance's buffer (after the work already on the context's
+ * stream, which this call waits for), so the tree may be destroyed afterwards.
+ * SWV_EINVAL if J exceeds tree_level_cap or the records the capacity;
+ * SWV_ENOTSUP if the cycle's traversal cannot walk the tree. */
+int swv_cycle_set_tree(swv_cycle cycle, int k, swv_tree tree);
+
+/* Enqueues one cycle on the context's stream (uploading changed models first). */
+int swv_cycle_run(swv_cycle cycle);
+
+/* Captures the cycle as a HIP graph held by the cycle (replacing an earlier
+ * one); capture needs no model to be set. */
+int swv_cycle_capture(swv_cycle cycle);
+
+/* Replays the captured graph on the context's stream, after uploading changed
+ * models; SWV_EINVAL if nothing was captured. */
+int swv_cycle_launch(swv_cycle cycle);
+
+int swv_cycle_destroy(swv_cycle cycle);
 
 /* ------------------------------------------------------ measured peaks --- */
 

@@ -5,7 +5,7 @@ exact adjoint and chi^2 gradients, behind the C ABI of libswvis.so
 library; the library must be built (build.py) -- there is no CPU fallback.
 """
 from ._lib import SwvError, lib  # noqa: F401
-from .api import (BatchPlan, Context, Graph, Tree, adjoint, ang2pix, context,  # noqa: F401
+from .api import (BatchPlan, Context, Graph, MajorCycle, Tree, adjoint, ang2pix, context,  # noqa: F401
                   cross_reference, dirty_beam, dirty_image, fit_clean_beam, grad_direct, hogbom,
                   image_grid, pixel_centres, pixels_in_disk, predict_degrid, predict_direct,
                   residual_chi2,

@@ -54,6 +54,16 @@ class Instance(C.Structure):
                 ("flux", C.c_void_p), ("tree", C.c_void_p), ("vis_out", C.c_void_p)]
 
 
+class CycleInstance(C.Structure):
+    _fields_ = [("route", C.c_int), ("sign", C.c_int), ("n_vis", C.c_int64),
+                ("u", C.c_void_p), ("v", C.c_void_p), ("w", C.c_void_p),
+                ("vis_obs", C.c_void_p), ("vis_model", C.c_void_p), ("resid", C.c_void_p),
+                ("chi2", C.c_void_p), ("inv_sigma2", C.c_double), ("n_pix", C.c_int64),
+                ("pix_l", C.c_void_p), ("pix_m", C.c_void_p), ("pix_nm1", C.c_void_p),
+                ("image", C.c_void_p), ("comp_cap", C.c_int64), ("tree_level_cap", C.c_int),
+                ("d_flux", C.c_void_p), ("d_l", C.c_void_p), ("d_m", C.c_void_p)]
+
+
 class CleanParams(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("cell", C.c_double), ("J", C.c_int),
                 ("ra_p", C.c_double), ("dec_p", C.c_double), ("gain", C.c_double),
@@ -113,6 +123,13 @@ SIGNATURES = {
     "swv_graph_launch": [_vp],
     "swv_graph_destroy": [_vp],
     "swv_plan_destroy": [_vp],
+    "swv_cycle_create": [_vp, _int, C.POINTER(CycleInstance), _pvp],
+    "swv_cycle_set_components": [_vp, _int, _i64, _vp, _vp, _vp],
+    "swv_cycle_set_tree": [_vp, _int, _vp],
+    "swv_cycle_run": [_vp],
+    "swv_cycle_capture": [_vp],
+    "swv_cycle_launch": [_vp],
+    "swv_cycle_destroy": [_vp],
     "swv_autotune": [_vp, C.c_char_p, _int],
     "swv_tune_load": [_vp, C.c_char_p],
     "swv_tune_get": [_vp, _int, _int, C.POINTER(C.c_int), C.POINTER(C.c_int)],

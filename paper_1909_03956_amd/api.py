@@ -10,19 +10,19 @@ import numpy as np
 import torch
 
 from ._lib import (PREDICTORS, SWV_F32C, SWV_FP64, SWV_HOGBOM_ABS, SWV_HOGBOM_SINGLE,
-                   CleanParams, CleanStats,
+                   CleanParams, CleanStats, CycleInstance,
                    DegridStats, Instance, PlanStats, TreeStats, check, lib)
 
 PRECISIONS = {"fp64": SWV_FP64, "f32c": SWV_F32C}
 
 # Live library objects by kind.  At interpreter exit they are destroyed in
-# dependency order -- graphs, plans, trees, contexts (and with them the FFT
+# dependency order -- graphs, cycles, plans, trees, contexts (and with them the FFT
 # plans of the degridding predictor) -- from an atexit hook, which runs before
 # Python tears down its modules and before the HIP runtime and any tool
 # attached to it shut down.  Finalizers left to module teardown would run in
 # no useful order, and objects never destroyed would be released by the
 # runtime's own exit handlers.
-_LIVE = {kind: weakref.WeakSet() for kind in ("graph", "plan", "tree", "ctx")}
+_LIVE = {kind: weakref.WeakSet() for kind in ("graph", "cycle", "plan", "tree", "ctx")}
 
 
 def _track(kind, obj):
@@ -32,7 +32,7 @@ def _track(kind, obj):
 def shutdown():
     """Destroys every live library object in dependency order (registered to
     run at interpreter exit; safe to call earlier, objects are then closed)."""
-    for kind in ("graph", "plan", "tree", "ctx"):
+    for kind in ("graph", "cycle", "plan", "tree", "ctx"):
         for obj in list(_LIVE[kind]):
             try:
                 obj.close()
@@ -709,6 +709,103 @@ class BatchPlan:
             pass
 
 
+class MajorCycle:
+    """Major cycles over many instances, eager or as one captured HIP graph:
+    batched prediction, then per instance the residual and chi^2, the residual
+    image on a pixel set and (direct instances) the chi^2 gradients.
+
+    instances: dicts with route ("direct" | "tree"), u, v, w, vis_obs
+    (complex128), inv_sigma2, optional sign (-1), pixels (l, m, nm1) of the
+    residual image, comp_cap (direct: most components; tree: most leaves),
+    tree_level_cap (tree: largest J) and grads (direct: True to form d chi^2 /
+    d(flux, l, m)).  The cycle allocates the outputs: vis_model, resid, chi2,
+    image and grads per instance (tensors, overwritten by every cycle).  Models
+    are set with set_components / set_tree and may change between cycles
+    without a new capture."""
+
+    def __init__(self, instances, device=None):
+        self._keep = []
+        self.out = []
+        arr = (CycleInstance * max(1, len(instances)))()
+        dev = None
+        for k, d in enumerate(instances):
+            u = _dev_f64(d["u"], "u")
+            dev = dev or u.device
+            v, w = _dev_f64(d["v"], "v", u.device), _dev_f64(d["w"], "w", u.device)
+            obs = _dev_c128(d["vis_obs"], "vis_obs", u.device)
+            n = u.numel()
+            if v.numel() != n or w.numel() != n or obs.numel() != n:
+                raise ValueError(f"instance {k}: length mismatch")
+            I = arr[k]
+            I.route = ROUTES[d.get("route", "direct")]
+            I.sign = int(d.get("sign", -1))
+            I.n_vis = n
+            I.u, I.v, I.w, I.vis_obs = (_ptr(t).value for t in (u, v, w, obs))
+            o = {"vis_model": torch.empty(n, dtype=torch.complex128, device=u.device),
+                 "resid": torch.empty(n, dtype=torch.complex128, device=u.device),
+                 "chi2": torch.zeros(1, dtype=torch.float64, device=u.device)}
+            I.vis_model, I.resid, I.chi2 = (_ptr(o[x]).value for x in ("vis_model", "resid",
+                                                                         "chi2"))
+            I.inv_sigma2 = float(d["inv_sigma2"])
+            self._keep += [u, v, w, obs]
+            if d.get("pixels") is not None:
+                pl, pm, pn = (_dev_f64(t, "pixels", u.device) for t in d["pixels"])
+                if pm.numel() != pl.numel() or pn.numel() != pl.numel():
+                    raise ValueError(f"instance {k}: pixel arrays differ in length")
+                o["image"] = torch.empty(pl.numel(), dtype=torch.complex128, device=u.device)
+                I.n_pix = pl.numel()
+                I.pix_l, I.pix_m, I.pix_nm1 = _ptr(pl).value, _ptr(pm).value, _ptr(pn).value
+                I.image = _ptr(o["image"]).value
+                self._keep += [pl, pm, pn]
+            I.comp_cap = int(d.get("comp_cap", 0))
+            I.tree_level_cap = int(d.get("tree_level_cap", 1 if I.route == 0 else 10))
+            if d.get("grads"):
+                g = [torch.zeros(max(I.comp_cap, 1), dtype=torch.float64, device=u.device)
+                     for _ in range(3)]
+                o["grads"] = g
+                I.d_flux, I.d_l, I.d_m = (_ptr(t).value for t in g)
+            self.out.append(o)
+        self.ctx = context(dev if device is None else device)
+        self._h = C.c_void_p()
+        check(lib().swv_cycle_create(self.ctx.handle, len(instances), arr, C.byref(self._h)))
+        _track("cycle", self)
+        self._models = [None] * len(instances)
+
+    def set_components(self, k: int, l, m, flux):
+        dev = self.ctx.device
+        l, m, flux = _dev_f64(l, "l", dev), _dev_f64(m, "m", dev), _dev_f64(flux, "flux", dev)
+        if m.numel() != l.numel() or flux.numel() != l.numel():
+            raise ValueError("l, m, flux differ in length")
+        check(lib().swv_cycle_set_components(self._h, int(k), l.numel(), _ptr(l), _ptr(m),
+                                             _ptr(flux)))
+        self._models[k] = (l, m, flux)     # read on every run: keep them alive
+
+    def set_tree(self, k: int, tree):
+        check(lib().swv_cycle_set_tree(self._h, int(k), tree.handle))
+        self._models[k] = None              # the records were copied
+
+    def run(self):
+        check(lib().swv_cycle_run(self._h))
+
+    def capture(self):
+        check(lib().swv_cycle_capture(self._h))
+
+    def launch(self):
+        check(lib().swv_cycle_launch(self._h))
+
+    def close(self):
+        if self._h:
+            lib().swv_cycle_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        # never raises (at interpreter exit shutdown() has already closed it)
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def synchronize(device=None):
     """Waits for the current stream and raises deferred kernel errors."""
     context(device).synchronize()
@@ -716,4 +813,4 @@ def synchronize(device=None):
 
 __all__ = ["Context", "context", "predict_direct", "Tree", "ang2pix", "pixel_centres",
            "pixels_in_disk", "residual_chi2", "adjoint", "grad_direct", "synchronize",
-           "BatchPlan", "Graph"]
+           "BatchPlan", "Graph", "MajorCycle"]

@@ -255,17 +255,22 @@ hipError_t launch_adjoint(hipStream_t s, int prec, int ppl, int block, int64_t c
 // every component of a chunk and each row is fetched from memory once.
 constexpr int kGradRowTile = 256;
 
+// n_comp_dev, if not null, holds the number of components on the device (a
+// captured major cycle whose model changes between replays): the grid is then
+// sized for n_comp, the capacity, and blocks past the actual count leave.
 template <int CPL, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_grad_partial(
     const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
     const double2* __restrict__ y, int64_t n_vis, int64_t chunk, const Comp* __restrict__ comp,
-    int64_t n_comp, double sgn, int64_t n_chunks, int64_t tiles, int64_t bid0,
-    double* __restrict__ partial) {
+    int64_t n_comp, const int* __restrict__ n_comp_dev, double sgn, int64_t n_chunks,
+    int64_t tiles, int64_t bid0, double* __restrict__ partial) {
     // one row: u, v, w, yr, yi, 4 s yr, 4 s yi, (pad) -- 64 bytes
     __shared__ double2 rows[kGradRowTile][4];
     int64_t chunk_id, tile;
     chunk_tile(bid0 + blockIdx.x, tiles, chunk_id, tile);
     if (chunk_id >= n_chunks) return;   // padding of the last XCD group (whole block)
+    if (n_comp_dev) n_comp = *n_comp_dev;
+    if (tile * (BLOCK * CPL) >= n_comp) return;   // no component in this tile (whole block)
     const int64_t k0 = tile * (BLOCK * CPL) + threadIdx.x;
     double L[CPL], M[CPL], N[CPL];
     double z0[CPL], zu[CPL], zv[CPL], zw[CPL];
@@ -337,9 +342,11 @@ __global__ __launch_bounds__(BLOCK) void k_grad_partial(
 
 __global__ __launch_bounds__(kSumCols * kSumQ) void k_grad_finish(
     const double* __restrict__ partial, int64_t n_chunks, const Comp* __restrict__ comp,
-    int64_t n_comp, double sgn, double alpha, double* __restrict__ d_flux,
-    double* __restrict__ d_l, double* __restrict__ d_m) {
+    int64_t n_comp, const int* __restrict__ n_comp_dev, double sgn, double alpha,
+    double* __restrict__ d_flux, double* __restrict__ d_l, double* __restrict__ d_m) {
     __shared__ double red[4][kSumQ][kSumCols];
+    if (n_comp_dev) n_comp = *n_comp_dev;
+    if ((int64_t)blockIdx.x * kSumCols >= n_comp) return;   // whole block past the count
     const int tx = threadIdx.x % kSumCols, q = threadIdx.x / kSumCols;
     const int64_t k = (int64_t)blockIdx.x * kSumCols + tx;
     double z[4] = {0, 0, 0, 0};
@@ -389,7 +396,7 @@ int grad_blocks_per_cu(int cpl, int block) {
 hipError_t launch_grad(hipStream_t s, int cpl, int64_t chunk, int64_t n_vis, const double* u,
                        const double* v, const double* w, const void* y, const Comp* comp,
                        int64_t n_comp, int sign, double alpha, double* partial, double* d_flux,
-                       double* d_l, double* d_m) {
+                       double* d_l, double* d_m, const int* n_comp_dev) {
     if (n_comp <= 0) return hipSuccess;
     if (cpl != 1 && cpl != 2 && cpl != 4) return hipErrorInvalidValue;
     const int64_t n_chunks = n_vis > 0 ? (n_vis + chunk - 1) / chunk : 0;
@@ -403,7 +410,8 @@ hipError_t launch_grad(hipStream_t s, int cpl, int64_t chunk, int64_t n_vis, con
 #define SWV_RUN_G(C, B)                                                                      \
     if (cpl == C && block == B)                                                              \
         k_grad_partial<C, B><<<dim3(nb), dim3(B), 0, s>>>(u, v, w, yy, n_vis, chunk, comp, n_comp, \
-                                                          sg, n_chunks, tiles, b0, partial);
+                                                          n_comp_dev, sg, n_chunks, tiles, b0,  \
+                                                          partial);
             SWV_RUN_G(1, 128) SWV_RUN_G(1, 256) SWV_RUN_G(1, 512) SWV_RUN_G(1, 1024)
             SWV_RUN_G(2, 128) SWV_RUN_G(2, 256) SWV_RUN_G(2, 512) SWV_RUN_G(2, 1024)
             SWV_RUN_G(4, 128) SWV_RUN_G(4, 256) SWV_RUN_G(4, 512) SWV_RUN_G(4, 1024)
@@ -413,8 +421,8 @@ hipError_t launch_grad(hipStream_t s, int cpl, int64_t chunk, int64_t n_vis, con
         if (e != hipSuccess) return e;
     }
     k_grad_finish<<<dim3((unsigned)((n_comp + kSumCols - 1) / kSumCols)), dim3(kSumCols * kSumQ),
-                    0, s>>>(partial, n_chunks, comp, n_comp, (double)sign, alpha, d_flux, d_l,
-                            d_m);
+                    0, s>>>(partial, n_chunks, comp, n_comp, n_comp_dev, (double)sign, alpha,
+                            d_flux, d_l, d_m);
     return hipGetLastError();
 }
 

@@ -62,10 +62,12 @@ int adjoint_blocks_per_cu(int prec, int ppl, int block);
 void grad_tiling(int cpl, int64_t n_comp, int* block, int64_t* tiles);
 int grad_blocks_per_cu(int cpl, int block);
 
+// n_comp_dev (optional): the actual component count on the device, at most
+// n_comp, which then only sizes the grid (see k_grad_partial).
 hipError_t launch_grad(hipStream_t s, int cpl, int64_t chunk, int64_t n_vis, const double* u,
                        const double* v, const double* w, const void* y, const Comp* comp,
                        int64_t n_comp, int sign, double alpha, double* partial, double* d_flux,
-                       double* d_l, double* d_m);
+                       double* d_l, double* d_m, const int* n_comp_dev = nullptr);
 
 hipError_t launch_residual(hipStream_t s, int64_t n_vis, const void* obs, const void* model,
                            double inv_sigma2, void* resid, double* partial, double* chi2);

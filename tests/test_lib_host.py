@@ -303,8 +303,8 @@ TrackSpecSmall = configs.TrackSpec(27, 1.7e3, 45.0, 2016.0, 4, 1.0e7, seed=731)
 
 
 def test_shutdown_closes_in_dependency_order(monkeypatch):
-    # at interpreter exit the binding destroys graphs, then plans, then trees,
-    # then contexts (the C side releases device memory while the runtime is up)
+    # at interpreter exit the binding destroys graphs, then cycles, then plans,
+    # then trees, then contexts (the C side releases device memory while the runtime is up)
     import weakref
 
     from paper_1909_03956_amd import api
@@ -317,10 +317,10 @@ def test_shutdown_closes_in_dependency_order(monkeypatch):
         def close(self):
             order.append(self.kind)
 
-    objs = [Obj(k) for k in ("ctx", "tree", "graph", "plan", "tree", "ctx", "graph")]
-    live = {k: weakref.WeakSet() for k in ("graph", "plan", "tree", "ctx")}
+    objs = [Obj(k) for k in ("ctx", "tree", "graph", "cycle", "plan", "tree", "ctx", "graph")]
+    live = {k: weakref.WeakSet() for k in ("graph", "cycle", "plan", "tree", "ctx")}
     for o in objs:
         live[o.kind].add(o)
     monkeypatch.setattr(api, "_LIVE", live)
     api.shutdown()
-    assert order == ["graph", "graph", "plan", "tree", "tree", "ctx", "ctx"]
+    assert order == ["graph", "graph", "cycle", "plan", "tree", "tree", "ctx", "ctx"]
