@@ -288,3 +288,48 @@ def test_degrid_missing_centring_phase_caught(monkeypatch):
     monkeypatch.setattr(od, "predict_degrid", bad)
     with pytest.raises(AssertionError):
         TG.test_wide_field_w_term(TG.TRACK.uvw())
+
+
+# ------------------------------------------------------------- thresholding --
+from oracle import threshold as oth  # noqa: E402
+
+from . import test_oracle_threshold as TT2  # noqa: E402
+
+
+def test_threshold_collapsed_node_at_wrong_centre_caught(monkeypatch):
+    # a collapsed node sampled at its parent's pixel centre instead of its own
+    # (planted in the thresholding oracle only, through a copy of the module)
+    import types
+    orig = sp.pixel_centres_lmn
+
+    def parent_centre(j, pix, ra, dec):
+        if j >= 2:
+            return orig(j - 1, np.asarray(pix) >> 2, ra, dec)
+        return orig(j, pix, ra, dec)
+    shim = types.SimpleNamespace(**{k: getattr(sp, k) for k in dir(sp) if not k.startswith("__")})
+    shim.pixel_centres_lmn = parent_centre
+    monkeypatch.setattr(oth, "sphere", shim)
+    with pytest.raises(AssertionError):
+        TT2.test_levels_kept_whole_give_the_direct_sum_one_level_down(4)
+
+
+def test_threshold_dropped_coefficients_kept_caught(monkeypatch):
+    # collapse only: the dropped coefficients of remaining nodes left in V
+    monkeypatch.setattr(oth, "keep_masks",
+                        lambda tree, flat: [np.ones_like(k) | k for k in
+                                            _orig_keep_masks(tree, flat)])
+    with pytest.raises(AssertionError):
+        TT2.test_two_leaf_tree_by_hand()
+
+
+_orig_keep_masks = oth.keep_masks
+
+
+def test_threshold_signed_ranking_caught(monkeypatch):
+    # ranking by gamma instead of |gamma|
+    def signed(tree):
+        vals = np.concatenate([lv.gamma.ravel() for lv in tree.levels[:-1]])
+        return np.argsort(-vals, kind="stable")
+    monkeypatch.setattr(oth, "coefficient_ranking", signed)
+    with pytest.raises(AssertionError):
+        TT2.test_ranking_order_and_count()
