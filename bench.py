@@ -142,6 +142,11 @@ def parse():
                    help="write the autotuner's table and timings (JSON) to this path")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run one device copy of 1 GiB (HBM counter calibration)")
+    p.add_argument("--threshold", action="store_true",
+                   help="coefficient thresholding on the measured workload (cfg2, J = 10 and "
+                        "the run-time sweep's track at J = 16): time and error against the "
+                        "exact tree route for retained proportions 1 .. 0.005; print one "
+                        "JSON line and exit")
     p.add_argument("--no-cfg3", action="store_true",
                    help="skip the precision-form leg on its own workload (cfg3)")
     p.add_argument("--no-cfg4", action="store_true",
@@ -565,6 +570,66 @@ def run_precision(swv, torch, np, dev, configs, peaks=None):
     return out
 
 
+def run_threshold(swv, torch, np, dev, configs):
+    """Retained proportion against time and error (the thresholded variant of
+    section 1): each thresholded tree is timed as single launches (median of
+    five after a warm-up) and compared with the exact tree route on every row;
+    E_max = max |V_p - V| / sum |I|."""
+    def D(x):
+        return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+
+    def timed(fn, reps=5):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    cases = []
+    W = configs.CFG2
+    l, m, f = W.components()
+    cases.append(("cfg2 (8,355,840 vis, 2,000 components), J = 10", W.track.uvw(), W.ra_p,
+                  W.dec_p, 10, l, m, f))
+    T = configs.SWEEP_TRACK
+    ls, ms, fs = configs.sweep_components(140)
+    cases.append(("run-time sweep track (1,263,600 vis, 140 components), J = 16", T.uvw(),
+                  math.radians(T.ra_deg), math.radians(T.dec_deg), 16, ls, ms, fs))
+    out = []
+    for name, (u, v, w), ra, dec, J, l, m, f in cases:
+        U, V, Wt = D(u), D(v), D(w)
+        t = swv.Tree(J, ra, dec, l, m, f)
+        exact = torch.empty(U.numel(), dtype=torch.complex128, device=dev)
+        ms_exact = timed(lambda: t.predict(U, V, Wt, out=exact))
+        buf = torch.empty_like(exact)
+        ms_leaf = timed(lambda: t.predict_leaves(U, V, Wt, out=buf))
+        scale = float(np.abs(f).sum())
+        st = t.stats()
+        rows = []
+        for frac in (1.0, 0.5, 0.2, 0.1, 0.05, 0.02, 0.01, 0.005):
+            tp = t.threshold(frac)
+            ms = timed(lambda: tp.predict(U, V, Wt, out=buf))
+            err = float((buf - exact).abs().max()) / scale
+            sp_ = tp.stats()
+            kept, n_coeffs = tp.kept()
+            rows.append({"fraction": frac, "kept": int(kept.size), "leaves": sp_["n_leaves"],
+                         "internal": sp_["n_internal"], "records": sp_["n_records"],
+                         "ms": round(ms, 4), "speedup": round(ms_exact / ms, 3),
+                         "E_max": float(f"{err:.3e}")})
+            log(f"threshold {name}: keep {frac} -> {ms:.3f} ms, E_max {err:.2e}")
+            tp.close()
+        out.append({"workload": name, "J": J, "leaves": st["n_leaves"],
+                    "internal": st["n_internal"], "coefficients": 3 * st["n_internal"],
+                    "exact_ms": round(ms_exact, 4), "leaf_sum_ms": round(ms_leaf, 4),
+                    "rows": rows})
+        t.close()
+    return out
+
+
 def run_batched(swv, torch, np, dev, configs):
     """The batched workload: 64 channels x 4 pointings of the 256-antenna array,
     2M-8M unflagged rows each (1.29e9 in all), made on the device; one plan per
@@ -695,6 +760,10 @@ def main():
         return
     if args.precision:
         print(json.dumps({"precision": run_precision(swv, torch, np, dev, configs)}),
+              flush=True)
+        return
+    if args.threshold:
+        print(json.dumps({"threshold": run_threshold(swv, torch, np, dev, configs)}),
               flush=True)
         return
     if args.clean_only:

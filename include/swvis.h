@@ -200,6 +200,39 @@ int swv_predict_tree_leaves(swv_ctx ctx, swv_tree tree, int64_t n_vis, const dou
                             const double* v, const double* w, int sign, int prec,
                             void* vis_out);
 
+/* Coefficient thresholding: the retention of a fixed proportion of the wavelet
+ * coefficients that section 1 cites (McEwen 2008), an approximation the paper
+ * itself does not use (it keeps every non-zero coefficient).  Writes a new,
+ * thresholded tree:
+ *  - ranked are the wavelet coefficients gamma^m_{j,k} of every node at levels
+ *    1 .. J-1 (Eq. 10 gives them orthonormal, so |gamma| compares across
+ *    levels); the level-1 scaling coefficients are always kept;
+ *  - the round(fraction N) largest |gamma| are retained (N = 3 x internal
+ *    nodes; ties to the lower flat index, below), the rest set to zero;
+ *  - a node with nothing retained at or below it becomes a leaf at its own
+ *    level: the plane wave is sampled at its pixel centre, as at the level-J
+ *    leaves, and nothing below it is visited.
+ * swv_predict_tree then evaluates Eq. 17 over the thresholded tree (FP64 or
+ * F32C); fraction 1 gives the exact tree route.  The thresholded tree works
+ * with swv_predict_tree (64-thread blocks), swv_tree_stats (n_leaves counts the
+ * leaves of every level, n_internal the remaining internal nodes) and batched
+ * plans (which then walk every tree with the traversal per branching node);
+ * swv_tree_leaves, swv_tree_level, swv_tree_set_flux, swv_predict_tree_leaves
+ * and swv_cycle_set_tree return SWV_ENOTSUP for it.  0 <= fraction <= 1. */
+int swv_tree_threshold(swv_tree tree, double fraction, swv_tree* out);
+
+/* The same with the retained coefficients given: kept [n_kept] HOST, flat
+ * indices increasing, where gamma^m_{j,k} has flat index
+ * 3 x (nodes at levels < j) + 3 k + m (k in the level's pixel order, as
+ * swv_tree_level lists it). */
+int swv_tree_prune(swv_tree tree, int64_t n_kept, const int64_t* kept, swv_tree* out);
+
+/* The retained coefficients of a thresholded tree: up to cap flat indices to
+ * kept (HOST), their count to *n_kept and the number of coefficients of the
+ * source tree to *n_coeffs. */
+int swv_tree_kept(swv_tree tree, int64_t cap, int64_t* kept, int64_t* n_kept,
+                  int64_t* n_coeffs);
+
 /* Releases the caller's handle.  A plan made with the tree holds its own
  * reference (its device records stay valid until the plan and its graphs are
  * destroyed); the tree is freed with the last reference. */

@@ -123,6 +123,9 @@ SIGNATURES = {
     "swv_graph_launch": [_vp],
     "swv_graph_destroy": [_vp],
     "swv_plan_destroy": [_vp],
+    "swv_tree_threshold": [_vp, _dbl, _pvp],
+    "swv_tree_prune": [_vp, _i64, _vp, _pvp],
+    "swv_tree_kept": [_vp, _i64, _vp, C.POINTER(_i64), C.POINTER(_i64)],
     "swv_cycle_create": [_vp, _int, C.POINTER(CycleInstance), _pvp],
     "swv_cycle_set_components": [_vp, _int, _i64, _vp, _vp, _vp],
     "swv_cycle_set_tree": [_vp, _int, _vp],

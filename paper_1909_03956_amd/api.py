@@ -251,6 +251,36 @@ class Tree:
                                    _np_ptr(gam)))
         return {"pix": pix, "mask": mask, "lambda": lam, "gamma": gam}
 
+    def threshold(self, fraction: float) -> "Tree":
+        """A thresholded copy keeping the given proportion of the wavelet
+        coefficients (largest |gamma|); nodes with nothing kept below them
+        become leaves at their own level."""
+        t = Tree.__new__(Tree)
+        t._h = C.c_void_p()
+        check(lib().swv_tree_threshold(self._h, float(fraction), C.byref(t._h)))
+        _track("tree", t)
+        t.J, t.ra_p, t.dec_p = self.J, self.ra_p, self.dec_p
+        return t
+
+    def prune(self, kept) -> "Tree":
+        """A thresholded copy keeping the coefficients with the given flat
+        indices (increasing; 3 x nodes of the levels above + 3 k + m)."""
+        k = np.ascontiguousarray(np.asarray(kept, dtype=np.int64))
+        t = Tree.__new__(Tree)
+        t._h = C.c_void_p()
+        check(lib().swv_tree_prune(self._h, k.size, _np_ptr(k), C.byref(t._h)))
+        _track("tree", t)
+        t.J, t.ra_p, t.dec_p = self.J, self.ra_p, self.dec_p
+        return t
+
+    def kept(self):
+        """(retained flat indices, number of coefficients) of a thresholded tree."""
+        n, nc = C.c_int64(), C.c_int64()
+        check(lib().swv_tree_kept(self._h, 0, C.c_void_p(0), C.byref(n), C.byref(nc)))
+        out = np.empty(n.value, np.int64)
+        check(lib().swv_tree_kept(self._h, n.value, _np_ptr(out), C.byref(n), C.byref(nc)))
+        return out, nc.value
+
     def set_leaf_flux(self, flux):
         """New flux per leaf (leaf order), same pixel set; coefficients recomputed."""
         f = _host_f64(flux)

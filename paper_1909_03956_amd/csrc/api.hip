@@ -182,6 +182,7 @@ TreeArgs tree_args(swv_tree t, const TRec* d_rec) {
     a.n_roots = (int)t->n_roots;
     a.J = t->J;
     a.seg_depth = t->max_branching + 1;
+    a.pruned = t->thresholded ? 1 : 0;
     for (int j = 0; j <= SWV_MAX_LEVEL; ++j) a.scale[j] = t->level_scale[j];
     return a;
 }
@@ -410,7 +411,8 @@ int swv_tree_stats(swv_tree t, swv_tree_stats_t* out) {
     for (int j = 1; j <= t->J; ++j) out->n_nodes[j] = (int64_t)t->levels[j - 1].pix.size();
     int64_t internal = 0;
     for (int j = 1; j < t->J; ++j) internal += out->n_nodes[j];
-    out->n_internal = internal;
+    // a thresholded tree has leaves above level J too
+    out->n_internal = t->thresholded ? t->n_alive : internal;
     out->n_records = (int64_t)t->records.size();
     out->sparsity = (double)out->n_leaves / (double)n_pixels(t->J);
     out->build_seconds = t->build_seconds;
@@ -420,6 +422,8 @@ int swv_tree_stats(swv_tree t, swv_tree_stats_t* out) {
 
 int swv_tree_leaves(swv_tree t, int64_t* pix, double* l, double* m, double* nm1, double* flux) {
     if (!t) return fail(SWV_EINVAL, "swv_tree_leaves: null tree");
+    if (t->thresholded)
+        return fail(SWV_ENOTSUP, "swv_tree_leaves: defined on an unthresholded tree only");
     const size_t n = t->leaf_pix.size();
     if (pix) std::memcpy(pix, t->leaf_pix.data(), n * sizeof(int64_t));
     if (l) std::memcpy(l, t->leaf_l.data(), n * sizeof(double));
@@ -432,6 +436,8 @@ int swv_tree_leaves(swv_tree t, int64_t* pix, double* l, double* m, double* nm1,
 int swv_tree_level(swv_tree t, int j, int64_t* pix, int32_t* child_mask, double* lambda,
                    double* gamma) {
     if (!t) return fail(SWV_EINVAL, "swv_tree_level: null tree");
+    if (t->thresholded)
+        return fail(SWV_ENOTSUP, "swv_tree_level: defined on an unthresholded tree only");
     if (j < 1 || j > t->J) return fail(SWV_EINVAL, "swv_tree_level: level %d not in [1, %d]", j, t->J);
     const TreeLevel& L = t->levels[j - 1];
     const size_t n = L.pix.size();
@@ -444,6 +450,8 @@ int swv_tree_level(swv_tree t, int j, int64_t* pix, int32_t* child_mask, double*
 
 int swv_tree_set_flux(swv_tree t, const double* leaf_flux) {
     if (!t) return fail(SWV_EINVAL, "swv_tree_set_flux: null tree");
+    if (t->thresholded)
+        return fail(SWV_ENOTSUP, "swv_tree_set_flux: defined on an unthresholded tree only");
     const size_t n = t->leaf_pix.size();
     if (n > 0 && !leaf_flux) return fail(SWV_EINVAL, "swv_tree_set_flux: null leaf_flux");
     for (size_t k = 0; k < n; ++k)
@@ -512,6 +520,10 @@ int swv_predict_tree_leaves(swv_ctx ctx, swv_tree t, int64_t n_vis, const double
                             void* vis_out) {
     CHECK_CTX(ctx);
     if (!t) return fail(SWV_EINVAL, "swv_predict_tree_leaves: null tree");
+    if (t->thresholded)
+        return fail(SWV_ENOTSUP,
+                    "swv_predict_tree_leaves: a thresholded tree has no Eq. 16 form (its dropped "
+                    "coefficients do not collapse onto leaves)");
     if (n_vis < 0) return fail(SWV_EINVAL, "swv_predict_tree_leaves: negative n_vis");
     NEED(u, n_vis); NEED(v, n_vis); NEED(w, n_vis); NEED(vis_out, n_vis);
     int rc = check_sign_prec(sign, prec, true);
@@ -541,6 +553,58 @@ int swv_tree_destroy(swv_tree t) {
             (void)hipFree(kv.second);
         }
     delete t;
+    return SWV_OK;
+}
+
+int swv_tree_threshold(swv_tree t, double fraction, swv_tree* out) {
+    if (!out) return fail(SWV_EINVAL, "swv_tree_threshold: null out");
+    *out = nullptr;
+    if (!t) return fail(SWV_EINVAL, "swv_tree_threshold: null tree");
+    if (t->thresholded) return fail(SWV_ENOTSUP, "swv_tree_threshold: tree already thresholded");
+    if (!(fraction >= 0.0 && fraction <= 1.0))
+        return fail(SWV_EDOMAIN, "swv_tree_threshold: fraction must be in [0, 1]");
+    TRY_BEGIN
+    auto* p = new swv_tree_s();
+    const int rc = prune_tree(*t, retain_fraction(*t, fraction), p);
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return SWV_OK;
+    TRY_END
+}
+
+int swv_tree_prune(swv_tree t, int64_t n_kept, const int64_t* kept, swv_tree* out) {
+    if (!out) return fail(SWV_EINVAL, "swv_tree_prune: null out");
+    *out = nullptr;
+    if (!t) return fail(SWV_EINVAL, "swv_tree_prune: null tree");
+    if (t->thresholded) return fail(SWV_ENOTSUP, "swv_tree_prune: tree already thresholded");
+    if (n_kept < 0 || (n_kept > 0 && !kept)) return fail(SWV_EINVAL, "swv_tree_prune: bad list");
+    TRY_BEGIN
+    std::vector<int64_t> k(kept, kept + n_kept);
+    for (int64_t i = 1; i < n_kept; ++i)
+        if (k[i] <= k[i - 1])
+            return fail(SWV_EINVAL, "swv_tree_prune: indices must increase");
+    auto* p = new swv_tree_s();
+    const int rc = prune_tree(*t, k, p);
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return SWV_OK;
+    TRY_END
+}
+
+int swv_tree_kept(swv_tree t, int64_t cap, int64_t* kept, int64_t* n_kept, int64_t* n_coeffs) {
+    if (!t || !n_kept || !n_coeffs || cap < 0 || (cap > 0 && !kept))
+        return fail(SWV_EINVAL, "swv_tree_kept: bad argument");
+    if (!t->thresholded) return fail(SWV_EINVAL, "swv_tree_kept: tree not thresholded");
+    *n_kept = (int64_t)t->kept.size();
+    *n_coeffs = t->n_coeffs;
+    const int64_t nw = std::min<int64_t>(cap, *n_kept);
+    if (nw > 0) std::memcpy(kept, t->kept.data(), (size_t)nw * sizeof(int64_t));
     return SWV_OK;
 }
 

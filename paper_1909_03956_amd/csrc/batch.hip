@@ -30,6 +30,7 @@ struct swv_plan_s {
     int vpl = 2, block = 256, grid_direct = 0, grid_tree = 0, grid_tree32 = 0, max_comp = 0;
     int jmax = 1, smax = 1;           // largest J and segment depth of the trees
     int tree_walker = 0, tree_depth = 1;
+    bool pruned = false;              // some tree is thresholded (leaves above level J)
     int tile_rows = 0;
     int64_t total_terms = 0;
     TreeArgs scales{};
@@ -97,11 +98,11 @@ hipError_t enqueue_plan(swv_plan p, hipStream_t s) {
     if (e != hipSuccess) return e;
     e = launch_batch_tree(s, p->tree_walker, p->tree_depth, SWV_FP64, p->grid_tree, p->scales,
                           p->d_tree, p->d_items_tree, p->n_items_tree, p->d_counters + 1,
-                          p->ctx->d_status);
+                          p->ctx->d_status, p->pruned);
     if (e != hipSuccess) return e;
     return launch_batch_tree(s, p->tree_walker, p->tree_depth, SWV_F32C, p->grid_tree32,
                              p->scales, p->d_tree, p->d_items_tree32, p->n_items_tree32,
-                             p->d_counters + 2, p->ctx->d_status);
+                             p->d_counters + 2, p->ctx->d_status, p->pruned);
 }
 
 int check_instance(const swv_instance& I, int k) {
@@ -190,6 +191,7 @@ int swv_batch_plan(swv_ctx ctx, int n, const swv_instance* inst, swv_plan* out) 
                 b.J = I.tree->J;
                 p->jmax = std::max(p->jmax, b.J);
                 p->smax = std::max(p->smax, I.tree->max_branching + 1);
+                p->pruned = p->pruned || I.tree->thresholded;
                 p->tree.push_back(b);
                 cost_per_row_tree.push_back((int64_t)I.tree->records.size() + 1);
                 p->total_terms += I.n_vis * I.tree->n_comp;
@@ -210,11 +212,25 @@ int swv_batch_plan(swv_ctx ctx, int n, const swv_instance* inst, swv_plan* out) 
         }
         p->tree_walker = (branch_ok && (want_branch || !level_ok)) ? 1 : 0;
         p->tree_depth = p->tree_walker ? p->smax : p->jmax;
+        if (p->pruned) {
+            // thresholded trees: the branch walker compiled for leaves above level J
+            if (!branch_ok) {
+                delete p;
+                return fail(SWV_ENOTSUP, "swv_batch_plan: a thresholded tree's branching is "
+                                         "above the compiled maximum");
+            }
+            p->tree_walker = 1;
+            p->tree_depth = kTreeMaxSeg;
+        }
 
         // persistent grids: as many blocks as stay resident
         p->grid_direct = ctx->n_cu * batch_direct_blocks_per_cu(p->vpl, p->block);
-        p->grid_tree = ctx->n_cu * batch_tree_blocks_per_cu(p->tree_walker, p->tree_depth, SWV_FP64);
-        p->grid_tree32 = ctx->n_cu * batch_tree_blocks_per_cu(p->tree_walker, p->tree_depth, SWV_F32C);
+        p->grid_tree = ctx->n_cu * (p->pruned ? batch_tree_pruned_blocks_per_cu(SWV_FP64)
+                                              : batch_tree_blocks_per_cu(p->tree_walker,
+                                                                         p->tree_depth, SWV_FP64));
+        p->grid_tree32 = ctx->n_cu * (p->pruned ? batch_tree_pruned_blocks_per_cu(SWV_F32C)
+                                                : batch_tree_blocks_per_cu(p->tree_walker,
+                                                                           p->tree_depth, SWV_F32C));
         const int64_t waves = (int64_t)p->grid_direct * (p->block / 64);
         // about 16 items per resident wave, in whole wave tiles, at most 64 of them
         const int64_t unit = 64LL * p->vpl;

@@ -378,6 +378,9 @@ int swv_cycle_set_tree(swv_cycle cy, int k, swv_tree t) {
     if (k < 0 || k >= (int)cy->spec.size() || cy->spec[k].route != SWV_ROUTE_TREE)
         return fail(SWV_EINVAL, "swv_cycle_set_tree: %d is not a tree instance", k);
     if (!t) return fail(SWV_EINVAL, "swv_cycle_set_tree: null tree");
+    if (t->thresholded)
+        return fail(SWV_ENOTSUP, "swv_cycle_set_tree: thresholded trees are not supported in a "
+                                 "captured cycle (its traversal is fixed at capture)");
     const int d = cy->slot[k];
     if (t->J > cy->spec[k].tree_level_cap)
         return fail(SWV_EINVAL, "swv_cycle_set_tree: J = %d above the instance's cap %d", t->J,

@@ -90,7 +90,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_direct(const BatchInst* __restr
 
 // PREC: SWV_FP64 (complex128 out) or SWV_F32C (FP32 leaf phasors, complex64
 // out), exactly as the single-instance tree kernel writes them.
-template <int JMAX, int WALKER, int PREC>
+template <int JMAX, int WALKER, int PREC, bool PRUNED = false>
 __global__ __launch_bounds__(kBatchTreeBlock) void k_batch_tree(
     TreeArgs scales, const BatchInst* __restrict__ inst, const WorkItem* __restrict__ items,
     unsigned n_items, unsigned* __restrict__ counter, int* __restrict__ status) {
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kBatchTreeBlock) void k_batch_tree(
             const int64_t j = jr < limit ? jr : limit - 1;
             const double U = u[j], V = v[j], W = w[j];
             double Vr, Vi;
-            tree_row<JMAX, WALKER, LDSL, kBatchTreeBlock, PREC == SWV_F32C>(
+            tree_row<JMAX, WALKER, LDSL, kBatchTreeBlock, PREC == SWV_F32C, PRUNED>(
                 rec, n_roots, J, scales, (LdsPtr)sums, U, V, W, Vr, Vi);
             if (jr < limit) {
                 if (!isfinite(U + V + W)) atomicOr(status, kStatusNonFinite);
@@ -150,13 +150,18 @@ int batch_direct_blocks_per_cu(int vpl, int block) {
     return 1;
 }
 
-template <int JMAX, int WALKER, int PREC>
+template <int JMAX, int WALKER, int PREC, bool PRUNED = false>
 static int tree_occupancy() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_tree<JMAX, WALKER, PREC>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_tree<JMAX, WALKER, PREC, PRUNED>,
                                                      kBatchTreeBlock, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
+}
+
+int batch_tree_pruned_blocks_per_cu(int prec) {
+    return prec == SWV_F32C ? tree_occupancy<kTreeMaxSeg, 1, SWV_F32C, true>()
+                            : tree_occupancy<kTreeMaxSeg, 1, SWV_FP64, true>();
 }
 
 // Instantiates X(depth, walker) for every compiled traversal.
@@ -194,9 +199,19 @@ hipError_t launch_batch_direct(hipStream_t s, int vpl, int block, int grid,
 hipError_t launch_batch_tree(hipStream_t s, int walker, int depth, int prec, int grid,
                              const TreeArgs& scales, const BatchInst* inst,
                              const WorkItem* items, unsigned n_items, unsigned* counter,
-                             int* status) {
+                             int* status, bool pruned) {
     if (n_items == 0) return hipSuccess;
     const dim3 g(grid), b(kBatchTreeBlock);
+    if (pruned) {
+        if (walker != 1 || depth != kTreeMaxSeg) return hipErrorInvalidValue;
+        if (prec == SWV_F32C)
+            k_batch_tree<kTreeMaxSeg, 1, SWV_F32C, true><<<g, b, 0, s>>>(scales, inst, items, n_items,
+                                                                       counter, status);
+        else
+            k_batch_tree<kTreeMaxSeg, 1, SWV_FP64, true><<<g, b, 0, s>>>(scales, inst, items, n_items,
+                                                                       counter, status);
+        return hipGetLastError();
+    }
 #define SWV_RUN_T(D, W)                                                                    \
     if (walker == W && depth == D) {                                                       \
         if (prec == SWV_F32C)                                                              \

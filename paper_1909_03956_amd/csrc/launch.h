@@ -32,6 +32,7 @@ struct TreeArgs {
     int n_roots;
     int J;
     int seg_depth;                    // 1 + most branching nodes on a root-to-leaf path
+    int pruned;                       // leaves above level J (coefficient thresholding)
     double scale[SWV_MAX_LEVEL + 1];  // sqrt(A_j) / 4
 };
 
@@ -45,7 +46,8 @@ constexpr int kTreeMaxSeg = 16;
 
 // walker 0: level walker (t.J <= kTreeMaxJ); 1: branch walker
 // (t.seg_depth <= kTreeMaxSeg).  prec SWV_FP64 (complex128 out) or SWV_F32C
-// (FP32 leaf phasors, complex64 out).
+// (FP32 leaf phasors, complex64 out).  A thresholded tree (t.pruned) runs the
+// traversals compiled for leaves above level J, at 64-thread blocks.
 hipError_t launch_tree(hipStream_t s, int walker, int block, int prec, const TreeArgs& t,
                        int64_t n_vis, const double* u, const double* v, const double* w,
                        int sign, void* out, int* status);
@@ -113,10 +115,14 @@ int batch_tree_blocks_per_cu(int walker, int depth, int prec);
 hipError_t launch_batch_direct(hipStream_t s, int vpl, int block, int grid,
                                const BatchInst* inst, const Comp* pack, const WorkItem* items,
                                unsigned n_items, unsigned* counter, int* status);
-// prec: the precision of every instance the work items refer to.
+// prec: the precision of every instance the work items refer to.  pruned: some
+// tree holds leaves above level J; only the branch walker at depth kTreeMaxSeg
+// is compiled for that.
 hipError_t launch_batch_tree(hipStream_t s, int walker, int depth, int prec, int grid,
                              const TreeArgs& scales, const BatchInst* inst, const WorkItem* items,
-                             unsigned n_items, unsigned* counter, int* status);
+                             unsigned n_items, unsigned* counter, int* status,
+                             bool pruned = false);
+int batch_tree_pruned_blocks_per_cu(int prec);
 constexpr int kBatchTreeBlock = 64;
 
 }  // namespace swv

@@ -119,6 +119,149 @@ void build_coefficients(swv_tree_s* t) {
     }
 }
 
+// ------------------------------------------------------------ thresholding --
+// Hard thresholding of the wavelet coefficients, the retention of a fixed
+// proportion that section 1 cites (the paper itself keeps every non-zero
+// coefficient).  The coefficients of Eq. 10 are orthonormal (sqrt(A_j)/4), so
+// their magnitudes rank across levels.
+
+std::vector<int64_t> retain_fraction(const swv_tree_s& t, double fraction) {
+    std::vector<double> mag;
+    for (int j = 1; j < t.J; ++j)
+        for (double g : t.levels[j - 1].gamma) mag.push_back(std::fabs(g));
+    const int64_t n = (int64_t)mag.size();
+    std::vector<int64_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    // largest first, ties to the lower flat index
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return mag[a] > mag[b]; });
+    int64_t keep = (int64_t)std::floor(fraction * (double)n + 0.5);
+    keep = std::max<int64_t>(0, std::min<int64_t>(n, keep));
+    std::vector<int64_t> kept(order.begin(), order.begin() + keep);
+    std::sort(kept.begin(), kept.end());
+    return kept;
+}
+
+namespace {
+
+struct Pruner {
+    const swv_tree_s& t;
+    const Frame F;
+    std::vector<int64_t> off;                    // flat offset of level j's coefficients
+    std::vector<uint8_t> keep;                   // per flat index
+    std::vector<std::vector<uint8_t>> alive;     // [j - 1][k], levels < J
+    std::vector<std::vector<int32_t>> chain;     // one-child runs of the pruned tree
+    std::vector<std::vector<int32_t>> depth;     // branching nodes at and below
+    swv_tree_s* out;
+
+    Pruner(const swv_tree_s& tt, swv_tree_s* o) : t(tt), F(make_frame(tt.ra_p, tt.dec_p)), out(o) {}
+
+    void emit(int j, int64_t idx) {
+        if (j == t.J) {
+            out->records.push_back(
+                TRec{t.leaf_l[idx], t.leaf_m[idx], t.leaf_nm1[idx], make_meta(0, j, 0)});
+            out->levels[j - 1].pix.push_back(t.leaf_pix[idx]);
+            out->leaf_pix.push_back(t.leaf_pix[idx]);
+            return;
+        }
+        const TreeLevel& L = t.levels[j - 1];
+        if (!alive[j - 1][idx]) {
+            // nothing retained here or below: a leaf at its own level, the
+            // plane wave sampled at its pixel centre
+            ld xyz[3];
+            double l, m, nm1;
+            pix2xyz(j, L.pix[idx], xyz);
+            xyz_to_lmn(F, xyz, &l, &m, &nm1);
+            out->records.push_back(TRec{l, m, nm1, make_meta(0, j, 0)});
+            out->levels[j - 1].pix.push_back(L.pix[idx]);
+            out->leaf_pix.push_back(L.pix[idx]);
+            return;
+        }
+        const int64_t f = off[j - 1] + 3 * idx;
+        out->records.push_back(TRec{keep[f] ? L.gamma[3 * idx] : 0.0,
+                                    keep[f + 1] ? L.gamma[3 * idx + 1] : 0.0,
+                                    keep[f + 2] ? L.gamma[3 * idx + 2] : 0.0,
+                                    make_meta((unsigned)L.mask[idx], j, chain[j - 1][idx])});
+        out->levels[j - 1].pix.push_back(L.pix[idx]);
+        ++out->n_alive;
+        int64_t child = L.first_child[idx];
+        for (int c = 0; c < 4; ++c)
+            if (L.mask[idx] & (1 << c)) emit(j + 1, child++);
+    }
+};
+
+}  // namespace
+
+int prune_tree(const swv_tree_s& t, const std::vector<int64_t>& kept, swv_tree_s* out) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int J = t.J;
+    Pruner P(t, out);
+    P.off.assign(J, 0);
+    for (int j = 1; j < J; ++j) P.off[j] = P.off[j - 1] + 3 * (int64_t)t.levels[j - 1].pix.size();
+    const int64_t n_coeffs = J > 1 ? P.off[J - 1] : 0;
+    P.keep.assign((size_t)n_coeffs, 0);
+    for (int64_t f : kept) {
+        if (f < 0 || f >= n_coeffs)
+            return fail(SWV_EINVAL, "coefficient index %lld outside [0, %lld)", (long long)f,
+                        (long long)n_coeffs);
+        P.keep[(size_t)f] = 1;
+    }
+    // bottom-up: whether a node keeps a coefficient at or below it, its
+    // one-child run and its branching depth in the pruned tree
+    P.alive.assign(J, {});
+    P.chain.assign(J, {});
+    P.depth.assign(J, {});
+    for (int j = J - 1; j >= 1; --j) {
+        const TreeLevel& L = t.levels[j - 1];
+        const int64_t n = (int64_t)L.pix.size();
+        P.alive[j - 1].assign(n, 0);
+        P.chain[j - 1].assign(n, 0);
+        P.depth[j - 1].assign(n, 0);
+        for (int64_t k = 0; k < n; ++k) {
+            const int64_t f = P.off[j - 1] + 3 * k;
+            bool a = P.keep[f] || P.keep[f + 1] || P.keep[f + 2];
+            const int nch = __builtin_popcount((unsigned)L.mask[k]);
+            const int64_t c0 = L.first_child[k];
+            int d = 0;
+            if (j + 1 < J)
+                for (int i = 0; i < nch; ++i)
+                    if (P.alive[j][c0 + i]) {
+                        a = true;
+                        d = std::max(d, P.depth[j][c0 + i]);
+                    }
+            P.alive[j - 1][k] = a;
+            P.depth[j - 1][k] = d + (nch >= 2 ? 1 : 0);
+            if (nch == 1)
+                P.chain[j - 1][k] =
+                    1 + ((j + 1 < J && P.alive[j][c0]) ? P.chain[j][c0] : 0);
+        }
+    }
+    out->J = J;
+    out->ra_p = t.ra_p;
+    out->dec_p = t.dec_p;
+    out->n_comp = t.n_comp;
+    out->thresholded = true;
+    out->n_coeffs = n_coeffs;
+    out->kept = kept;
+    out->levels.assign(J, TreeLevel());
+    out->records.clear();
+    out->leaf_pix.clear();
+    out->n_alive = 0;
+    for (int j = 1; j <= SWV_MAX_LEVEL; ++j) out->level_scale[j] = level_scale(j);
+    out->max_branching = 0;
+    const TreeLevel& L1 = t.levels[0];
+    const double A1 = pixel_area(1);
+    out->n_roots = (int64_t)L1.pix.size();
+    for (int64_t r = 0; r < out->n_roots; ++r) {
+        out->records.push_back(TRec{A1 * L1.lambda[r], 0.0, 0.0, 0ull});
+        P.emit(1, r);
+        if (J > 1 && P.alive[0][r]) out->max_branching = std::max(out->max_branching, P.depth[0][r]);
+    }
+    out->build_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return SWV_OK;
+}
+
 int build_tree_pixels(int J, double ra_p, double dec_p, int64_t n, const int64_t* kJ,
                       const double* flux, swv_tree_s* t) {
     const auto t0 = std::chrono::steady_clock::now();

@@ -44,6 +44,14 @@ struct swv_tree_s {
     // the caller's handle plus one per plan that reads the device records; the
     // tree is freed when the last of them is released
     int refs = 1;
+    // coefficient thresholding (swv_tree_threshold / swv_tree_prune): the tree
+    // is a pruned copy whose record stream has leaves at several levels;
+    // `levels[j - 1].pix` then lists the nodes present at level j and
+    // `leaf_pix` the leaves of every level
+    bool thresholded = false;
+    int64_t n_alive = 0;                 // internal nodes of the pruned tree
+    int64_t n_coeffs = 0;                // wavelet coefficients of the source tree
+    std::vector<int64_t> kept;           // retained ones, flat indices, increasing
 };
 
 namespace swv {
@@ -58,5 +66,16 @@ int build_tree(int J, double ra_p, double dec_p, int64_t n, const double* l, con
 // The same from the components' level-J pixel ids (the cross-referenced form).
 int build_tree_pixels(int J, double ra_p, double dec_p, int64_t n, const int64_t* kJ,
                       const double* flux, swv_tree_s* out);
+
+// Flat index of gamma^m_{j,k}: 3 x (nodes at levels < j) + 3 k + m.  The
+// retained coefficients of a proportion `fraction`: the round(fraction N)
+// largest |gamma|, ties to the lower flat index; returned increasing.
+std::vector<int64_t> retain_fraction(const swv_tree_s& t, double fraction);
+
+// The thresholded tree of `t` keeping the coefficients `kept` (flat indices,
+// increasing, each below 3 x internal nodes): nodes with nothing retained at or
+// below them become leaves at their own level (their pixel centre), dropped
+// coefficients of the other nodes are zero.  Status code.
+int prune_tree(const swv_tree_s& t, const std::vector<int64_t>& kept, swv_tree_s* out);
 
 }  // namespace swv

@@ -42,7 +42,7 @@
 namespace swv {
 
 // PREC: SWV_FP64 (complex128 out) or SWV_F32C (FP32 leaf phasors, complex64 out).
-template <int JMAX, int BLOCK, int WALKER, int PREC>
+template <int JMAX, int BLOCK, int WALKER, int PREC, bool PRUNED = false>
 __global__ __launch_bounds__(BLOCK) void k_tree(TreeArgs ta, const double* __restrict__ u,
                                                 const double* __restrict__ v,
                                                 const double* __restrict__ w, int64_t n_vis,
@@ -54,8 +54,8 @@ __global__ __launch_bounds__(BLOCK) void k_tree(TreeArgs ta, const double* __res
     constexpr int LDSL = tree_lds_levels<JMAX, BLOCK>();
     __shared__ double sums[LDSL > 0 ? LDSL * kSlotDoubles * BLOCK : 1];
     double Vr, Vi;
-    tree_row<JMAX, WALKER, LDSL, BLOCK, PREC == SWV_F32C>(ta.rec, ta.n_roots, ta.J, ta,
-                                                          (LdsPtr)sums, U, V, W, Vr, Vi);
+    tree_row<JMAX, WALKER, LDSL, BLOCK, PREC == SWV_F32C, PRUNED>(ta.rec, ta.n_roots, ta.J, ta,
+                                                                  (LdsPtr)sums, U, V, W, Vr, Vi);
     if (jrow < n_vis) {
         if (!isfinite(U + V + W)) atomicOr(status, kStatusNonFinite);
         if constexpr (PREC == SWV_F32C)
@@ -70,6 +70,12 @@ static hipError_t run_tree_p(hipStream_t s, int block, const TreeArgs& t, int64_
                              const double* u, const double* v, const double* w, int sign,
                              void* out, int* status) {
     const double sg = (double)sign;
+    if (t.pruned) {
+        // thresholded trees: one block shape
+        k_tree<JMAX, 64, WALKER, PREC, true><<<dim3((unsigned)((n_vis + 63) / 64)), dim3(64), 0, s>>>(
+            t, u, v, w, n_vis, sg, out, status);
+        return hipGetLastError();
+    }
     switch (block) {
         case 64:
             k_tree<JMAX, 64, WALKER, PREC><<<dim3((unsigned)((n_vis + 63) / 64)), dim3(64), 0, s>>>(

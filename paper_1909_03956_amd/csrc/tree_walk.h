@@ -190,9 +190,23 @@ __device__ __forceinline__ void leaf_wave(RecPtr rec, int me, double u, double v
     }
 }
 
+// Leaf at level j < J, which only a thresholded tree has: a node none of whose
+// coefficients at or below it is retained, walked as a leaf at its pixel
+// centre.  The traversal hands up plain sums T_j = 4^(J-j) eta_j (see
+// close_node), so its plane wave is scaled by that exact power of two.  Only
+// the PRUNED instantiations of the walkers test for such leaves.
+template <bool F32>
+__device__ __forceinline__ void leaf_above(RecPtr rec, int me, int j, int J, double u,
+                                           double v, double w, double& er, double& ei) {
+    leaf_wave<false, F32>(rec, me, u, v, w, er, ei);
+    const double s = pow2_scale(1.0, 2 * (J - j));
+    er *= s;
+    ei *= s;
+}
+
 // Level walker: one register set per level, the level a template parameter
 // (levels <= LDSL keep theirs in LDS).
-template <int LVL, int JMAX, int LDSL, int BLOCK, bool F32>
+template <int LVL, int JMAX, int LDSL, int BLOCK, bool F32, bool PRUNED>
 __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const TreeArgs& ta,
                                      LdsPtr lds, const double u, const double v, const double w,
                                      double& er, double& ei, double& Vr, double& Vi) {
@@ -203,6 +217,12 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const Tr
     }
     if constexpr (LVL < JMAX) {
         const unsigned all = meta_mask(rec[me].meta);
+        if constexpr (PRUNED) {
+            if (all == 0) {   // a node collapsed by thresholding
+                leaf_above<F32>(rec, me, LVL, J, u, v, w, er, ei);
+                return;
+            }
+        }
         const int c0 = __builtin_ctz(all);
         unsigned mask = all;
         NodeSums n;
@@ -216,7 +236,7 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const Tr
                 if (mask != all) slot_put<BLOCK>(lds, LVL - 1, k++, xr, xi);
                 c = __builtin_ctz(mask);
                 mask &= mask - 1;
-                walk<LVL + 1, JMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr,
+                walk<LVL + 1, JMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr,
                                                       Vi);
             }
             slot_replay<BLOCK>(lds, LVL - 1, k, all, c0, n, first);
@@ -226,14 +246,14 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const Tr
                 const int c = __builtin_ctz(mask);
                 mask &= mask - 1;
                 double xr, xi;
-                walk<LVL + 1, JMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr,
+                walk<LVL + 1, JMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr,
                                                       Vi);
                 add_child(n, c, c0, xr, xi, first);
                 first = false;
             }
         }
-        close_node(n, c0, pow2_scale(ta.scale[LVL], 2 * (LVL + 1 - J)), rec[me].a, rec[me].b,
-                   rec[me].c, er, ei, Vr, Vi);
+        close_node(n, c0, level_factor(ta, LVL, J), rec[me].a, rec[me].b, rec[me].c, er, ei,
+                   Vr, Vi);
     }
 }
 
@@ -243,7 +263,7 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const Tr
 // walked, and is closed bottom-up afterwards with the same arithmetic a
 // one-child node gets in the level walker.  D counts segments from the root;
 // the host launches DMAX >= 1 + the tree's largest branching count on a path.
-template <int D, int DMAX, int LDSL, int BLOCK, bool F32>
+template <int D, int DMAX, int LDSL, int BLOCK, bool F32, bool PRUNED>
 __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, const TreeArgs& ta,
                                          LdsPtr lds, const double u, const double v,
                                          const double w, double& er, double& ei, double& Vr,
@@ -257,6 +277,9 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
     ei = 0.0;
     if (meta_level(mt) == J) {
         leaf_wave<false, F32>(rec, term, u, v, w, er, ei);
+    } else if (PRUNED && meta_mask(mt) == 0) {
+        // a node collapsed by thresholding
+        leaf_above<F32>(rec, term, meta_level(mt), J, u, v, w, er, ei);
     } else {
         if constexpr (D < DMAX) {
             // a terminal node has two or more children.  Its sums start at
@@ -276,7 +299,7 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
                     if (mask != all) slot_put<BLOCK>(lds, D - 1, k++, xr, xi);
                     c = __builtin_ctz(mask);
                     mask &= mask - 1;
-                    seg_walk<D + 1, DMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, u, v, w, xr,
+                    seg_walk<D + 1, DMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, ta, lds, u, v, w, xr,
                                                             xi, Vr, Vi);
                 }
                 slot_replay<BLOCK>(lds, D - 1, k, all, 0, n, first);
@@ -286,7 +309,7 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
                     const int c = __builtin_ctz(mask);
                     mask &= mask - 1;
                     double xr, xi;
-                    seg_walk<D + 1, DMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, u, v, w, xr,
+                    seg_walk<D + 1, DMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, ta, lds, u, v, w, xr,
                                                             xi, Vr, Vi);
                     add_child(n, c, 0, xr, xi, false);
                 }
@@ -316,7 +339,8 @@ constexpr int tree_lds_levels() {
 // V (real, imaginary / 4) of one row: the root loop of the traversal.
 // WALKER 0: level walker up to level JMAX; 1: branch walker up to JMAX segments.
 // lds: the block's [LDSL][6][BLOCK] child slots.  F32: FP32 phasors at the leaves.
-template <int JMAX, int WALKER, int LDSL, int BLOCK, bool F32 = false>
+// PRUNED: the tree may hold leaves above level J (coefficient thresholding).
+template <int JMAX, int WALKER, int LDSL, int BLOCK, bool F32 = false, bool PRUNED = false>
 __device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J,
                                          const TreeArgs& ta, LdsPtr lds, double U, double V,
                                          double W, double& Vr, double& Vi) {
@@ -328,9 +352,10 @@ __device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J,
         const int root = pos++;
         double er, ei;
         if constexpr (WALKER == 0)
-            walk<1, JMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, U, V, W, er, ei, Vr, Vi);
+            walk<1, JMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, ta, lds, U, V, W, er, ei, Vr, Vi);
         else
-            seg_walk<1, JMAX, LDSL, BLOCK, F32>(rec, pos, J, ta, lds, U, V, W, er, ei, Vr, Vi);
+            seg_walk<1, JMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, ta, lds, U, V, W, er, ei, Vr,
+                                                         Vi);
         // A_1 lambda_1 eta_1 with eta_1 = T_1 / 4^(J-1); ldexp, as A_1 lambda_1
         // may be zero
         const double A1lam = ldexp(rec[root].a, -2 * (J - 1));

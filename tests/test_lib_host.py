@@ -324,3 +324,66 @@ def test_shutdown_closes_in_dependency_order(monkeypatch):
     monkeypatch.setattr(api, "_LIVE", live)
     api.shutdown()
     assert order == ["graph", "graph", "cycle", "plan", "tree", "tree", "ctx", "ctx"]
+
+
+@pytest.mark.parametrize("J,frac", [(10, 0.01), (10, 0.1), (10, 0.5), (9, 0.25), (14, 0.05),
+                                    (1, 0.5), (6, 0.0), (6, 1.0)])
+def test_threshold_keeps_the_oracle_coefficients(swv, J, frac):
+    # the library ranks its own coefficients; ranks differ from the oracle's
+    # only where two magnitudes are within rounding of each other at the cut
+    from oracle import threshold as oth
+    from paper_1909_03956_amd.api import Tree
+    W = configs.CFG2
+    l, m, f = W.components()
+    t = Tree(J, W.ra_p, W.dec_p, l, m, f)
+    ref = ot.build_tree(J, W.ra_p, W.dec_p, l, m, f)
+    tt = t.threshold(frac)
+    kept, n_coeffs = tt.kept()
+    want = oth.retained(ref, frac)
+    assert n_coeffs == 3 * ref.n_internal and kept.size == want.size
+    mags = np.concatenate([np.abs(lv.gamma).ravel() for lv in ref.levels[:-1]]) \
+        if J > 1 else np.zeros(0)
+    diff = np.setxor1d(kept, want)
+    if diff.size:
+        cut = mags[want].min()
+        assert np.all(np.abs(mags[diff] - cut) <= 1e-14 * cut), (J, frac, diff.size)
+    # the pruned tree's shape from the oracle's decision
+    tp = t.prune(want)
+    alive = oth.alive_nodes(ref, oth.keep_masks(ref, want)) if J > 1 else []
+    st = tp.stats()
+    assert st["n_internal"] == int(sum(a.sum() for a in alive))
+    # every leaf is a collapsed node or a level-J leaf under a remaining node
+    n_leaf = 0
+    for j in range(1, J + 1):
+        if j == 1:
+            parent_alive = np.ones(ref.levels[0].pix.size, bool)
+        else:
+            lv = ref.levels[j - 2]
+            parent_alive = np.zeros(ref.levels[j - 1].pix.size, bool)
+            for cc in range(4):
+                has = lv.child[:, cc] >= 0
+                parent_alive[lv.child[has, cc]] = alive[j - 2][has]
+        here = parent_alive if j == J else parent_alive & ~alive[j - 1]
+        n_leaf += int(here.sum())
+    assert st["n_leaves"] == n_leaf
+    for name, call in (("leaves", tp.leaves), ("level", lambda: tp.level(1)),
+                       ("set_flux", lambda: tp.set_leaf_flux(np.ones(st["n_leaves"])))):
+        with pytest.raises(swv.SwvError) as e:
+            call()
+        assert e.value.code == swv.SWV_ENOTSUP, name
+
+
+def test_threshold_argument_errors(swv):
+    from paper_1909_03956_amd.api import Tree
+    t = Tree(5, 0.1, 0.2, np.array([0.01, 0.02]), np.array([0.0, 0.01]), np.array([1.0, 2.0]))
+    for bad in (-0.1, 1.5, float("nan")):
+        with pytest.raises(swv.SwvError) as e:
+            t.threshold(bad)
+        assert e.value.code == swv.SWV_EDOMAIN
+    n = 3 * t.stats()["n_internal"]
+    with pytest.raises(swv.SwvError):
+        t.prune([n])                       # out of range
+    with pytest.raises(swv.SwvError):
+        t.prune([2, 1])                    # not increasing
+    with pytest.raises(swv.SwvError):
+        t.threshold(0.5).threshold(0.5)    # already thresholded
