@@ -474,6 +474,9 @@ def run_compare(swv, torch, np, dev, configs):
     ms_direct = timed(lambda: swv.predict_direct(U, V, Wt, L, M, F, out=ref))
     out = {"workload": f"clean7 track (707,616 vis) and 256 x 256 grid; {pix.size} components "
                        "on image pixels within 30 deg; reference: the direct sum",
+           "comparator": "FFT + degridding as a type-2 non-uniform FFT in (u, v, w): "
+                         "exponential-of-semicircle kernel over W cells, w planes interpolated "
+                         "(improved w-stacking), not the w-kernel convolution of Eq. 3",
            "direct": {"ms": round(ms_direct, 4)}}
     buf = torch.empty_like(ref)
     for J in (11, 16, 20, 25):
@@ -900,6 +903,23 @@ def main():
         "Gvis_terms_per_s": round(n_vis * n_comp / (ms * 1e-3) / 1e9, 2),
         "max_diff_vs_tree": float(f"{diff:.3e}")}
     Tx.close()
+    # the adjoint's precision form on the step's residual (FP32 phasors,
+    # products and Kahan sums; complex128 image)
+    r_, _ = swv.residual_chi2(v_obs, v64, inv_s2, out=resid)
+    swv.adjoint(U, V, Wt, r_, PL, PM, PN, prec="f32c")
+    times = []
+    for _ in range(max(3, args.steps // 2)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        swv.adjoint(U, V, Wt, r_, PL, PM, PN, prec="f32c")
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    extra_routes["adjoint_f32c"] = {
+        "ms": round(ms, 4), "Gvis_terms_per_s": round(n_vis * n_pix / (ms * 1e-3) / 1e9, 2),
+        "roofline": dict(f32c_roofline("adjoint_f32c", n_vis * n_pix / (ms * 1e-3), peaks),
+                         kernel="k_adjoint (SWV_F32C)")}
 
     # per-stage device times (median over steps)
     per = {s: [] for s in stages}

@@ -100,6 +100,29 @@ def predict_direct(u, v, w, l, m, flux, sign=-1, nm1=None, chunk=2048):
     return out
 
 
+def predict_direct_fp64(u, v, w, l, m, flux, sign=-1, nm1=None, chunk=1024):
+    """Eq. 12 as predict_direct, with the phase u l + v m + w (n - 1) formed in
+    plain FP64 arithmetic (then reduced by rint) instead of error-free
+    products: its error is a few units in the last place of the phase, about
+    2 pi 3 2^-53 |phi| per term, and it runs several times faster, for inputs
+    of full workload size (the observed visibilities of a perturbed model)."""
+    _check_sign(sign)
+    u = np.asarray(u, np.float64)
+    v = np.asarray(v, np.float64)
+    w = np.asarray(w, np.float64)
+    l = np.asarray(l, np.float64)
+    m = np.asarray(m, np.float64)
+    nm1 = n_minus_1(l, m) if nm1 is None else np.asarray(nm1, np.float64)
+    a = np.asarray(flux, np.float64)
+    out = np.empty(u.shape[0], np.complex128)
+    for s in range(0, u.shape[0], chunk):
+        sl = slice(s, s + chunk)
+        ph = np.outer(u[sl], l) + np.outer(v[sl], m) + np.outer(w[sl], nm1)
+        ang = 2.0 * np.pi * (ph - np.rint(ph))
+        out[sl] = np.cos(ang) @ a + 1j * (sign * (np.sin(ang) @ a))
+    return out
+
+
 def adjoint(u, v, w, y, l, m, nm1, sign=-1, chunk=2048):
     """Adjoint of predict_direct on a pixel set p = (l, m, n-1):
 

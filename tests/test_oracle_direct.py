@@ -179,3 +179,24 @@ def test_residual_chi2_closed_form():
     r, chi2 = ov.residual_chi2(obs, obs - (3 + 4j), 1e4)
     assert np.all(r == 3 + 4j)
     assert abs(chi2 - 1000 * 25 * 1e4) < 1e-6
+
+
+def test_plain_fp64_phase_form_agrees_with_the_exact_one():
+    # predict_direct_fp64 (plain FP64 phase) against predict_direct (error-free
+    # phase products): within the phase rounding 2 pi 3 2^-53 |phi| per term,
+    # and the closed forms hold for it too
+    from oracle import visibility as ov
+    rng = np.random.default_rng(41)
+    u, v, w = (rng.uniform(-1e5, 1e5, 3000) for _ in range(3))
+    l, m = rng.uniform(-0.05, 0.05, 70), rng.uniform(-0.05, 0.05, 70)
+    f = rng.lognormal(-3, 1, 70)
+    a = ov.predict_direct_fp64(u, v, w, l, m, f)
+    b = ov.predict_direct(u, v, w, l, m, f)
+    nm1 = ov.n_minus_1(l, m)
+    phi = np.abs(np.outer(u, l)) + np.abs(np.outer(v, m)) + np.abs(np.outer(w, nm1))
+    bound = (2 * np.pi * 3 * 2.0 ** -53 * phi + 1e-15) @ f
+    assert np.all(np.abs(a - b) <= bound)
+    one = ov.predict_direct_fp64(u, v, w, np.zeros(1), np.zeros(1), np.ones(1))
+    assert np.all(one == 1.0)
+    assert np.allclose(ov.predict_direct_fp64(u, v, w, l, m, f, sign=1),
+                       np.conj(a), rtol=0, atol=1e-13)
