@@ -147,6 +147,11 @@ def parse():
                         "the run-time sweep's track at J = 16): time and error against the "
                         "exact tree route for retained proportions 1 .. 0.005; print one "
                         "JSON line and exit")
+    p.add_argument("--adjoint-shapes", action="store_true",
+                   help="the adjoint on the step's rows and pixels (8,355,840 x 955) at "
+                        "tile shapes 4x128, 4x256, 2x256 and 1x256 (pixels per lane x "
+                        "threads): median time of seven launches each, one JSON line; for "
+                        "a FETCH_SIZE counter pass per shape")
     p.add_argument("--no-cfg3", action="store_true",
                    help="skip the precision-form leg on its own workload (cfg3)")
     p.add_argument("--no-cfg4", action="store_true",
@@ -573,6 +578,46 @@ def run_precision(swv, torch, np, dev, configs, peaks=None):
     return out
 
 
+def run_adjoint_shapes(swv, torch, np, dev, configs, models):
+    """The adjoint of the step (cfg2 rows, the J = 9 pixels within 4 deg) at
+    several tile shapes, each set in the tuning table of the device's context
+    (the large-row class of the adjoint family), which is left at the default
+    shape afterwards."""
+    W = configs.CFG2
+
+    def D(x):
+        return torch.as_tensor(np.ascontiguousarray(x), device=dev)
+
+    u, v, w = (D(a) for a in W.track.uvw())
+    y = D(models.complex_noise(u.numel(), configs.CFG5_NOISE_SIGMA,
+                               np.random.default_rng(configs.CFG5_SEED_NOISE)))
+    _, pl, pm, pn = swv.pixels_in_disk(9, W.ra_p, W.dec_p, math.radians(4.0))
+    L, M, N = D(pl), D(pm), D(pn)
+    ctx = swv.context(dev)
+    from paper_1909_03956_amd._lib import FAM_ADJOINT as fam_adjoint
+    large = 1   # size class of 2^20 rows or more
+    out = []
+    for ppl, block in ((4, 128), (4, 256), (2, 256), (1, 256)):
+        ctx.tune_set(fam_adjoint, large, ppl, block)
+        img = swv.adjoint(u, v, w, y, L, M, N)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(7):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            img = swv.adjoint(u, v, w, y, L, M, N)
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        out.append({"pixels_per_lane": ppl, "block": block,
+                    "tiles": -(-pl.size // (ppl * block)),
+                    "ms": round(float(np.median(times)), 4)})
+        log(f"adjoint {ppl} x {block}: {out[-1]['ms']} ms")
+    ctx.tune_set(fam_adjoint, large, 4, 256)
+    return {"workload": f"cfg2 rows ({u.numel():,}) x {pl.size} pixels (J = 9 within 4 deg)",
+            "shapes": out}
+
+
 def run_threshold(swv, torch, np, dev, configs):
     """Retained proportion against time and error (the thresholded variant of
     section 1): each thresholded tree is timed as single launches (median of
@@ -768,6 +813,10 @@ def main():
     if args.threshold:
         print(json.dumps({"threshold": run_threshold(swv, torch, np, dev, configs)}),
               flush=True)
+        return
+    if args.adjoint_shapes:
+        print(json.dumps({"adjoint_shapes": run_adjoint_shapes(swv, torch, np, dev, configs,
+                                                                models)}), flush=True)
         return
     if args.clean_only:
         print(json.dumps({"clean_loop": run_clean(swv, torch, np, dev, configs),

@@ -10,7 +10,6 @@
 #include <vector>
 
 #include "api_internal.h"
-#include "sphere.h"
 
 using namespace swv;
 
@@ -33,7 +32,6 @@ struct swv_plan_s {
     bool pruned = false;              // some tree is thresholded (leaves above level J)
     int tile_rows = 0;
     int64_t total_terms = 0;
-    TreeArgs scales{};
     int refs = 1;  // graphs captured from this plan hold a reference
 };
 
@@ -96,12 +94,11 @@ hipError_t enqueue_plan(swv_plan p, hipStream_t s) {
                             p->d_items_direct, p->n_items_direct, p->d_counters,
                             p->ctx->d_status);
     if (e != hipSuccess) return e;
-    e = launch_batch_tree(s, p->tree_walker, p->tree_depth, SWV_FP64, p->grid_tree, p->scales,
-                          p->d_tree, p->d_items_tree, p->n_items_tree, p->d_counters + 1,
+    e = launch_batch_tree(s, p->tree_walker, p->tree_depth, SWV_FP64, p->grid_tree, p->d_tree, p->d_items_tree, p->n_items_tree, p->d_counters + 1,
                           p->ctx->d_status, p->pruned);
     if (e != hipSuccess) return e;
     return launch_batch_tree(s, p->tree_walker, p->tree_depth, SWV_F32C, p->grid_tree32,
-                             p->scales, p->d_tree, p->d_items_tree32, p->n_items_tree32,
+                             p->d_tree, p->d_items_tree32, p->n_items_tree32,
                              p->d_counters + 2, p->ctx->d_status, p->pruned);
 }
 
@@ -197,9 +194,6 @@ int swv_batch_plan(swv_ctx ctx, int n, const swv_instance* inst, swv_plan* out) 
                 p->total_terms += I.n_vis * I.tree->n_comp;
             }
         }
-        for (int j = 0; j <= SWV_MAX_LEVEL; ++j)
-            p->scales.scale[j] = j >= 1 ? level_scale(j) : 0.0;
-        p->scales.J = p->jmax;
         // one traversal for all trees of the plan: the tuned one where it fits
         const bool level_ok = p->jmax <= kTreeMaxJ, branch_ok = p->smax <= kTreeMaxSeg;
         const bool want_branch = ctx->per_lane[kFamTree][1] == 2;

@@ -20,7 +20,6 @@
 #include <vector>
 
 #include "api_internal.h"
-#include "sphere.h"
 
 using namespace swv;
 
@@ -51,7 +50,6 @@ struct swv_cycle_s {
     int vpl = 2, block = 64, grid_direct = 0, grid_tree = 0, walker = 0, depth = 1;
     int max_comp_cap = 0;
     int64_t tile_rows = 64, tree_tile = 64;   // rows per work item, fixed at creation
-    TreeArgs scales{};
     std::vector<AdjointShape> adj;          // per instance
     std::vector<int> gcpl;                  // per instance: gradient components per lane
     std::vector<int64_t> gchunk;            // per instance: gradient row chunk
@@ -174,8 +172,7 @@ hipError_t enqueue_cycle(swv_cycle cy, hipStream_t s) {
                             cy->d_items_direct, (unsigned)cy->items_direct.size(),
                             cy->d_counters, ctx->d_status);
     if (e != hipSuccess) return e;
-    e = launch_batch_tree(s, cy->walker, cy->depth, SWV_FP64, cy->grid_tree, cy->scales,
-                          cy->d_tree, cy->d_items_tree, (unsigned)cy->items_tree.size(),
+    e = launch_batch_tree(s, cy->walker, cy->depth, SWV_FP64, cy->grid_tree, cy->d_tree, cy->d_items_tree, (unsigned)cy->items_tree.size(),
                           cy->d_counters + 1, ctx->d_status);
     if (e != hipSuccess) return e;
     for (size_t k = 0; k < cy->spec.size(); ++k) {
@@ -270,8 +267,6 @@ int swv_cycle_create(swv_ctx ctx, int n, const swv_cycle_instance* inst, swv_cyc
         // largest J, else the branch walker at its deepest segment count
         cy->walker = jcap <= kTreeMaxJ ? 0 : 1;
         cy->depth = cy->walker == 0 ? jcap : kTreeMaxSeg;
-        for (int j = 0; j <= SWV_MAX_LEVEL; ++j) cy->scales.scale[j] = j >= 1 ? level_scale(j) : 0.0;
-        cy->scales.J = jcap;
         cy->grid_direct = ctx->n_cu * batch_direct_blocks_per_cu(cy->vpl, cy->block);
         cy->grid_tree = ctx->n_cu * batch_tree_blocks_per_cu(cy->walker, cy->depth, SWV_FP64);
         const int64_t waves = (int64_t)cy->grid_direct * (cy->block / 64);

@@ -91,13 +91,14 @@ __global__ __launch_bounds__(BLOCK) void k_batch_direct(const BatchInst* __restr
 // PREC: SWV_FP64 (complex128 out) or SWV_F32C (FP32 leaf phasors, complex64
 // out), exactly as the single-instance tree kernel writes them.
 template <int JMAX, int WALKER, int PREC, bool PRUNED = false>
-__global__ __launch_bounds__(kBatchTreeBlock) void k_batch_tree(
-    TreeArgs scales, const BatchInst* __restrict__ inst, const WorkItem* __restrict__ items,
+__global__ __launch_bounds__(kBatchTreeBlock)
+__attribute__((amdgpu_waves_per_eu(tree_waves_per_simd<JMAX, WALKER>()))) void k_batch_tree(
+    const BatchInst* __restrict__ inst, const WorkItem* __restrict__ items,
     unsigned n_items, unsigned* __restrict__ counter, int* __restrict__ status) {
     const int lane = threadIdx.x & 63;
     const auto* IT = uniform_ptr(items);
     const auto* IN = uniform_ptr(inst);
-    constexpr int LDSL = tree_lds_levels<JMAX, kBatchTreeBlock>();
+    constexpr int LDSL = tree_lds_levels<JMAX, WALKER, kBatchTreeBlock>();
     __shared__ double sums[LDSL > 0 ? LDSL * kSlotDoubles * kBatchTreeBlock : 1];
     for (;;) {
         const unsigned it = next_item(counter);
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(kBatchTreeBlock) void k_batch_tree(
             const double U = u[j], V = v[j], W = w[j];
             double Vr, Vi;
             tree_row<JMAX, WALKER, LDSL, kBatchTreeBlock, PREC == SWV_F32C, PRUNED>(
-                rec, n_roots, J, scales, (LdsPtr)sums, U, V, W, Vr, Vi);
+                rec, n_roots, J, (LdsPtr)sums, U, V, W, Vr, Vi);
             if (jr < limit) {
                 if (!isfinite(U + V + W)) atomicOr(status, kStatusNonFinite);
                 if constexpr (PREC == SWV_F32C)
@@ -197,7 +198,7 @@ hipError_t launch_batch_direct(hipStream_t s, int vpl, int block, int grid,
 }
 
 hipError_t launch_batch_tree(hipStream_t s, int walker, int depth, int prec, int grid,
-                             const TreeArgs& scales, const BatchInst* inst,
+                             const BatchInst* inst,
                              const WorkItem* items, unsigned n_items, unsigned* counter,
                              int* status, bool pruned) {
     if (n_items == 0) return hipSuccess;
@@ -205,20 +206,20 @@ hipError_t launch_batch_tree(hipStream_t s, int walker, int depth, int prec, int
     if (pruned) {
         if (walker != 1 || depth != kTreeMaxSeg) return hipErrorInvalidValue;
         if (prec == SWV_F32C)
-            k_batch_tree<kTreeMaxSeg, 1, SWV_F32C, true><<<g, b, 0, s>>>(scales, inst, items, n_items,
+            k_batch_tree<kTreeMaxSeg, 1, SWV_F32C, true><<<g, b, 0, s>>>(inst, items, n_items,
                                                                        counter, status);
         else
-            k_batch_tree<kTreeMaxSeg, 1, SWV_FP64, true><<<g, b, 0, s>>>(scales, inst, items, n_items,
+            k_batch_tree<kTreeMaxSeg, 1, SWV_FP64, true><<<g, b, 0, s>>>(inst, items, n_items,
                                                                        counter, status);
         return hipGetLastError();
     }
 #define SWV_RUN_T(D, W)                                                                    \
     if (walker == W && depth == D) {                                                       \
         if (prec == SWV_F32C)                                                              \
-            k_batch_tree<D, W, SWV_F32C><<<g, b, 0, s>>>(scales, inst, items, n_items,     \
+            k_batch_tree<D, W, SWV_F32C><<<g, b, 0, s>>>(inst, items, n_items,     \
                                                          counter, status);                 \
         else                                                                               \
-            k_batch_tree<D, W, SWV_FP64><<<g, b, 0, s>>>(scales, inst, items, n_items,     \
+            k_batch_tree<D, W, SWV_FP64><<<g, b, 0, s>>>(inst, items, n_items,     \
                                                          counter, status);                 \
         return hipGetLastError();                                                          \
     }

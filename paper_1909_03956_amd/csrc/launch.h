@@ -33,12 +33,10 @@ struct TreeArgs {
     int J;
     int seg_depth;                    // 1 + most branching nodes on a root-to-leaf path
     int pruned;                       // leaves above level J (coefficient thresholding)
-    double scale[SWV_MAX_LEVEL + 1];  // sqrt(A_j) / 4
 };
 
-// Largest J of the level walker (one register set per level); beyond it the
-// per-level state no longer fits two waves per SIMD and the branch walker is
-// the faster one.
+// Largest J of the level walker (one state set per level); beyond it the
+// branch walker, whose state follows the branching depth, is the faster one.
 constexpr int kTreeMaxJ = 10;
 // Largest segment depth of the branch walker (one register set per branching
 // node); it serves every J.
@@ -119,7 +117,7 @@ hipError_t launch_batch_direct(hipStream_t s, int vpl, int block, int grid,
 // tree holds leaves above level J; only the branch walker at depth kTreeMaxSeg
 // is compiled for that.
 hipError_t launch_batch_tree(hipStream_t s, int walker, int depth, int prec, int grid,
-                             const TreeArgs& scales, const BatchInst* inst, const WorkItem* items,
+                             const BatchInst* inst, const WorkItem* items,
                              unsigned n_items, unsigned* counter, int* status,
                              bool pruned = false);
 int batch_tree_pruned_blocks_per_cu(int prec);

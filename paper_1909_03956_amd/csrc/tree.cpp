@@ -30,13 +30,21 @@ namespace swv {
 // Eq. 10 sign pattern s^m_c (row m, column c).
 static const double kSign[3][4] = {{+1, -1, +1, -1}, {+1, +1, -1, -1}, {+1, -1, -1, +1}};
 
+// The factor a node record's coefficients carry for the traversal:
+// gamma^m_j sigma^m_j = gamma^m_j (sqrt(A_j)/4) sum_c s^m_c eta_{j+1,c}, and the
+// traversal hands up T_{j+1} = 4^(J-j-1) eta_{j+1}, so the record holds
+// g^m = gamma^m_j (sqrt(A_j)/4) 4^-(J-j-1) and the row's work for the node's
+// part of Eq. 17 is one product per coefficient.
+static double record_factor(int j, int J) { return std::ldexp(level_scale(j), -2 * (J - j - 1)); }
+
 static void emit(const swv_tree_s& t, int j, int64_t idx, std::vector<TRec>& out) {
     if (j == t.J) {
         out.push_back(TRec{t.leaf_l[idx], t.leaf_m[idx], t.leaf_nm1[idx], make_meta(0, j, 0)});
         return;
     }
     const TreeLevel& L = t.levels[j - 1];
-    out.push_back(TRec{L.gamma[3 * idx], L.gamma[3 * idx + 1], L.gamma[3 * idx + 2],
+    const double a = record_factor(j, t.J);
+    out.push_back(TRec{a * L.gamma[3 * idx], a * L.gamma[3 * idx + 1], a * L.gamma[3 * idx + 2],
                        make_meta((unsigned)L.mask[idx], j, L.chain[idx])});
     int64_t child = L.first_child[idx];
     for (int c = 0; c < 4; ++c)
@@ -82,9 +90,6 @@ void build_coefficients(swv_tree_s* t) {
             s = e;
         }
     }
-    // sqrt(A_j)/4; A_j = A_1 4^(1-j), so every level's factor is the level-1
-    // factor times an exact power of two (the device forms it that way too)
-    for (int j = 1; j <= SWV_MAX_LEVEL; ++j) t->level_scale[j] = level_scale(j);
 
     // one-child runs and branching depth, bottom-up
     std::vector<int> depth_below(nl, 0);   // branching nodes strictly below, per node
@@ -178,9 +183,10 @@ struct Pruner {
             return;
         }
         const int64_t f = off[j - 1] + 3 * idx;
-        out->records.push_back(TRec{keep[f] ? L.gamma[3 * idx] : 0.0,
-                                    keep[f + 1] ? L.gamma[3 * idx + 1] : 0.0,
-                                    keep[f + 2] ? L.gamma[3 * idx + 2] : 0.0,
+        const double a = record_factor(j, t.J);
+        out->records.push_back(TRec{keep[f] ? a * L.gamma[3 * idx] : 0.0,
+                                    keep[f + 1] ? a * L.gamma[3 * idx + 1] : 0.0,
+                                    keep[f + 2] ? a * L.gamma[3 * idx + 2] : 0.0,
                                     make_meta((unsigned)L.mask[idx], j, chain[j - 1][idx])});
         out->levels[j - 1].pix.push_back(L.pix[idx]);
         ++out->n_alive;
@@ -247,7 +253,6 @@ int prune_tree(const swv_tree_s& t, const std::vector<int64_t>& kept, swv_tree_s
     out->records.clear();
     out->leaf_pix.clear();
     out->n_alive = 0;
-    for (int j = 1; j <= SWV_MAX_LEVEL; ++j) out->level_scale[j] = level_scale(j);
     out->max_branching = 0;
     const TreeLevel& L1 = t.levels[0];
     const double A1 = pixel_area(1);

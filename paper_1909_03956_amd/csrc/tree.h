@@ -34,7 +34,6 @@ struct swv_tree_s {
     int64_t n_roots = 0;
     // most nodes with two or more children on one root-to-leaf path
     int max_branching = 0;
-    double level_scale[SWV_MAX_LEVEL + 1] = {};  // sqrt(A_j) / 4
     double build_seconds = 0;
     // device copies of `records`, one per HIP device id
     std::map<int, void*> device_records;

@@ -17,13 +17,17 @@
 // child returns, the node forms eta_j = S / 4 and sigma^m_j = sqrt(A_j)/4 D^m,
 // adds gamma^m_j sigma^m_j to V, and hands eta_j to its parent.  The level is
 // a template parameter, so each open level's sums live in their own
-// registers; one call site per level (inside a loop over the set bits of the
-// child mask) keeps the code linear in J.  Roots add A_1 lambda_1 eta_1.
-// Two exact rewritings cut the arithmetic without changing a bit (see
-// tree_walk.h): nodes hand up T_j = 4^(J-j) eta_j, the plain sum of the leaf
-// phasors below, with the quarters moved into the scale factors as powers of
-// two; and the level walker keeps D^m relative to a node's first child, which
-// then enters every sum without a sign product.
+// registers (the deepest levels; the ones above keep their finished children
+// in LDS or private-memory slots); one call site per level (inside a loop
+// over the set bits of the child mask) keeps the code linear in J.  Roots add
+// A_1 lambda_1 eta_1.
+// Three rewritings cut the arithmetic (see tree_walk.h): nodes hand up
+// T_j = 4^(J-j) eta_j, the plain sum of the leaf phasors below, with the
+// quarters moved into the node constants as exact powers of two; the level
+// walker keeps D^m relative to a node's first child, which then enters every
+// sum without a sign product (both exact); and a node's record carries
+// gamma^m_j times its constant sqrt(A_j)/4 4^-(J-j-1), multiplied once per
+// tree on the host, so gamma^m_j sigma^m_j costs one FMA per part per row.
 //
 // Deep trees are mostly runs of one-child nodes, so a second traversal (the
 // branch walker) keeps a register set only for open BRANCHING nodes: a run of
@@ -43,7 +47,8 @@ namespace swv {
 
 // PREC: SWV_FP64 (complex128 out) or SWV_F32C (FP32 leaf phasors, complex64 out).
 template <int JMAX, int BLOCK, int WALKER, int PREC, bool PRUNED = false>
-__global__ __launch_bounds__(BLOCK) void k_tree(TreeArgs ta, const double* __restrict__ u,
+__global__ __launch_bounds__(BLOCK)
+__attribute__((amdgpu_waves_per_eu(tree_waves_per_simd<JMAX, WALKER>()))) void k_tree(TreeArgs ta, const double* __restrict__ u,
                                                 const double* __restrict__ v,
                                                 const double* __restrict__ w, int64_t n_vis,
                                                 double sgn, void* __restrict__ out,
@@ -51,10 +56,10 @@ __global__ __launch_bounds__(BLOCK) void k_tree(TreeArgs ta, const double* __res
     const int64_t jrow = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int64_t j = jrow < n_vis ? jrow : n_vis - 1;
     const double U = u[j], V = v[j], W = w[j];
-    constexpr int LDSL = tree_lds_levels<JMAX, BLOCK>();
+    constexpr int LDSL = tree_lds_levels<JMAX, WALKER, BLOCK>();
     __shared__ double sums[LDSL > 0 ? LDSL * kSlotDoubles * BLOCK : 1];
     double Vr, Vi;
-    tree_row<JMAX, WALKER, LDSL, BLOCK, PREC == SWV_F32C, PRUNED>(ta.rec, ta.n_roots, ta.J, ta,
+    tree_row<JMAX, WALKER, LDSL, BLOCK, PREC == SWV_F32C, PRUNED>(ta.rec, ta.n_roots, ta.J,
                                                                   (LdsPtr)sums, U, V, W, Vr, Vi);
     if (jrow < n_vis) {
         if (!isfinite(U + V + W)) atomicOr(status, kStatusNonFinite);

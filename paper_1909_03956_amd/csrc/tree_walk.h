@@ -10,10 +10,28 @@ namespace swv {
 
 using RecPtr = const __attribute__((address_space(4))) TRec*;
 using LdsPtr = __attribute__((address_space(3))) double*;
+using PrivPtr = __attribute__((address_space(5))) double*;
 
-// Open levels (segments) whose running sums stay in registers; the ones above
-// them are kept in LDS (see slot_put).
+// Branch walker: the deepest six open segments keep their running sums in
+// registers, the ones above them keep their children in LDS (see slot_put).
 constexpr int kTreeRegLevels = 6;
+// Level walker, open levels 1 .. JMAX-1 (level JMAX holds the leaves): the
+// deepest level_reg_levels in registers, the level_lds_levels above them in
+// LDS, the rest in private memory, compiled for level_waves waves per SIMD (1:
+// left to the compiler).  Chosen by measurement at cfg2 (one MI355X, median
+// of nine launches; before: one register set for each of the deepest four to
+// six levels, the rest in LDS, three waves: J = 10 8.67, J = 9 3.62, J = 8
+// 1.35 ms):
+//   J = 10: 2 register + 2 LDS levels, 5 waves (96 VGPRs)  7.13 ms
+//           (3 + 2 at 5 waves 7.43; 3 + 3 at 4 waves 7.56; all but 3 LDS
+//           levels in registers, compiler spills, 4 waves 8.00; 6 waves 7.5-14)
+//   J = 8, 9: 3 + 3 levels, 4 waves (126 VGPRs)           1.25, 3.25 ms
+template <int JMAX>
+constexpr int level_reg_levels() { return JMAX >= 10 ? 2 : 3; }
+template <int JMAX>
+constexpr int level_lds_levels() { return JMAX >= 10 ? 2 : 3; }
+template <int JMAX>
+constexpr int level_waves() { return JMAX >= 10 ? 5 : (JMAX >= 8 ? 4 : 1); }
 
 // Running sums of an open node at level j over its finished children, whose
 // values are T_{j+1,c} = 4^(J-j-1) eta_{j+1,c} (the plain sums of the leaf
@@ -21,9 +39,9 @@ constexpr int kTreeRegLevels = 6;
 // first child c0:
 //   S = sum_c T_{j+1,c},   D^m = s^m_{c0} sum_c s^m_c T_{j+1,c}   (m = 0, 1, 2),
 // so the first child's value enters every sum as it is, and the sign
-// s^m_{c0} moves to the node's scale factor when it closes.  With s = +-1 and
+// s^m_{c0} moves to the node's coefficient when it closes.  With s = +-1 and
 // rounding symmetric in sign, each value is the plain sum times s^m_{c0}
-// exactly, so sigma comes out the same bit for bit.  (The branch walker
+// exactly, so the result comes out the same bit for bit.  (The branch walker
 // passes c0 = 0 and starts its sums at zero.)
 struct NodeSums {
     double Sr, Si, D0r, D0i, D1r, D1i, D2r, D2i;
@@ -37,8 +55,8 @@ __device__ __forceinline__ double sign2(int c) { return ((c ^ (c >> 1)) & 1) ? -
 
 // Takes child c's value x = T_{j+1,c} into the sums of a node whose first
 // child is c0: the first child sets them all to x, later ones add with the
-// signs of c ^ c0.  `first` is the same for every lane, so this is
-// a scalar branch, and no sums need zeroing.
+// signs of c ^ c0.  `first` is the same for every lane, so this is a scalar
+// branch, and no sums need zeroing.
 __device__ __forceinline__ void add_child(NodeSums& n, int c, int c0, double xr, double xi,
                                           bool first) {
     if (first) {
@@ -58,74 +76,108 @@ __device__ __forceinline__ void add_child(NodeSums& n, int c, int c0, double xr,
     }
 }
 
-// Closes a node at level j whose first child is c0 (g = gamma^m_j): its sum
-// T_j goes to the parent, sigma^m_j = s^m_{c0} a D^m (Eq. 10 on the plane
-// wave) is formed with a = (sqrt(A_j)/4) 4^-(J-j-1) (the children's sums are
-// T_{j+1} = 4^(J-j-1) eta_{j+1}) and gamma^m_j sigma^m_j added to V (Eq. 17).
+// Closes a node at level j whose first child is c0.  The record carries the
+// node's coefficients already multiplied by its scale,
+//   g^m = gamma^m_j a,   a = (sqrt(A_j)/4) 4^-(J-j-1),
+// so gamma^m_j sigma^m_j (Eq. 10 on the plane wave, then Eq. 17) is
+// g^m s^m_{c0} D^m, one FMA per part: sigma^m_j = sqrt(A_j)/4 sum_c s^m_c
+// eta_{j+1,c} and the children's sums are T_{j+1} = 4^(J-j-1) eta_{j+1}.
 // Passing T_j = sum over the leaves below of eta_J instead of eta_j = T_j /
-// 4^(J-j) (Eq. 9 on the plane wave) moves every quarter into the scale
-// factors as exact powers of two: the same sigma bit for bit, two fewer
-// products per node.
-__device__ __forceinline__ void close_node(const NodeSums& n, int c0, double a, double g0,
-                                           double g1, double g2, double& er, double& ei,
-                                           double& Vr, double& Vi) {
+// 4^(J-j) (Eq. 9 on the plane wave) keeps every quarter out of the per-row
+// work.  T_j goes to the parent.
+__device__ __forceinline__ void close_node(const NodeSums& n, int c0, double g0, double g1,
+                                           double g2, double& er, double& ei, double& Vr,
+                                           double& Vi) {
     // sign choices on a wave-uniform value: scalar selects, no arithmetic
-    const double a0 = (c0 & 1) ? -a : a;
-    const double a1 = (c0 & 2) ? -a : a;
-    const double a2 = ((c0 ^ (c0 >> 1)) & 1) ? -a : a;
+    const double h0 = (c0 & 1) ? -g0 : g0;
+    const double h1 = (c0 & 2) ? -g1 : g1;
+    const double h2 = ((c0 ^ (c0 >> 1)) & 1) ? -g2 : g2;
     er = n.Sr;
     ei = n.Si;
-    const double s0r = a0 * n.D0r, s0i = a0 * n.D0i;
-    const double s1r = a1 * n.D1r, s1i = a1 * n.D1i;
-    const double s2r = a2 * n.D2r, s2i = a2 * n.D2i;
-    Vr = fma(g0, s0r, Vr);
-    Vi = fma(g0, s0i, Vi);
-    Vr = fma(g1, s1r, Vr);
-    Vi = fma(g1, s1i, Vi);
-    Vr = fma(g2, s2r, Vr);
-    Vi = fma(g2, s2i, Vi);
+    Vr = fma(h0, n.D0r, Vr);
+    Vi = fma(h0, n.D0i, Vi);
+    Vr = fma(h1, n.D1r, Vr);
+    Vi = fma(h1, n.D1i, Vi);
+    Vr = fma(h2, n.D2r, Vr);
+    Vi = fma(h2, n.D2i, Vi);
 }
 
-// Open nodes of the top LDSL levels (level walker) or segments (branch
-// walker) keep their children's plane-wave coefficients in LDS rather than
-// running sums in registers: such a node is touched only when one of its few
-// children finishes, and its registers would otherwise stay allocated through
-// every subtree below it, which limits how many waves share a SIMD.  A node
+// Adds gamma^m_j sigma^m_j of a node whose only child c returned the sum x
+// (T_j = x): close_node's arithmetic with c0 = c and D^m = x.
+__device__ __forceinline__ void close_single(int c, double g0, double g1, double g2, double xr,
+                                             double xi, double& Vr, double& Vi) {
+    const double h0 = (c & 1) ? -g0 : g0;
+    const double h1 = (c & 2) ? -g1 : g1;
+    const double h2 = ((c ^ (c >> 1)) & 1) ? -g2 : g2;
+    Vr = fma(h0, xr, Vr);
+    Vi = fma(h0, xi, Vi);
+    Vr = fma(h1, xr, Vr);
+    Vi = fma(h1, xi, Vi);
+    Vr = fma(h2, xr, Vr);
+    Vi = fma(h2, xi, Vi);
+}
+
+// Open nodes above the register levels (level walker) or segments (branch
+// walker) keep their children's plane-wave coefficients in a slot (LDS, or
+// for the level walker's topmost levels the lane's private memory) rather
+// than running sums in registers: such a node is touched only when one of its
+// few children finishes, and its registers would otherwise stay allocated
+// through every subtree below it, which limits how many waves share a SIMD.  A node
 // holds at most three finished children while its last one is walked, so a
 // slot is three complex values (6 doubles, against 8 for the four running
 // sums); the sums are formed when the last child is back, in child order, so
 // they equal the register levels' bit for bit.  Layout [slot][6][BLOCK]:
-// lane-contiguous, so the accesses are free of bank conflicts.
-// The accesses are volatile: otherwise the compiler, seeing the whole inlined
-// walk, forwards each stored value to its reload and keeps it in registers.
+// lane-contiguous, so the accesses are free of bank conflicts; private
+// slots are [slot][6] per lane.  The accesses are volatile: otherwise the
+// compiler, seeing the whole inlined walk, forwards each stored value to its
+// reload and keeps it in registers.
 constexpr int kSlotDoubles = 6;
 
-template <int BLOCK>
-__device__ __forceinline__ void slot_put(LdsPtr lds, int slot, int k, double xr, double xi) {
-    volatile __attribute__((address_space(3))) double* p =
-        lds + (slot * kSlotDoubles + 2 * k) * BLOCK + threadIdx.x;
-    p[0] = xr;
-    p[BLOCK] = xi;
+//
+// Private slots hold the level walker's topmost levels, whose slots are
+// touched least (once per child of a node there: at cfg2 J = 10 levels 1-5
+// take 22 values per row, levels 6-7 117, levels 8-9 804).
+template <int BLOCK, bool PRIV>
+__device__ __forceinline__ void slot_put(LdsPtr lds, PrivPtr priv, int slot, int k, double xr,
+                                         double xi) {
+    if constexpr (PRIV) {
+        volatile __attribute__((address_space(5))) double* p = priv + slot * kSlotDoubles + 2 * k;
+        p[0] = xr;
+        p[1] = xi;
+    } else {
+        volatile __attribute__((address_space(3))) double* p =
+            lds + (slot * kSlotDoubles + 2 * k) * BLOCK + threadIdx.x;
+        p[0] = xr;
+        p[BLOCK] = xi;
+    }
 }
 
-template <int BLOCK>
-__device__ __forceinline__ void slot_get(LdsPtr lds, int slot, int k, double& xr, double& xi) {
-    const volatile __attribute__((address_space(3))) double* p =
-        lds + (slot * kSlotDoubles + 2 * k) * BLOCK + threadIdx.x;
-    xr = p[0];
-    xi = p[BLOCK];
+template <int BLOCK, bool PRIV>
+__device__ __forceinline__ void slot_get(LdsPtr lds, PrivPtr priv, int slot, int k, double& xr,
+                                         double& xi) {
+    if constexpr (PRIV) {
+        const volatile __attribute__((address_space(5))) double* p =
+            priv + slot * kSlotDoubles + 2 * k;
+        xr = p[0];
+        xi = p[1];
+    } else {
+        const volatile __attribute__((address_space(3))) double* p =
+            lds + (slot * kSlotDoubles + 2 * k) * BLOCK + threadIdx.x;
+        xr = p[0];
+        xi = p[BLOCK];
+    }
 }
 
 // Adds the k children kept in a slot to n, in child order, relative to
 // child c0; `all` is the node's child mask, whose k lowest set bits name them.
-template <int BLOCK>
-__device__ __forceinline__ void slot_replay(LdsPtr lds, int slot, int k, unsigned all, int c0,
-                                            NodeSums& n, bool& first) {
+template <int BLOCK, bool PRIV>
+__device__ __forceinline__ void slot_replay(LdsPtr lds, PrivPtr priv, int slot, int k,
+                                            unsigned all, int c0, NodeSums& n, bool& first) {
     for (int q = 0; q < k; ++q) {
         const int c = __builtin_ctz(all);
         all &= all - 1;
         double xr, xi;
-        slot_get<BLOCK>(lds, slot, q, xr, xi);
+        slot_get<BLOCK, PRIV>(lds, priv, slot, q, xr, xi);
         add_child(n, c, c0, xr, xi, first);
         first = false;
     }
@@ -136,34 +188,6 @@ __device__ __forceinline__ void slot_replay(LdsPtr lds, int slot, int k, unsigne
 // operands.
 __device__ __forceinline__ double pow2_scale(double a, int e) {
     return __longlong_as_double(__double_as_longlong(a) + ((long long)e << 52));
-}
-
-// The scale a of close_node at level j of a depth-J tree:
-// (sqrt(A_j)/4) 4^-(J-j-1) = (sqrt(A_1)/4) 2^(j+3-2J), from the level-1 factor
-// the host stores (sqrt(A_j)/4 halves from level to level) with no load that
-// waits on the record.
-__device__ __forceinline__ double level_factor(const TreeArgs& ta, int j, int J) {
-    return pow2_scale(ta.scale[1], j + 3 - 2 * J);
-}
-
-// Closes a node whose only child c returned its sum x: T_j = x and
-// sigma^m_j = (s^m_c a) x -- close_node after add_child with c0 = c, the
-// same operations -- then gamma^m_j sigma^m_j is added to V.
-__device__ __forceinline__ void close_single(int c, double a, double g0, double g1, double g2,
-                                             double& er, double& ei, double& Vr, double& Vi) {
-    const double xr = er, xi = ei;
-    const double a0 = (c & 1) ? -a : a;
-    const double a1 = (c & 2) ? -a : a;
-    const double a2 = ((c ^ (c >> 1)) & 1) ? -a : a;
-    const double s0r = a0 * xr, s0i = a0 * xi;
-    const double s1r = a1 * xr, s1i = a1 * xi;
-    const double s2r = a2 * xr, s2i = a2 * xi;
-    Vr = fma(g0, s0r, Vr);
-    Vi = fma(g0, s0i, Vi);
-    Vr = fma(g1, s1r, Vr);
-    Vi = fma(g1, s1i, Vi);
-    Vr = fma(g2, s2r, Vr);
-    Vi = fma(g2, s2i, Vi);
 }
 
 // Leaf: eta_{J,k} = exp(2 pi i B . (s_k - P)) (imaginary part / 4).  VOP3
@@ -205,11 +229,12 @@ __device__ __forceinline__ void leaf_above(RecPtr rec, int me, int j, int J, dou
 }
 
 // Level walker: one register set per level, the level a template parameter
-// (levels <= LDSL keep theirs in LDS).
-template <int LVL, int JMAX, int LDSL, int BLOCK, bool F32, bool PRUNED>
-__device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const TreeArgs& ta,
-                                     LdsPtr lds, const double u, const double v, const double w,
-                                     double& er, double& ei, double& Vr, double& Vi) {
+// (levels <= PRIVL keep theirs in private memory, the next LDSL in LDS).
+template <int LVL, int JMAX, int LDSL, int PRIVL, int BLOCK, bool F32, bool PRUNED>
+__device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, LdsPtr lds,
+                                     PrivPtr priv, const double u, const double v,
+                                     const double w, double& er, double& ei, double& Vr,
+                                     double& Vi) {
     const int me = pos++;
     if (LVL == JMAX || LVL == J) {
         leaf_wave<true, F32>(rec, me, u, v, w, er, ei);
@@ -227,33 +252,34 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const Tr
         unsigned mask = all;
         NodeSums n;
         bool first = true;
-        if constexpr (LVL <= LDSL) {
+        if constexpr (LVL <= PRIVL + LDSL) {
             // every child but the last waits in the slot (stored when the
             // next one starts); only the last one's value leaves the loop
+            constexpr bool PRIV = LVL <= PRIVL;
+            constexpr int SLOT = PRIV ? LVL - 1 : LVL - PRIVL - 1;
             int k = 0, c = 0;
             double xr = 0.0, xi = 0.0;
             while (mask) {
-                if (mask != all) slot_put<BLOCK>(lds, LVL - 1, k++, xr, xi);
+                if (mask != all) slot_put<BLOCK, PRIV>(lds, priv, SLOT, k++, xr, xi);
                 c = __builtin_ctz(mask);
                 mask &= mask - 1;
-                walk<LVL + 1, JMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr,
-                                                      Vi);
+                walk<LVL + 1, JMAX, LDSL, PRIVL, BLOCK, F32, PRUNED>(rec, pos, J, lds, priv, u, v,
+                                                                     w, xr, xi, Vr, Vi);
             }
-            slot_replay<BLOCK>(lds, LVL - 1, k, all, c0, n, first);
+            slot_replay<BLOCK, PRIV>(lds, priv, SLOT, k, all, c0, n, first);
             add_child(n, c, c0, xr, xi, first);
         } else {
             while (mask) {
                 const int c = __builtin_ctz(mask);
                 mask &= mask - 1;
                 double xr, xi;
-                walk<LVL + 1, JMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, ta, lds, u, v, w, xr, xi, Vr,
-                                                      Vi);
+                walk<LVL + 1, JMAX, LDSL, PRIVL, BLOCK, F32, PRUNED>(rec, pos, J, lds, priv, u, v,
+                                                                     w, xr, xi, Vr, Vi);
                 add_child(n, c, c0, xr, xi, first);
                 first = false;
             }
         }
-        close_node(n, c0, level_factor(ta, LVL, J), rec[me].a, rec[me].b, rec[me].c, er, ei,
-                   Vr, Vi);
+        close_node(n, c0, rec[me].a, rec[me].b, rec[me].c, er, ei, Vr, Vi);
     }
 }
 
@@ -264,10 +290,9 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, const Tr
 // one-child node gets in the level walker.  D counts segments from the root;
 // the host launches DMAX >= 1 + the tree's largest branching count on a path.
 template <int D, int DMAX, int LDSL, int BLOCK, bool F32, bool PRUNED>
-__device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, const TreeArgs& ta,
-                                         LdsPtr lds, const double u, const double v,
-                                         const double w, double& er, double& ei, double& Vr,
-                                         double& Vi) {
+__device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, LdsPtr lds,
+                                         const double u, const double v, const double w,
+                                         double& er, double& ei, double& Vr, double& Vi) {
     const int first = pos;
     const int run = meta_chain(rec[first].meta);
     const int term = first + run;
@@ -296,44 +321,64 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, cons
                 int k = 0, c = 0;
                 double xr = 0.0, xi = 0.0;
                 while (mask) {
-                    if (mask != all) slot_put<BLOCK>(lds, D - 1, k++, xr, xi);
+                    if (mask != all) slot_put<BLOCK, false>(lds, nullptr, D - 1, k++, xr, xi);
                     c = __builtin_ctz(mask);
                     mask &= mask - 1;
-                    seg_walk<D + 1, DMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, ta, lds, u, v, w, xr,
-                                                            xi, Vr, Vi);
+                    seg_walk<D + 1, DMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, lds, u, v, w, xr,
+                                                                    xi, Vr, Vi);
                 }
-                slot_replay<BLOCK>(lds, D - 1, k, all, 0, n, first);
+                slot_replay<BLOCK, false>(lds, nullptr, D - 1, k, all, 0, n, first);
                 add_child(n, c, 0, xr, xi, false);
             } else {
                 while (mask) {
                     const int c = __builtin_ctz(mask);
                     mask &= mask - 1;
                     double xr, xi;
-                    seg_walk<D + 1, DMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, ta, lds, u, v, w, xr,
-                                                            xi, Vr, Vi);
+                    seg_walk<D + 1, DMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, lds, u, v, w, xr,
+                                                                    xi, Vr, Vi);
                     add_child(n, c, 0, xr, xi, false);
                 }
             }
-            close_node(n, 0, level_factor(ta, meta_level(mt), J), rec[term].a, rec[term].b,
-                       rec[term].c, er, ei, Vr, Vi);
+            close_node(n, 0, rec[term].a, rec[term].b, rec[term].c, er, ei, Vr, Vi);
         }
     }
     // the run, bottom-up
     for (int i = run - 1; i >= 0; --i) {
         const int me = first + i;
-        const unsigned long long mm = rec[me].meta;
-        close_single(__builtin_ctz(meta_mask(mm)), level_factor(ta, meta_level(mm), J), rec[me].a,
-                     rec[me].b, rec[me].c, er, ei, Vr, Vi);
+        close_single(__builtin_ctz(meta_mask(rec[me].meta)), rec[me].a, rec[me].b, rec[me].c, er,
+                     ei, Vr, Vi);
     }
 }
 
-// Levels (segments) of a traversal compiled to depth JMAX whose sums go to
-// LDS: all but the deepest kTreeRegLevels, within 64 KB per block.
-template <int JMAX, int BLOCK>
+// Levels (segments) of a traversal compiled to depth JMAX whose children go
+// to LDS: for the level walker the level_lds_levels above its register levels,
+// for the branch walker all segments above the deepest kTreeRegLevels within
+// 64 KB per block.
+template <int JMAX, int WALKER, int BLOCK>
 constexpr int tree_lds_levels() {
-    constexpr int want = JMAX > kTreeRegLevels ? JMAX - kTreeRegLevels : 0;
-    constexpr int cap = (64 * 1024) / (kSlotDoubles * 8 * BLOCK);
-    return want < cap ? want : cap;
+    if constexpr (WALKER == 0) {
+        constexpr int above = JMAX - 1 - level_reg_levels<JMAX>();
+        constexpr int cap = level_lds_levels<JMAX>();
+        return above <= 0 ? 0 : (above < cap ? above : cap);
+    } else {
+        constexpr int want = JMAX > kTreeRegLevels ? JMAX - kTreeRegLevels : 0;
+        constexpr int cap = (64 * 1024) / (kSlotDoubles * 8 * BLOCK);
+        return want < cap ? want : cap;
+    }
+}
+
+// Top levels of the level walker whose children go to private memory.
+template <int JMAX, int WALKER>
+constexpr int tree_priv_levels() {
+    constexpr int above = JMAX - 1 - level_reg_levels<JMAX>() - level_lds_levels<JMAX>();
+    return WALKER != 0 || above <= 0 ? 0 : above;
+}
+
+// Waves per SIMD a traversal is compiled for (the kernels' amdgpu_waves_per_eu):
+// the level walker's level_waves; the branch walker is left to the compiler.
+template <int JMAX, int WALKER>
+constexpr int tree_waves_per_simd() {
+    return WALKER != 0 ? 1 : level_waves<JMAX>();
 }
 
 // V (real, imaginary / 4) of one row: the root loop of the traversal.
@@ -341,10 +386,12 @@ constexpr int tree_lds_levels() {
 // lds: the block's [LDSL][6][BLOCK] child slots.  F32: FP32 phasors at the leaves.
 // PRUNED: the tree may hold leaves above level J (coefficient thresholding).
 template <int JMAX, int WALKER, int LDSL, int BLOCK, bool F32 = false, bool PRUNED = false>
-__device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J,
-                                         const TreeArgs& ta, LdsPtr lds, double U, double V,
-                                         double W, double& Vr, double& Vi) {
+__device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J, LdsPtr lds,
+                                         double U, double V, double W, double& Vr, double& Vi) {
     const RecPtr rec = uniform_ptr(recs);
+    constexpr int PRIVL = tree_priv_levels<JMAX, WALKER>();
+    double slots[PRIVL > 0 ? PRIVL * kSlotDoubles : 1];
+    const PrivPtr priv = (PrivPtr)slots;
     Vr = 0.0;
     Vi = 0.0;
     int pos = 0;
@@ -352,10 +399,10 @@ __device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J,
         const int root = pos++;
         double er, ei;
         if constexpr (WALKER == 0)
-            walk<1, JMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, ta, lds, U, V, W, er, ei, Vr, Vi);
+            walk<1, JMAX, LDSL, PRIVL, BLOCK, F32, PRUNED>(rec, pos, J, lds, priv, U, V, W, er, ei,
+                                                           Vr, Vi);
         else
-            seg_walk<1, JMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, ta, lds, U, V, W, er, ei, Vr,
-                                                         Vi);
+            seg_walk<1, JMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, lds, U, V, W, er, ei, Vr, Vi);
         // A_1 lambda_1 eta_1 with eta_1 = T_1 / 4^(J-1); ldexp, as A_1 lambda_1
         // may be zero
         const double A1lam = ldexp(rec[root].a, -2 * (J - 1));
