@@ -303,6 +303,20 @@ def traffic_for(kernel_file: str, per_launch_key: str, path: str | None = None,
     return rec.get("bytes_per_launch")
 
 
+def valu_count_for(kernel_file: str, key: str, path: str | None = None,
+                   csrc: str | None = None):
+    """VALU wave instructions per launch from the committed counter summary,
+    or None if the kernel source changed since the counters were taken."""
+    path = path or os.path.join(ROOT, "profiles", "valu_issue.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(key)
+    if not rec or rec.get("source_sha") != source_digest(kernel_file, csrc):
+        return None
+    return rec.get("valu_wave_instructions")
+
+
 def run_sweep():
     """Time per visibility of the tree route (host build excluded, reported
     apart) against J and against the number of distinct components, the two
@@ -1036,6 +1050,15 @@ def main():
         routes[s]["fp64_alu_frac_excl_phasor"] = round(
             (flops[s] - PHASOR_FLOPS * phasors[s]) / (med[s] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)
     roofline["frac_excl_phasor"] = routes[dom]["fp64_alu_frac_excl_phasor"]
+    # counter-based VALU issue: the kernel's VALU instructions (rocprofv3 SQ
+    # counters, per launch) at 64 lanes each over the live launch time, against
+    # the FP64 FMA lane rate measured on this part
+    lane_rate = peaks["fp64_fma_tflops"] / 2 * 1e12
+    for s in flops:
+        nv = valu_count_for(*kernel_of[s])
+        if nv:
+            routes[s]["valu_issue_frac"] = round(64 * nv / (med[s] * 1e-3) / lane_rate, 4)
+    roofline["valu_issue_frac"] = routes[dom].get("valu_issue_frac")
     routes["direct_f32c"]["roofline"] = dict(
         f32c_roofline("direct_f32c", n_vis * n_comp / (med["direct_f32c"] * 1e-3), peaks),
         kernel="k_direct_f32c")

@@ -64,6 +64,27 @@ def test_committed_traffic_record_names_every_kernel():
         assert rec[key]["bytes_per_launch"] > 0 and len(rec[key]["source_sha"]) == 16
 
 
+def test_valu_count_is_null_once_the_source_changes(tmp_path):
+    d = _tree(tmp_path, {"k.hip": '#include "a.h"\n', "a.h": "x\n"})
+    rec = tmp_path / "valu.json"
+    rec.write_text(json.dumps({"k_x": {"valu_wave_instructions": 4.5e9,
+                                       "source_sha": bench.source_digest("k.hip", d)}}))
+    assert bench.valu_count_for("k.hip", "k_x", str(rec), d) == 4.5e9
+    assert bench.valu_count_for("k.hip", "k_missing", str(rec), d) is None
+    (tmp_path / "a.h").write_text("x changed\n")
+    assert bench.valu_count_for("k.hip", "k_x", str(rec), d) is None
+
+
+def test_committed_valu_record_classes_add_up():
+    with open(os.path.join(ROOT, "profiles", "valu_issue.json")) as fh:
+        rec = json.load(fh)
+    for key in ("k_direct_f64", "k_tree_J10", "k_adjoint", "k_grad_partial", "k_direct_f32c"):
+        r = rec[key]
+        parts = sum(r[c] for c in ("f64", "f32", "trans_f32", "cvt", "int32", "int64", "other"))
+        assert abs(parts - r["valu_wave_instructions"]) <= 1e-6 * r["valu_wave_instructions"]
+        assert len(r["source_sha"]) == 16
+
+
 def test_cpu_baseline_record_on_a_small_sample():
     b = bench.cpu_baseline(64)
     assert b["kind"] == "oracle" and b["unit"] == bench.UNIT
