@@ -16,8 +16,9 @@ struct alignas(32) Comp {
 
 // One record of the depth-first tree stream (32 bytes).
 //   root : a = A_1 * lambda_1 of the level-1 node that follows; meta = 0
-//   node : a, b, c = g^0, g^1, g^2 with g^m = gamma^m_j (sqrt(A_j)/4) 4^-(J-j-1)
-//          (a thresholded tree: 0 for a coefficient that is not kept)
+//   node : a, b, c = h^0, h^1, h^2 with h^m = s^m_{c0} gamma^m_j (sqrt(A_j)/4) 4^-(J-j-1),
+//          c0 the node's first child, s the Eq. 10 signs (a thresholded tree:
+//          0 for a coefficient that is not kept)
 //   leaf : a, b, c = l, m, n - 1 of the pixel centre
 // meta of nodes and leaves:
 //   bits 0-3   child mask (bit c set if child 4k + c exists; 0 for a leaf)

@@ -32,10 +32,17 @@ static const double kSign[3][4] = {{+1, -1, +1, -1}, {+1, +1, -1, -1}, {+1, -1, 
 
 // The factor a node record's coefficients carry for the traversal:
 // gamma^m_j sigma^m_j = gamma^m_j (sqrt(A_j)/4) sum_c s^m_c eta_{j+1,c}, and the
-// traversal hands up T_{j+1} = 4^(J-j-1) eta_{j+1}, so the record holds
-// g^m = gamma^m_j (sqrt(A_j)/4) 4^-(J-j-1) and the row's work for the node's
-// part of Eq. 17 is one product per coefficient.
+// traversal hands up T_{j+1} = 4^(J-j-1) eta_{j+1} and forms the sums relative
+// to the node's first child c0 (times s^m_{c0}), so the record holds
+// h^m = s^m_{c0} gamma^m_j (sqrt(A_j)/4) 4^-(J-j-1) and the row's work for the
+// node's part of Eq. 17 is one product per coefficient.
 static double record_factor(int j, int J) { return std::ldexp(level_scale(j), -2 * (J - j - 1)); }
+
+static void record_coefficients(double a, unsigned mask, const double* gamma, const bool* keep,
+                                double* h) {
+    const int c0 = mask ? __builtin_ctz(mask) : 0;
+    for (int m = 0; m < 3; ++m) h[m] = keep[m] ? kSign[m][c0] * (a * gamma[m]) : 0.0;
+}
 
 static void emit(const swv_tree_s& t, int j, int64_t idx, std::vector<TRec>& out) {
     if (j == t.J) {
@@ -43,9 +50,10 @@ static void emit(const swv_tree_s& t, int j, int64_t idx, std::vector<TRec>& out
         return;
     }
     const TreeLevel& L = t.levels[j - 1];
-    const double a = record_factor(j, t.J);
-    out.push_back(TRec{a * L.gamma[3 * idx], a * L.gamma[3 * idx + 1], a * L.gamma[3 * idx + 2],
-                       make_meta((unsigned)L.mask[idx], j, L.chain[idx])});
+    const bool all[3] = {true, true, true};
+    double h[3];
+    record_coefficients(record_factor(j, t.J), (unsigned)L.mask[idx], &L.gamma[3 * idx], all, h);
+    out.push_back(TRec{h[0], h[1], h[2], make_meta((unsigned)L.mask[idx], j, L.chain[idx])});
     int64_t child = L.first_child[idx];
     for (int c = 0; c < 4; ++c)
         if (L.mask[idx] & (1 << c)) emit(t, j + 1, child++, out);
@@ -183,11 +191,12 @@ struct Pruner {
             return;
         }
         const int64_t f = off[j - 1] + 3 * idx;
-        const double a = record_factor(j, t.J);
-        out->records.push_back(TRec{keep[f] ? a * L.gamma[3 * idx] : 0.0,
-                                    keep[f + 1] ? a * L.gamma[3 * idx + 1] : 0.0,
-                                    keep[f + 2] ? a * L.gamma[3 * idx + 2] : 0.0,
-                                    make_meta((unsigned)L.mask[idx], j, chain[j - 1][idx])});
+        const bool kept3[3] = {keep[f] != 0, keep[f + 1] != 0, keep[f + 2] != 0};
+        double h[3];
+        record_coefficients(record_factor(j, t.J), (unsigned)L.mask[idx], &L.gamma[3 * idx], kept3,
+                            h);
+        out->records.push_back(
+            TRec{h[0], h[1], h[2], make_meta((unsigned)L.mask[idx], j, chain[j - 1][idx])});
         out->levels[j - 1].pix.push_back(L.pix[idx]);
         ++out->n_alive;
         int64_t child = L.first_child[idx];

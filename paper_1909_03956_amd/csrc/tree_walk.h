@@ -39,10 +39,10 @@ constexpr int level_waves() { return JMAX >= 10 ? 5 : (JMAX >= 8 ? 4 : 1); }
 // first child c0:
 //   S = sum_c T_{j+1,c},   D^m = s^m_{c0} sum_c s^m_c T_{j+1,c}   (m = 0, 1, 2),
 // so the first child's value enters every sum as it is, and the sign
-// s^m_{c0} moves to the node's coefficient when it closes.  With s = +-1 and
-// rounding symmetric in sign, each value is the plain sum times s^m_{c0}
-// exactly, so the result comes out the same bit for bit.  (The branch walker
-// passes c0 = 0 and starts its sums at zero.)
+// s^m_{c0} sits in the node's coefficient, which the host stores multiplied
+// by it.  With s = +-1 and rounding symmetric in sign, each value is the
+// plain sum times s^m_{c0} exactly, so the result comes out the same bit for
+// bit.  (The branch walker starts its sums at zero.)
 struct NodeSums {
     double Sr, Si, D0r, D0i, D1r, D1i, D2r, D2i;
 };
@@ -76,22 +76,17 @@ __device__ __forceinline__ void add_child(NodeSums& n, int c, int c0, double xr,
     }
 }
 
-// Closes a node at level j whose first child is c0.  The record carries the
-// node's coefficients already multiplied by its scale,
-//   g^m = gamma^m_j a,   a = (sqrt(A_j)/4) 4^-(J-j-1),
-// so gamma^m_j sigma^m_j (Eq. 10 on the plane wave, then Eq. 17) is
-// g^m s^m_{c0} D^m, one FMA per part: sigma^m_j = sqrt(A_j)/4 sum_c s^m_c
-// eta_{j+1,c} and the children's sums are T_{j+1} = 4^(J-j-1) eta_{j+1}.
-// Passing T_j = sum over the leaves below of eta_J instead of eta_j = T_j /
-// 4^(J-j) (Eq. 9 on the plane wave) keeps every quarter out of the per-row
-// work.  T_j goes to the parent.
-__device__ __forceinline__ void close_node(const NodeSums& n, int c0, double g0, double g1,
-                                           double g2, double& er, double& ei, double& Vr,
-                                           double& Vi) {
-    // sign choices on a wave-uniform value: scalar selects, no arithmetic
-    const double h0 = (c0 & 1) ? -g0 : g0;
-    const double h1 = (c0 & 2) ? -g1 : g1;
-    const double h2 = ((c0 ^ (c0 >> 1)) & 1) ? -g2 : g2;
+// Closes a node at level j.  The record carries the node's coefficients
+// already multiplied by its scale and by the signs of its first child c0,
+//   h^m = s^m_{c0} gamma^m_j a,   a = (sqrt(A_j)/4) 4^-(J-j-1),
+// so gamma^m_j sigma^m_j (Eq. 10 on the plane wave, then Eq. 17) is h^m D^m
+// with the sums relative to c0, one FMA per part and no per-row sign work:
+// sigma^m_j = sqrt(A_j)/4 sum_c s^m_c eta_{j+1,c} and the children's sums are
+// T_{j+1} = 4^(J-j-1) eta_{j+1}.  Passing T_j = sum over the leaves below of
+// eta_J instead of eta_j = T_j / 4^(J-j) (Eq. 9 on the plane wave) keeps every
+// quarter out of the per-row work.  T_j goes to the parent.
+__device__ __forceinline__ void close_node(const NodeSums& n, double h0, double h1, double h2,
+                                           double& er, double& ei, double& Vr, double& Vi) {
     er = n.Sr;
     ei = n.Si;
     Vr = fma(h0, n.D0r, Vr);
@@ -102,13 +97,10 @@ __device__ __forceinline__ void close_node(const NodeSums& n, int c0, double g0,
     Vi = fma(h2, n.D2i, Vi);
 }
 
-// Adds gamma^m_j sigma^m_j of a node whose only child c returned the sum x
-// (T_j = x): close_node's arithmetic with c0 = c and D^m = x.
-__device__ __forceinline__ void close_single(int c, double g0, double g1, double g2, double xr,
+// Adds gamma^m_j sigma^m_j of a node whose only child returned the sum x
+// (T_j = x, D^m relative to that child = x): close_node's arithmetic.
+__device__ __forceinline__ void close_single(double h0, double h1, double h2, double xr,
                                              double xi, double& Vr, double& Vi) {
-    const double h0 = (c & 1) ? -g0 : g0;
-    const double h1 = (c & 2) ? -g1 : g1;
-    const double h2 = ((c ^ (c >> 1)) & 1) ? -g2 : g2;
     Vr = fma(h0, xr, Vr);
     Vi = fma(h0, xi, Vi);
     Vr = fma(h1, xr, Vr);
@@ -279,7 +271,7 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, LdsPtr l
                 first = false;
             }
         }
-        close_node(n, c0, rec[me].a, rec[me].b, rec[me].c, er, ei, Vr, Vi);
+        close_node(n, rec[me].a, rec[me].b, rec[me].c, er, ei, Vr, Vi);
     }
 }
 
@@ -308,10 +300,12 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, LdsP
     } else {
         if constexpr (D < DMAX) {
             // a terminal node has two or more children.  Its sums start at
-            // zero and take every child with its own signs (c0 = 0: the
-            // plain sums); the level walker's first-child form costs this
-            // walker more in scalar registers than it saves
+            // zero and take every child with the signs of c ^ c0 (relative
+            // to its first child, as the record's coefficients are); the
+            // level walker's first-child seeding costs this walker more in
+            // scalar registers than it saves
             const unsigned all = meta_mask(mt);
+            const int c0 = __builtin_ctz(all);
             unsigned mask = all;
             NodeSums n{};
             bool first = false;
@@ -327,8 +321,8 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, LdsP
                     seg_walk<D + 1, DMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, lds, u, v, w, xr,
                                                                     xi, Vr, Vi);
                 }
-                slot_replay<BLOCK, false>(lds, nullptr, D - 1, k, all, 0, n, first);
-                add_child(n, c, 0, xr, xi, false);
+                slot_replay<BLOCK, false>(lds, nullptr, D - 1, k, all, c0, n, first);
+                add_child(n, c, c0, xr, xi, false);
             } else {
                 while (mask) {
                     const int c = __builtin_ctz(mask);
@@ -336,17 +330,16 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, LdsP
                     double xr, xi;
                     seg_walk<D + 1, DMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, lds, u, v, w, xr,
                                                                     xi, Vr, Vi);
-                    add_child(n, c, 0, xr, xi, false);
+                    add_child(n, c, c0, xr, xi, false);
                 }
             }
-            close_node(n, 0, rec[term].a, rec[term].b, rec[term].c, er, ei, Vr, Vi);
+            close_node(n, rec[term].a, rec[term].b, rec[term].c, er, ei, Vr, Vi);
         }
     }
     // the run, bottom-up
     for (int i = run - 1; i >= 0; --i) {
         const int me = first + i;
-        close_single(__builtin_ctz(meta_mask(rec[me].meta)), rec[me].a, rec[me].b, rec[me].c, er,
-                     ei, Vr, Vi);
+        close_single(rec[me].a, rec[me].b, rec[me].c, er, ei, Vr, Vi);
     }
 }
 
