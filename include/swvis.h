@@ -184,7 +184,8 @@ int swv_tree_set_flux(swv_tree tree, const double* leaf_flux);
  * results): one keeps a register set per level (J <= 10), the other one per
  * open node with two or more children (any J, up to 15 such nodes on one
  * root-to-leaf path, see swv_tree_stats_t.max_branching).  The tuning table
- * picks between them where both fit; SWV_ENOTSUP if neither does. */
+ * picks between them where both fit; SWV_ENOTSUP if neither does, or if the
+ * tree's record stream (32 bytes per record) exceeds 4 GiB - 32. */
 int swv_predict_tree(swv_ctx ctx, swv_tree tree, int64_t n_vis, const double* u,
                      const double* v, const double* w, int sign, int prec, void* vis_out);
 
@@ -607,10 +608,10 @@ typedef struct {
  * tilings follow the capacities: results are bitwise the same eager and
  * replayed, and agree with the single calls to their tolerances (the
  * gradients' summation order follows comp_cap).  The cycle holds a tree
- * record buffer of 32 (comp_cap J_cap + 12) bytes per tree instance and
- * workspaces for the largest image and gradient step.  The buffers named by
- * `inst` must outlive the cycle.  Until a model is set an instance predicts
- * zero. */
+ * record buffer of 32 (comp_cap J_cap + 12) bytes per tree instance (at most
+ * 4 GiB - 32 each, else SWV_ENOTSUP) and workspaces for the largest image and
+ * gradient step.  The buffers named by `inst` must outlive the cycle.  Until a
+ * model is set an instance predicts zero. */
 int swv_cycle_create(swv_ctx ctx, int n, const swv_cycle_instance* inst, swv_cycle* out);
 
 /* Sets the component list of direct instance k for the following cycles:

@@ -122,6 +122,9 @@ int upload_tree(swv_ctx ctx, swv_tree t, const TRec** out) {
     }
     void* p = nullptr;
     const size_t bytes = t->records.size() * sizeof(TRec);
+    if (bytes > kMaxRecordBytes)
+        return fail(SWV_ENOTSUP, "tree upload: a record stream of %zu bytes exceeds the traversal's "
+                    "%zu-byte limit", bytes, (size_t)kMaxRecordBytes);
     hipError_t e = hipMalloc(&p, bytes < 32 ? 32 : bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();

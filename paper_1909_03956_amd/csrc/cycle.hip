@@ -251,6 +251,12 @@ int swv_cycle_create(swv_ctx ctx, int n, const swv_cycle_instance* inst, swv_cyc
                 // a level-j node exists only above a leaf: at most J records per leaf, plus
                 // the roots
                 const int64_t cap = std::max<int64_t>(1, I.comp_cap) * I.tree_level_cap + 12;
+                if ((uint64_t)cap * sizeof(TRec) > kMaxRecordBytes) {
+                    delete cy;
+                    return fail(SWV_ENOTSUP, "swv_cycle_create: instance %d: %lld records exceed the "
+                                "traversal's %zu-byte stream limit", k, (long long)cap,
+                                (size_t)kMaxRecordBytes);
+                }
                 b.rec = nullptr;           // set below, once the record buffer exists
                 b.comp_offset = rec_off;   // offset into the record buffer
                 b.n_roots = 0;             // no model until swv_cycle_set_tree

@@ -41,6 +41,8 @@ constexpr int kTreeMaxJ = 10;
 // Largest segment depth of the branch walker (one register set per branching
 // node); it serves every J.
 constexpr int kTreeMaxSeg = 16;
+// The traversals address a record stream by 32-bit byte offsets.
+constexpr size_t kMaxRecordBytes = 0xFFFFFFE0u;
 
 // walker 0: level walker (t.J <= kTreeMaxJ); 1: branch walker
 // (t.seg_depth <= kTreeMaxSeg).  prec SWV_FP64 (complex128 out) or SWV_F32C

@@ -59,7 +59,10 @@ __attribute__((amdgpu_waves_per_eu(tree_waves_per_simd<JMAX, WALKER>()))) void k
     constexpr int LDSL = tree_lds_levels<JMAX, WALKER, BLOCK>();
     __shared__ double sums[LDSL > 0 ? LDSL * kSlotDoubles * BLOCK : 1];
     double Vr, Vi;
-    tree_row<JMAX, WALKER, LDSL, BLOCK, PREC == SWV_F32C, PRUNED>(ta.rec, ta.n_roots, ta.J,
+    // the level walker is launched for the tree's own J (JMAX = J), which
+    // the compiler then folds into every level test
+    const int J = WALKER == 0 ? JMAX : ta.J;
+    tree_row<JMAX, WALKER, LDSL, BLOCK, PREC == SWV_F32C, PRUNED>(ta.rec, ta.n_roots, J,
                                                                   (LdsPtr)sums, U, V, W, Vr, Vi);
     if (jrow < n_vis) {
         if (!isfinite(U + V + W)) atomicOr(status, kStatusNonFinite);

@@ -9,6 +9,14 @@
 namespace swv {
 
 using RecPtr = const __attribute__((address_space(4))) TRec*;
+
+// The walkers address the record stream by byte offset (a 32-bit scalar that
+// steps by 32), so a record's address is one 64-bit add to the base; the host
+// keeps streams below 4 GiB.
+constexpr unsigned kRecBytes = sizeof(TRec);
+__device__ __forceinline__ RecPtr rec_at(RecPtr base, unsigned off) {
+    return (RecPtr)((const __attribute__((address_space(4))) char*)base + off);
+}
 using LdsPtr = __attribute__((address_space(3))) double*;
 using PrivPtr = __attribute__((address_space(5))) double*;
 
@@ -187,9 +195,10 @@ __device__ __forceinline__ double pow2_scale(double a, int e) {
 // F32 the precision form: the FP64 phase, reduced exactly in FP64, then the
 // FP32 hardware sine and cosine (everything after the leaf stays FP64).
 template <bool VOP3, bool F32>
-__device__ __forceinline__ void leaf_wave(RecPtr rec, int me, double u, double v, double w,
+__device__ __forceinline__ void leaf_wave(RecPtr rec, unsigned me, double u, double v, double w,
                                           double& er, double& ei) {
-    const double r = reduced_phase(u, v, w, rec[me].a, rec[me].b, rec[me].c);
+    const RecPtr q = rec_at(rec, me);
+    const double r = reduced_phase(u, v, w, q->a, q->b, q->c);
     if constexpr (F32) {
         float c32, s32;
         cis2pi_f32((float)r, c32, s32);
@@ -212,7 +221,7 @@ __device__ __forceinline__ void leaf_wave(RecPtr rec, int me, double u, double v
 // close_node), so its plane wave is scaled by that exact power of two.  Only
 // the PRUNED instantiations of the walkers test for such leaves.
 template <bool F32>
-__device__ __forceinline__ void leaf_above(RecPtr rec, int me, int j, int J, double u,
+__device__ __forceinline__ void leaf_above(RecPtr rec, unsigned me, int j, int J, double u,
                                            double v, double w, double& er, double& ei) {
     leaf_wave<false, F32>(rec, me, u, v, w, er, ei);
     const double s = pow2_scale(1.0, 2 * (J - j));
@@ -223,17 +232,18 @@ __device__ __forceinline__ void leaf_above(RecPtr rec, int me, int j, int J, dou
 // Level walker: one register set per level, the level a template parameter
 // (levels <= PRIVL keep theirs in private memory, the next LDSL in LDS).
 template <int LVL, int JMAX, int LDSL, int PRIVL, int BLOCK, bool F32, bool PRUNED>
-__device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, LdsPtr lds,
+__device__ __forceinline__ void walk(RecPtr rec, unsigned& pos, const int J, LdsPtr lds,
                                      PrivPtr priv, const double u, const double v,
                                      const double w, double& er, double& ei, double& Vr,
                                      double& Vi) {
-    const int me = pos++;
+    const unsigned me = pos;
+    pos += kRecBytes;
     if (LVL == JMAX || LVL == J) {
         leaf_wave<true, F32>(rec, me, u, v, w, er, ei);
         return;
     }
     if constexpr (LVL < JMAX) {
-        const unsigned all = meta_mask(rec[me].meta);
+        const unsigned all = meta_mask(rec_at(rec, me)->meta);
         if constexpr (PRUNED) {
             if (all == 0) {   // a node collapsed by thresholding
                 leaf_above<F32>(rec, me, LVL, J, u, v, w, er, ei);
@@ -271,7 +281,8 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, LdsPtr l
                 first = false;
             }
         }
-        close_node(n, rec[me].a, rec[me].b, rec[me].c, er, ei, Vr, Vi);
+        const RecPtr q = rec_at(rec, me);
+        close_node(n, q->a, q->b, q->c, er, ei, Vr, Vi);
     }
 }
 
@@ -282,14 +293,14 @@ __device__ __forceinline__ void walk(RecPtr rec, int& pos, const int J, LdsPtr l
 // one-child node gets in the level walker.  D counts segments from the root;
 // the host launches DMAX >= 1 + the tree's largest branching count on a path.
 template <int D, int DMAX, int LDSL, int BLOCK, bool F32, bool PRUNED>
-__device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, LdsPtr lds,
+__device__ __forceinline__ void seg_walk(RecPtr rec, unsigned& pos, const int J, LdsPtr lds,
                                          const double u, const double v, const double w,
                                          double& er, double& ei, double& Vr, double& Vi) {
-    const int first = pos;
-    const int run = meta_chain(rec[first].meta);
-    const int term = first + run;
-    pos = term + 1;
-    const unsigned long long mt = rec[term].meta;
+    const unsigned first = pos;
+    const int run = meta_chain(rec_at(rec, first)->meta);
+    const unsigned term = first + (unsigned)run * kRecBytes;
+    pos = term + kRecBytes;
+    const unsigned long long mt = rec_at(rec, term)->meta;
     er = 0.0;
     ei = 0.0;
     if (meta_level(mt) == J) {
@@ -333,13 +344,14 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, int& pos, const int J, LdsP
                     add_child(n, c, c0, xr, xi, false);
                 }
             }
-            close_node(n, rec[term].a, rec[term].b, rec[term].c, er, ei, Vr, Vi);
+            const RecPtr q = rec_at(rec, term);
+            close_node(n, q->a, q->b, q->c, er, ei, Vr, Vi);
         }
     }
     // the run, bottom-up
     for (int i = run - 1; i >= 0; --i) {
-        const int me = first + i;
-        close_single(rec[me].a, rec[me].b, rec[me].c, er, ei, Vr, Vi);
+        const RecPtr q = rec_at(rec, first + (unsigned)i * kRecBytes);
+        close_single(q->a, q->b, q->c, er, ei, Vr, Vi);
     }
 }
 
@@ -387,9 +399,10 @@ __device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J, L
     const PrivPtr priv = (PrivPtr)slots;
     Vr = 0.0;
     Vi = 0.0;
-    int pos = 0;
+    unsigned pos = 0;
     for (int r = 0; r < n_roots; ++r) {
-        const int root = pos++;
+        const unsigned root = pos;
+        pos += kRecBytes;
         double er, ei;
         if constexpr (WALKER == 0)
             walk<1, JMAX, LDSL, PRIVL, BLOCK, F32, PRUNED>(rec, pos, J, lds, priv, U, V, W, er, ei,
@@ -398,7 +411,7 @@ __device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J, L
             seg_walk<1, JMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, lds, U, V, W, er, ei, Vr, Vi);
         // A_1 lambda_1 eta_1 with eta_1 = T_1 / 4^(J-1); ldexp, as A_1 lambda_1
         // may be zero
-        const double A1lam = ldexp(rec[root].a, -2 * (J - 1));
+        const double A1lam = ldexp(rec_at(rec, root)->a, -2 * (J - 1));
         Vr = fma(A1lam, er, Vr);
         Vi = fma(A1lam, ei, Vi);
     }
