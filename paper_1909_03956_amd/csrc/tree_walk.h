@@ -26,20 +26,20 @@ constexpr int kTreeRegLevels = 6;
 // Level walker, open levels 1 .. JMAX-1 (level JMAX holds the leaves): the
 // deepest level_reg_levels in registers, the level_lds_levels above them in
 // LDS, the rest in private memory, compiled for level_waves waves per SIMD (1:
-// left to the compiler).  Chosen by measurement at cfg2 (one MI355X, median
-// of nine launches; before: one register set for each of the deepest four to
-// six levels, the rest in LDS, three waves: J = 10 8.67, J = 9 3.62, J = 8
-// 1.35 ms):
-//   J = 10: 2 register + 2 LDS levels, 5 waves (96 VGPRs)  7.13 ms
-//           (3 + 2 at 5 waves 7.43; 3 + 3 at 4 waves 7.56; all but 3 LDS
-//           levels in registers, compiler spills, 4 waves 8.00; 6 waves 7.5-14)
-//   J = 8, 9: 3 + 3 levels, 4 waves (126 VGPRs)           1.25, 3.25 ms
+// left to the compiler).  Chosen by measurement at cfg2 J = 8, 9, 10 (one
+// MI355X, median of nine launches): 3 register and 2 LDS levels at 5 waves
+// per SIMD (96 VGPRs, 6 KB of LDS per wave) give 1.13, 2.98 and 6.02 ms;
+// 2 + 2 levels 1.15, 3.04 and 6.31 ms (J = 8, 9 at 3 + 3 and 4 waves); 4 + 2
+// at 4 waves 1.14, 3.03 and 6.28 ms.  Before the depth was a compile-time
+// constant and the first child's signs sat in the records, 2 + 2 at 5 waves
+// was the best at J = 10 and one register set per level at 3 waves took
+// 8.67 ms.
 template <int JMAX>
-constexpr int level_reg_levels() { return JMAX >= 10 ? 2 : 3; }
+constexpr int level_reg_levels() { return 3; }
 template <int JMAX>
-constexpr int level_lds_levels() { return JMAX >= 10 ? 2 : 3; }
+constexpr int level_lds_levels() { return 2; }
 template <int JMAX>
-constexpr int level_waves() { return JMAX >= 10 ? 5 : (JMAX >= 8 ? 4 : 1); }
+constexpr int level_waves() { return JMAX >= 8 ? 5 : 1; }
 
 // Running sums of an open node at level j over its finished children, whose
 // values are T_{j+1,c} = 4^(J-j-1) eta_{j+1,c} (the plain sums of the leaf
