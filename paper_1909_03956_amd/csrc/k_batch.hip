@@ -88,6 +88,32 @@ __global__ __launch_bounds__(BLOCK) void k_batch_direct(const BatchInst* __restr
     }
 }
 
+// One row of an instance whose depth J is read per work item (level walker):
+// the depths JD, JD - 1, ..., JD - K are compiled with J folded in, as the
+// single-tree kernel is, and smaller depths go through the walk of the
+// kernel's JMAX with J tested at run time.  J is the same for every lane, so
+// the choice is a scalar branch; every path does the same operations in the
+// same order.
+template <int JD, int K, int JMAX, int LDSL, bool F32>
+__device__ __forceinline__ void batch_row_folded(const TRec* rec, int n_roots, int J, LdsPtr lds,
+                                                 double U, double V, double W, double& Vr,
+                                                 double& Vi) {
+    if (J == JD) {
+        // a shallower walk needs no more LDS levels than the kernel holds
+        constexpr int L = tree_lds_levels<JD, 0, kBatchTreeBlock>();
+        static_assert(L <= LDSL, "LDS levels grow with the depth");
+        tree_row<JD, 0, L, kBatchTreeBlock, F32, false>(rec, n_roots, JD, lds, U, V, W, Vr, Vi);
+    } else if constexpr (K > 0 && JD > 1) {
+        batch_row_folded<JD - 1, K - 1, JMAX, LDSL, F32>(rec, n_roots, J, lds, U, V, W, Vr, Vi);
+    } else {
+        tree_row<JMAX, 0, LDSL, kBatchTreeBlock, F32, false>(rec, n_roots, J, lds, U, V, W, Vr,
+                                                             Vi);
+    }
+}
+
+// Depths below JMAX compiled with J folded in.
+constexpr int kBatchFoldedDepths = 3;
+
 // PREC: SWV_FP64 (complex128 out) or SWV_F32C (FP32 leaf phasors, complex64
 // out), exactly as the single-instance tree kernel writes them.
 template <int JMAX, int WALKER, int PREC, bool PRUNED = false>
@@ -120,8 +146,12 @@ __attribute__((amdgpu_waves_per_eu(tree_waves_per_simd<JMAX, WALKER>()))) void k
             const int64_t j = jr < limit ? jr : limit - 1;
             const double U = u[j], V = v[j], W = w[j];
             double Vr, Vi;
-            tree_row<JMAX, WALKER, LDSL, kBatchTreeBlock, PREC == SWV_F32C, PRUNED>(
-                rec, n_roots, J, (LdsPtr)sums, U, V, W, Vr, Vi);
+            if constexpr (WALKER == 0 && !PRUNED)
+                batch_row_folded<JMAX, kBatchFoldedDepths, JMAX, LDSL, PREC == SWV_F32C>(
+                    rec, n_roots, J, (LdsPtr)sums, U, V, W, Vr, Vi);
+            else
+                tree_row<JMAX, WALKER, LDSL, kBatchTreeBlock, PREC == SWV_F32C, PRUNED>(
+                    rec, n_roots, J, (LdsPtr)sums, U, V, W, Vr, Vi);
             if (jr < limit) {
                 if (!isfinite(U + V + W)) atomicOr(status, kStatusNonFinite);
                 if constexpr (PREC == SWV_F32C)
