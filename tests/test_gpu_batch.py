@@ -254,6 +254,39 @@ def test_batched_workload_full_size(env):
     assert _check_instances(B, outs, chosen, torch, "cfg4") <= TOL64
 
 
+def test_batch_level_walker_every_depth_bitwise(env):
+    """A plan whose trees all fit the level walker (J <= 10): the four deepest
+    depths of the plan run walks compiled for their J, the shallower ones the
+    walk with J tested at run time; every output, FP64 and F32C, bitwise the
+    single-instance prediction, before and after a graph capture."""
+    torch, swv = env
+    rng = np.random.default_rng(31)
+    insts, refs = [], []
+    for J, n, k, prec in ((2, 1000, 30, "fp64"), (4, 3001, 80, "fp64"), (6, 777, 200, "fp64"),
+                          (7, 4097, 150, "fp64"), (8, 2048, 300, "fp64"), (9, 5000, 250, "fp64"),
+                          (10, 6001, 400, "fp64"), (3, 999, 40, "f32c"), (10, 2500, 300, "f32c"),
+                          (1, 65, 3, "fp64")):
+        u, v, w = (dev(rng.uniform(-3e4, 3e4, n), torch) for _ in range(3))
+        l, m = rng.uniform(-0.04, 0.04, k), rng.uniform(-0.04, 0.04, k)
+        t = swv.Tree(J, 1.1, 0.4, l, m, rng.lognormal(-3, 1, k))
+        dt = torch.complex64 if prec == "f32c" else torch.complex128
+        out = torch.full((n,), 7.0, dtype=dt, device="cuda")
+        insts.append(dict(route="tree", prec=prec, tree=t, u=u, v=v, w=w, out=out))
+        refs.append(lambda u=u, v=v, w=w, t=t, p=prec: t.predict(u, v, w, prec=p))
+    plan = swv.BatchPlan(insts)
+    plan.run()
+    swv.synchronize()
+    assert _mismatches(insts, refs, torch) == []
+    graph = plan.capture()
+    for d in insts:
+        d["out"].fill_(3.0)
+    graph.launch()
+    swv.synchronize()
+    assert _mismatches(insts, refs, torch) == []
+    graph.close()
+    plan.close()
+
+
 def test_batch_f32c_trees_bitwise(env):
     """Tree instances in FP32C (and FP64, and F32C direct ones) in one plan:
     every output bitwise equal to the single-instance prediction; the F32C
