@@ -181,11 +181,13 @@ int swv_tree_set_flux(swv_tree tree, const double* leaf_flux);
  * arithmetic stays FP64).  The tree is copied to the device on first use with
  * this context's device.
  * Two traversals compute the same operations in the same order (bitwise equal
- * results): one keeps a register set per level (J <= 10), the other one per
- * open node with two or more children (any J, up to 15 such nodes on one
- * root-to-leaf path, see swv_tree_stats_t.max_branching).  The tuning table
- * picks between them where both fit; SWV_ENOTSUP if neither does, or if the
- * tree's record stream (32 bytes per record) exceeds 4 GiB - 32. */
+ * results): one keeps a state set per level (J <= 16), the other one per open
+ * node with two or more children (any J, up to 15 such nodes on one
+ * root-to-leaf path, see swv_tree_stats_t.max_branching).  By default the
+ * first serves J <= 10, and J <= 16 unless more than three in four internal
+ * nodes have a single child; the tuning table can force either (swv_tune_set).
+ * SWV_ENOTSUP if neither fits, or if the tree's record stream (32 bytes per
+ * record) exceeds 4 GiB - 32. */
 int swv_predict_tree(swv_ctx ctx, swv_tree tree, int64_t n_vis, const double* u,
                      const double* v, const double* w, int sign, int prec, void* vis_out);
 
@@ -675,9 +677,9 @@ int swv_tune_load(swv_ctx ctx, const char* cache_path);
  * 0 direct FP64, 1 direct F32C, 2 tree, 3 adjoint, 4 gradients.  Size class
  * 0 is fewer than 2^20 visibility rows, 1 the rest.  per_lane is rows per lane
  * (direct), pixels per lane (adjoint) or components per lane (gradients), in
- * {1, 2, 4}; for the tree it selects the traversal (1: register set per level
- * where J <= 10, else per branching node; 2: always per branching node; see
- * swv_predict_tree).  block is threads per block in {64, 128, 256}; the
+ * {1, 2, 4}; for the tree it selects the traversal (1: by depth and shape as
+ * swv_predict_tree describes; 2: per branching node where it fits; 4: per
+ * level where J <= 16).  block is threads per block in {64, 128, 256}; the
  * gradients ignore it and take the narrowest block of 128 .. 1024 threads that
  * holds every component at per_lane (else 1024).  Results do not depend on the
  * shape except for the summation order of the adjoint and gradients. */

@@ -101,8 +101,9 @@ bool tune_valid(int family, int per_lane, int block) {
     if (family < 0 || family >= kFamilies) return false;
     const bool pl_ok = per_lane == 1 || per_lane == 2 || per_lane == 4;
     const bool bl_ok = block == 64 || block == 128 || block == 256;
-    // tree: per_lane selects the traversal (1 level walker, 2 branch walker)
-    if (family == kFamTree) return (per_lane == 1 || per_lane == 2) && bl_ok;
+    // tree: per_lane selects the traversal (1 by depth and shape, 2 branch
+    // walker, 4 level walker where it fits)
+    if (family == kFamTree) return (per_lane == 1 || per_lane == 2 || per_lane == 4) && bl_ok;
     if (family == kFamGrad) return pl_ok && block == 128;
     return pl_ok && bl_ok;
 }
@@ -180,8 +181,17 @@ int tree_walker(swv_tree t, int preferred) {
     const bool level_ok = t->J <= kTreeMaxJ;
     const bool branch_ok = t->max_branching + 1 <= kTreeMaxSeg;
     if (preferred == 2 && branch_ok) return 1;
-    if (level_ok) return 0;
-    return branch_ok ? 1 : -1;
+    if (!level_ok) return branch_ok ? 1 : -1;
+    if (preferred == 4 || t->J <= kTreeLevelAlwaysJ || !branch_ok) return 0;
+    // deeper trees: runs of one-child nodes cost the branch walker less (cfg2's
+    // 2,000 components at J = 11, 12, 53-62 % of the internal nodes with one
+    // child: 10.8 and 18.1 ms by levels against 17.5 and 27.3 ms by branchings;
+    // 140 sparse components at J = 12-16, 89-94 %: 0.83-1.11 ms by branchings
+    // against 1.49-1.99 ms by levels)
+    int64_t internal = t->n_alive;
+    if (!t->thresholded)
+        for (int j = 1; j < t->J; ++j) internal += (int64_t)t->levels[j - 1].pix.size();
+    return 4 * t->n_one_child > 3 * internal ? 1 : 0;
 }
 
 TreeArgs tree_args(swv_tree t, const TRec* d_rec) {

@@ -195,7 +195,7 @@ int swv_batch_plan(swv_ctx ctx, int n, const swv_instance* inst, swv_plan* out) 
             }
         }
         // one traversal for all trees of the plan: the tuned one where it fits
-        const bool level_ok = p->jmax <= kTreeMaxJ, branch_ok = p->smax <= kTreeMaxSeg;
+        const bool level_ok = p->jmax <= kBatchTreeMaxJ, branch_ok = p->smax <= kTreeMaxSeg;
         const bool want_branch = ctx->per_lane[kFamTree][1] == 2;
         if (!p->tree.empty() && !level_ok && !branch_ok) {
             delete p;

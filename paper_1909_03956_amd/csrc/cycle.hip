@@ -271,7 +271,7 @@ int swv_cycle_create(swv_ctx ctx, int n, const swv_cycle_instance* inst, swv_cyc
         }
         // one traversal for every tree of the cycle: the level walker up to its
         // largest J, else the branch walker at its deepest segment count
-        cy->walker = jcap <= kTreeMaxJ ? 0 : 1;
+        cy->walker = jcap <= kBatchTreeMaxJ ? 0 : 1;
         cy->depth = cy->walker == 0 ? jcap : kTreeMaxSeg;
         cy->grid_direct = ctx->n_cu * batch_direct_blocks_per_cu(cy->vpl, cy->block);
         cy->grid_tree = ctx->n_cu * batch_tree_blocks_per_cu(cy->walker, cy->depth, SWV_FP64);

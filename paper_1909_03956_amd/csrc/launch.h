@@ -35,9 +35,15 @@ struct TreeArgs {
     int pruned;                       // leaves above level J (coefficient thresholding)
 };
 
-// Largest J of the level walker (one state set per level); beyond it the
-// branch walker, whose state follows the branching depth, is the faster one.
-constexpr int kTreeMaxJ = 10;
+// Largest J of the level walker (one state set per level) in the single-tree
+// kernel, and in the batched and cycle kernels; beyond them the branch walker,
+// whose state follows the branching depth.
+constexpr int kTreeMaxJ = 16;
+constexpr int kBatchTreeMaxJ = 10;
+// Depth up to which the single-tree kernel takes the level walker for every
+// tree; above it (up to kTreeMaxJ) only for trees in which at most three in
+// four internal nodes have a single child.
+constexpr int kTreeLevelAlwaysJ = 10;
 // Largest segment depth of the branch walker (one register set per branching
 // node); it serves every J.
 constexpr int kTreeMaxSeg = 16;

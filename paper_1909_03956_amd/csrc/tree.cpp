@@ -102,6 +102,7 @@ void build_coefficients(swv_tree_s* t) {
     // one-child runs and branching depth, bottom-up
     std::vector<int> depth_below(nl, 0);   // branching nodes strictly below, per node
     top.chain.assign(nl, 0);
+    t->n_one_child = 0;
     for (int j = J - 1; j >= 1; --j) {
         TreeLevel& L = t->levels[j - 1];
         const TreeLevel& below = t->levels[j];
@@ -114,7 +115,10 @@ void build_coefficients(swv_tree_s* t) {
             int d = 0;
             for (int i = 0; i < nch; ++i) d = std::max(d, depth_below[c0 + i]);
             depth[k] = d + (nch >= 2 ? 1 : 0);
-            if (nch == 1) L.chain[k] = 1 + (j + 1 < J ? below.chain[c0] : 0);
+            if (nch == 1) {
+                L.chain[k] = 1 + (j + 1 < J ? below.chain[c0] : 0);
+                ++t->n_one_child;
+            }
         }
         depth_below.swap(depth);
     }
@@ -199,6 +203,7 @@ struct Pruner {
             TRec{h[0], h[1], h[2], make_meta((unsigned)L.mask[idx], j, chain[j - 1][idx])});
         out->levels[j - 1].pix.push_back(L.pix[idx]);
         ++out->n_alive;
+        if (__builtin_popcount((unsigned)L.mask[idx]) == 1) ++out->n_one_child;
         int64_t child = L.first_child[idx];
         for (int c = 0; c < 4; ++c)
             if (L.mask[idx] & (1 << c)) emit(j + 1, child++);
@@ -262,6 +267,7 @@ int prune_tree(const swv_tree_s& t, const std::vector<int64_t>& kept, swv_tree_s
     out->records.clear();
     out->leaf_pix.clear();
     out->n_alive = 0;
+    out->n_one_child = 0;
     out->max_branching = 0;
     const TreeLevel& L1 = t.levels[0];
     const double A1 = pixel_area(1);

@@ -49,6 +49,7 @@ struct swv_tree_s {
     // `leaf_pix` the leaves of every level
     bool thresholded = false;
     int64_t n_alive = 0;                 // internal nodes of the pruned tree
+    int64_t n_one_child = 0;             // internal nodes with a single child
     int64_t n_coeffs = 0;                // wavelet coefficients of the source tree
     std::vector<int64_t> kept;           // retained ones, flat indices, increasing
 };

@@ -117,7 +117,8 @@ hipError_t launch_tree_prec(hipStream_t s, int walker, int block, const TreeArgs
         switch (t.J) {
             SWV_TREE_CASE(1, 0) SWV_TREE_CASE(2, 0) SWV_TREE_CASE(3, 0) SWV_TREE_CASE(4, 0)
             SWV_TREE_CASE(5, 0) SWV_TREE_CASE(6, 0) SWV_TREE_CASE(7, 0) SWV_TREE_CASE(8, 0)
-            SWV_TREE_CASE(9, 0) SWV_TREE_CASE(10, 0)
+            SWV_TREE_CASE(9, 0) SWV_TREE_CASE(10, 0) SWV_TREE_CASE(11, 0) SWV_TREE_CASE(12, 0)
+            SWV_TREE_CASE(13, 0) SWV_TREE_CASE(14, 0) SWV_TREE_CASE(15, 0) SWV_TREE_CASE(16, 0)
             default: return hipErrorInvalidValue;
         }
     }

@@ -87,8 +87,8 @@ def test_thresholded_walkers_bitwise_and_f32c(env, J, frac):
     tp = swv.Tree(J, ra, dec, l, m, f).prune(keep)
     U, V, Wt = dev(u, torch), dev(v, torch), dev(w, torch)
     a = _with_walker(swv, 2, lambda: tp.predict(U, V, Wt))
-    if J <= 10:
-        b = _with_walker(swv, 1, lambda: tp.predict(U, V, Wt))
+    if J <= 16:
+        b = _with_walker(swv, 4, lambda: tp.predict(U, V, Wt))
         swv.synchronize()
         assert torch.equal(a, b)
     rows = configs.sample_rows(u.size, 512, seed=J)

@@ -124,7 +124,7 @@ def _spine_pixels(J, base, counts, rng):
     return pix
 
 
-@pytest.mark.parametrize("J,walker", [(10, 1), (10, 2), (12, 2), (15, 2)])
+@pytest.mark.parametrize("J,walker", [(10, 1), (10, 2), (12, 2), (15, 2), (12, 4), (15, 4)])
 def test_every_child_count_on_the_lds_levels(env, J, walker):
     """The top levels (segments) of a deep traversal keep their finished
     children in LDS and form the sums when the last child returns; spines
@@ -201,7 +201,8 @@ def _oracle_tree_on_library_pixels(J, ra, dec, l, m, f):
 
 
 def _with_walker(swv, walker, fn):
-    """Runs fn() with the tree traversal forced to `walker` (1 level, 2 branch)."""
+    """Runs fn() with the tree traversal chosen by `walker` (1 by depth and
+    shape, 2 branch walker, 4 level walker wherever it is compiled)."""
     from paper_1909_03956_amd._lib import FAM_TREE
     ctx = swv.context()
     saved = [ctx.tune_get(FAM_TREE, c) for c in (0, 1)]
@@ -214,7 +215,8 @@ def _with_walker(swv, walker, fn):
             ctx.tune_set(FAM_TREE, c, *saved[c])
 
 
-@pytest.mark.parametrize("name,J", [("cfg1", 6), ("cfg2", 8), ("cfg2", 9), ("cfg2", 10)])
+@pytest.mark.parametrize("name,J", [("cfg1", 6), ("cfg2", 8), ("cfg2", 9), ("cfg2", 10),
+                                    ("cfg1", 12), ("cfg1", 16)])
 def test_walkers_bitwise_equal(env, name, J):
     # both traversals perform the same operations in the same order
     torch, swv = env
@@ -222,15 +224,16 @@ def test_walkers_bitwise_equal(env, name, J):
     u, v, w = (dev(a, torch) for a in W.track.uvw())
     l, m, f = W.components()
     t = swv.Tree(J, W.ra_p, W.dec_p, l, m, f)
-    a = _with_walker(swv, 1, lambda: t.predict(u, v, w))
+    a = _with_walker(swv, 4, lambda: t.predict(u, v, w))
     b = _with_walker(swv, 2, lambda: t.predict(u, v, w))
+    c = _with_walker(swv, 1, lambda: t.predict(u, v, w))
     swv.synchronize()
     st = t.stats()
     note(f"{name} J={J}: max_branching={st['max_branching']} rows={u.numel()}")
-    assert torch.equal(a, b)
+    assert torch.equal(a, b) and torch.equal(a, c)
 
 
-@pytest.mark.parametrize("J", list(range(1, 11)))
+@pytest.mark.parametrize("J", list(range(1, 17)))
 def test_walkers_bitwise_equal_small_trees(env, J):
     torch, swv = env
     rng = np.random.default_rng(200 + J)
@@ -240,7 +243,7 @@ def test_walkers_bitwise_equal_small_trees(env, J):
     f = rng.lognormal(-3, 1, n)
     u, v, w = (dev(rng.uniform(-2e4, 2e4, 1000), torch) for _ in range(3))
     t = swv.Tree(J, 1.0, 0.3, l, m, f)
-    a = _with_walker(swv, 1, lambda: t.predict(u, v, w))
+    a = _with_walker(swv, 4, lambda: t.predict(u, v, w))
     b = _with_walker(swv, 2, lambda: t.predict(u, v, w))
     swv.synchronize()
     assert torch.equal(a, b)
