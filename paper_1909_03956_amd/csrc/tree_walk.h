@@ -20,9 +20,23 @@ __device__ __forceinline__ RecPtr rec_at(RecPtr base, unsigned off) {
 using LdsPtr = __attribute__((address_space(3))) double*;
 using PrivPtr = __attribute__((address_space(5))) double*;
 
-// Branch walker: the deepest six open segments keep their running sums in
-// registers, the ones above them keep their children in LDS (see slot_put).
-constexpr int kTreeRegLevels = 6;
+// Branch walker, open segment levels 1 .. DMAX-1 (DMAX: the compiled
+// branching depth): the deepest branch_reg_levels keep their running sums in
+// registers, the branch_lds_levels above them keep their children in LDS (see
+// slot_put; within 64 KB per block), the rest in private memory; compiled for
+// branch_waves waves per SIMD (1: left to the compiler).  Measured (one
+// MI355X, median of seven) with 3 + 3 levels at 4 waves against the earlier
+// 5 register levels and every level above in LDS (2-3 waves): the run-time
+// sweep's 140 components at J = 12, 16, 20, 25 0.76, 0.96, 1.20, 1.43 ms
+// against 0.83, 1.09, 1.37, 1.66; cfg2 at J = 11, 12 14.9 and 23.4 ms against
+// 17.5 and 27.4; 4 + 2 at 4 waves within 3 %, 2-3 register levels at 5 waves
+// 1-8 % slower than 3 + 3.
+template <int DMAX>
+constexpr int branch_reg_levels() { return 3; }
+template <int DMAX>
+constexpr int branch_lds_levels() { return 3; }
+template <int DMAX>
+constexpr int branch_waves() { return DMAX >= 5 ? 4 : 1; }
 // Level walker, open levels 1 .. JMAX-1 (level JMAX holds the leaves): the
 // deepest level_reg_levels in registers, the level_lds_levels above them in
 // LDS, the rest in private memory, compiled for level_waves waves per SIMD (1:
@@ -292,10 +306,11 @@ __device__ __forceinline__ void walk(RecPtr rec, unsigned& pos, const int J, Lds
 // walked, and is closed bottom-up afterwards with the same arithmetic a
 // one-child node gets in the level walker.  D counts segments from the root;
 // the host launches DMAX >= 1 + the tree's largest branching count on a path.
-template <int D, int DMAX, int LDSL, int BLOCK, bool F32, bool PRUNED>
+template <int D, int DMAX, int LDSL, int PRIVL, int BLOCK, bool F32, bool PRUNED>
 __device__ __forceinline__ void seg_walk(RecPtr rec, unsigned& pos, const int J, LdsPtr lds,
-                                         const double u, const double v, const double w,
-                                         double& er, double& ei, double& Vr, double& Vi) {
+                                         PrivPtr priv, const double u, const double v,
+                                         const double w, double& er, double& ei, double& Vr,
+                                         double& Vi) {
     const unsigned first = pos;
     const int run = meta_chain(rec_at(rec, first)->meta);
     const unsigned term = first + (unsigned)run * kRecBytes;
@@ -320,27 +335,31 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, unsigned& pos, const int J,
             unsigned mask = all;
             NodeSums n{};
             bool first = false;
-            if constexpr (D <= LDSL) {
+            if constexpr (D <= PRIVL + LDSL) {
                 // as in the level walker: all children but the last wait in
                 // the slot, and the sums are formed at the end
+                constexpr bool PRIV = D <= PRIVL;
+                constexpr int SLOT = PRIV ? D - 1 : D - PRIVL - 1;
                 int k = 0, c = 0;
                 double xr = 0.0, xi = 0.0;
                 while (mask) {
-                    if (mask != all) slot_put<BLOCK, false>(lds, nullptr, D - 1, k++, xr, xi);
+                    if (mask != all) slot_put<BLOCK, PRIV>(lds, priv, SLOT, k++, xr, xi);
                     c = __builtin_ctz(mask);
                     mask &= mask - 1;
-                    seg_walk<D + 1, DMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, lds, u, v, w, xr,
-                                                                    xi, Vr, Vi);
+                    seg_walk<D + 1, DMAX, LDSL, PRIVL, BLOCK, F32, PRUNED>(rec, pos, J, lds, priv,
+                                                                           u, v, w, xr, xi, Vr,
+                                                                           Vi);
                 }
-                slot_replay<BLOCK, false>(lds, nullptr, D - 1, k, all, c0, n, first);
+                slot_replay<BLOCK, PRIV>(lds, priv, SLOT, k, all, c0, n, first);
                 add_child(n, c, c0, xr, xi, false);
             } else {
                 while (mask) {
                     const int c = __builtin_ctz(mask);
                     mask &= mask - 1;
                     double xr, xi;
-                    seg_walk<D + 1, DMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, lds, u, v, w, xr,
-                                                                    xi, Vr, Vi);
+                    seg_walk<D + 1, DMAX, LDSL, PRIVL, BLOCK, F32, PRUNED>(rec, pos, J, lds, priv,
+                                                                           u, v, w, xr, xi, Vr,
+                                                                           Vi);
                     add_child(n, c, c0, xr, xi, false);
                 }
             }
@@ -357,33 +376,32 @@ __device__ __forceinline__ void seg_walk(RecPtr rec, unsigned& pos, const int J,
 
 // Levels (segments) of a traversal compiled to depth JMAX whose children go
 // to LDS: for the level walker the level_lds_levels above its register levels,
-// for the branch walker all segments above the deepest kTreeRegLevels within
+// for the branch walker the branch_lds_levels above its register levels, within
 // 64 KB per block.
 template <int JMAX, int WALKER, int BLOCK>
 constexpr int tree_lds_levels() {
-    if constexpr (WALKER == 0) {
-        constexpr int above = JMAX - 1 - level_reg_levels<JMAX>();
-        constexpr int cap = level_lds_levels<JMAX>();
-        return above <= 0 ? 0 : (above < cap ? above : cap);
-    } else {
-        constexpr int want = JMAX > kTreeRegLevels ? JMAX - kTreeRegLevels : 0;
-        constexpr int cap = (64 * 1024) / (kSlotDoubles * 8 * BLOCK);
-        return want < cap ? want : cap;
-    }
+    constexpr int above =
+        JMAX - 1 - (WALKER == 0 ? level_reg_levels<JMAX>() : branch_reg_levels<JMAX>());
+    constexpr int want = WALKER == 0 ? level_lds_levels<JMAX>() : branch_lds_levels<JMAX>();
+    constexpr int block_cap = (64 * 1024) / (kSlotDoubles * 8 * BLOCK);
+    constexpr int cap = want < block_cap ? want : block_cap;
+    return above <= 0 ? 0 : (above < cap ? above : cap);
 }
 
-// Top levels of the level walker whose children go to private memory.
-template <int JMAX, int WALKER>
+// Top levels (segments) whose children go to private memory: those above the
+// register and LDS levels.
+template <int JMAX, int WALKER, int BLOCK>
 constexpr int tree_priv_levels() {
-    constexpr int above = JMAX - 1 - level_reg_levels<JMAX>() - level_lds_levels<JMAX>();
-    return WALKER != 0 || above <= 0 ? 0 : above;
+    constexpr int above =
+        JMAX - 1 - (WALKER == 0 ? level_reg_levels<JMAX>() : branch_reg_levels<JMAX>()) -
+        tree_lds_levels<JMAX, WALKER, BLOCK>();
+    return above <= 0 ? 0 : above;
 }
 
-// Waves per SIMD a traversal is compiled for (the kernels' amdgpu_waves_per_eu):
-// the level walker's level_waves; the branch walker is left to the compiler.
+// Waves per SIMD a traversal is compiled for (the kernels' amdgpu_waves_per_eu).
 template <int JMAX, int WALKER>
 constexpr int tree_waves_per_simd() {
-    return WALKER != 0 ? 1 : level_waves<JMAX>();
+    return WALKER == 0 ? level_waves<JMAX>() : branch_waves<JMAX>();
 }
 
 // V (real, imaginary / 4) of one row: the root loop of the traversal.
@@ -394,7 +412,7 @@ template <int JMAX, int WALKER, int LDSL, int BLOCK, bool F32 = false, bool PRUN
 __device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J, LdsPtr lds,
                                          double U, double V, double W, double& Vr, double& Vi) {
     const RecPtr rec = uniform_ptr(recs);
-    constexpr int PRIVL = tree_priv_levels<JMAX, WALKER>();
+    constexpr int PRIVL = tree_priv_levels<JMAX, WALKER, BLOCK>();
     double slots[PRIVL > 0 ? PRIVL * kSlotDoubles : 1];
     const PrivPtr priv = (PrivPtr)slots;
     Vr = 0.0;
@@ -408,7 +426,8 @@ __device__ __forceinline__ void tree_row(const TRec* recs, int n_roots, int J, L
             walk<1, JMAX, LDSL, PRIVL, BLOCK, F32, PRUNED>(rec, pos, J, lds, priv, U, V, W, er, ei,
                                                            Vr, Vi);
         else
-            seg_walk<1, JMAX, LDSL, BLOCK, F32, PRUNED>(rec, pos, J, lds, U, V, W, er, ei, Vr, Vi);
+            seg_walk<1, JMAX, LDSL, PRIVL, BLOCK, F32, PRUNED>(rec, pos, J, lds, priv, U, V, W, er,
+                                                               ei, Vr, Vi);
         // A_1 lambda_1 eta_1 with eta_1 = T_1 / 4^(J-1); ldexp, as A_1 lambda_1
         // may be zero
         const double A1lam = ldexp(rec_at(rec, root)->a, -2 * (J - 1));
