@@ -15,12 +15,19 @@ def test_measured_peaks_plausible():
     assert 10.0 < p["fp64_fma_tflops"] <= 78.6 * 1.05
     assert 10.0 < p["fp32_fma_tflops"] <= 157.3 * 1.05
     assert p["sincos_f32_gops"] > 0
-    # one FP64 phasor costs 21 FP64 VALU lane-operations: phasors per second
-    # times 21 cannot beat the FP64 lane-operation rate at the top engine
-    # clock (the published 78.6 TFLOP/s over 2 flop per FMA).  The measured
-    # FMA stream is not the bound: it draws the most power of the four
-    # kernels and can run at a lower clock than the phasor kernel after it
-    # (seen: 70.6 TFLOP/s against 1,789 G phasors/s, 1.06x its lane rate).
-    assert p["cis2pi_f64_gops"] * 1e9 * 21 <= 78.6e12 / 2 * 1.02
-    # and within a power-throttling margin of the measured stream
-    assert p["cis2pi_f64_gops"] * 1e9 * 21 <= p["fp64_fma_tflops"] * 1e12 / 2 * 1.2
+    # FP32 FMA issues at twice the FP64 rate per lane on this part (the
+    # published 157.3 against 78.6; measured 1.93x at the same clock)
+    assert 1.7 <= p["fp32_fma_tflops"] / p["fp64_fma_tflops"] <= 2.1
+    # one FP64 phasor costs 21 FP64 VALU instructions (20 in the phasor, one
+    # to form the next phase; SQ_INSTS_VALU reads 21.0 per phasor).  Phasors
+    # per second times 21 cannot beat the FP64 lane rate at the top engine
+    # clock (the published 78.6 TFLOP/s over 2 flop per FMA) ...
+    lanes64 = p["fp64_fma_tflops"] * 1e12 / 2
+    phasor_lanes = p["cis2pi_f64_gops"] * 1e9 * 21
+    assert phasor_lanes <= 78.6e12 / 2 * 1.02
+    # ... and match the measured FMA stream's lane rate: both kernels run at
+    # the same engine clock once warm (2.37 and 2.38 GHz, busy cycles over
+    # duration) and issue 0.96 and 0.97 FP64 instructions per lane and cycle,
+    # so the phasor's rate was 1.017x the stream's.  A wider gap means one of
+    # the two was timed while the clock was still ramping.
+    assert 0.85 * lanes64 <= phasor_lanes <= 1.05 * lanes64
