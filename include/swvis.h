@@ -680,8 +680,9 @@ int swv_tune_load(swv_ctx ctx, const char* cache_path);
  * {1, 2, 4}; for the tree it selects the traversal (1: by depth and shape as
  * swv_predict_tree describes; 2: per branching node where it fits; 4: per
  * level where J <= 16).  block is threads per block in {64, 128, 256}; the
- * gradients ignore it and take the narrowest block of 128 .. 1024 threads that
- * holds every component at per_lane (else 1024).  Results do not depend on the
+ * gradients' entries hold 128 (swv_tune_set rejects any other value for them):
+ * their launches take the narrowest block of 128 .. 1024 threads that holds
+ * every component at per_lane (else 1024).  Results do not depend on the
  * shape except for the summation order of the adjoint and gradients. */
 int swv_tune_get(swv_ctx ctx, int family, int size_class, int* per_lane, int* block);
 

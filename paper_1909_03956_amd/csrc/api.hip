@@ -189,8 +189,8 @@ int tree_walker(swv_tree t, int preferred) {
     if (t->thresholded) return 1;
     // deeper trees: runs of one-child nodes cost the branch walker less (cfg2's
     // 2,000 components at J = 11, 12, 53-62 % of the internal nodes with one
-    // child: 10.8 and 18.1 ms by levels against 17.5 and 27.3 ms by branchings;
-    // 140 sparse components at J = 12-16, 89-94 %: 0.83-1.11 ms by branchings
+    // child: 10.8 and 18.1 ms by levels against 14.9 and 23.3 ms by branchings;
+    // 140 sparse components at J = 12-16, 89-94 %: 0.75-0.98 ms by branchings
     // against 1.49-1.99 ms by levels)
     int64_t internal = 0;
     for (int j = 1; j < t->J; ++j) internal += (int64_t)t->levels[j - 1].pix.size();
