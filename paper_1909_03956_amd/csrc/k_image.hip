@@ -44,22 +44,19 @@ static void launch_slabs(int64_t total, F&& launch) {
 // ---------------------------------------------------------------- adjoint --
 // img[p] = sum_j conj(e_jp) y_j, e = exp(s 2 pi i phi).  With e = c + i s S:
 // conj(e) y = (c yr + s S yi) + i (c yi - s S yr), S = 4 q.
-template <int PPL, int BLOCK, int PREC>
-__global__ __launch_bounds__(BLOCK) void k_adjoint(
+// One lane's G pixels q0, q0 + 64, ... over the rows of chunk chunk_id.
+template <int G, int PREC>
+__device__ __forceinline__ void adjoint_lane(
     const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
     const double2* __restrict__ y, int64_t n_vis, int64_t chunk, const double* __restrict__ pl,
     const double* __restrict__ pm, const double* __restrict__ pn, int64_t n_pix, double sgn,
-    int64_t n_chunks, int64_t tiles, int64_t bid0, double2* __restrict__ partial) {
-    int64_t chunk_id, tile;
-    chunk_tile(bid0 + blockIdx.x, tiles, chunk_id, tile);
-    if (chunk_id >= n_chunks) return;   // padding of the last XCD group
-    const int64_t p0 = tile * (BLOCK * PPL) + threadIdx.x;
-    double L[PPL], M[PPL], N[PPL];
-    double ar[PPL], ai[PPL];
-    float sr[PPL], cr[PPL], si[PPL], ci[PPL];
+    int64_t chunk_id, int64_t q0, double2* __restrict__ partial) {
+    double L[G], M[G], N[G];
+    double ar[G], ai[G];
+    float sr[G], cr[G], si[G], ci[G];
 #pragma unroll
-    for (int i = 0; i < PPL; ++i) {
-        int64_t p = p0 + (int64_t)i * BLOCK;
+    for (int i = 0; i < G; ++i) {
+        int64_t p = q0 + (int64_t)i * 64;
         p = p < n_pix ? p : n_pix - 1;
         L[i] = pl[p];
         M[i] = pm[p];
@@ -82,7 +79,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
         if constexpr (PREC == SWV_FP64) {
             const double y4r = 4.0 * sgn * yr, y4i = 4.0 * sgn * yi;
 #pragma unroll
-            for (int i = 0; i < PPL; ++i) {
+            for (int i = 0; i < G; ++i) {
                 double c, q;
                 cis2pi_q(reduced_phase(uj, vj, wj, L[i], M[i], N[i]), c, q);
                 ar[i] = fma(c, yr, ar[i]);
@@ -94,7 +91,7 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
             const float fyr = (float)yr, fyi = (float)yi;
             const float fsyr = (float)(sgn * yr), fsyi = (float)(sgn * yi);
 #pragma unroll
-            for (int i = 0; i < PPL; ++i) {
+            for (int i = 0; i < G; ++i) {
                 const float r = (float)reduced_phase(uj, vj, wj, L[i], M[i], N[i]);
                 float c, s;
                 cis2pi_f32(r, c, s);
@@ -104,8 +101,8 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
         }
     }
 #pragma unroll
-    for (int i = 0; i < PPL; ++i) {
-        const int64_t p = p0 + (int64_t)i * BLOCK;
+    for (int i = 0; i < G; ++i) {
+        const int64_t p = q0 + (int64_t)i * 64;
         if (p < n_pix) {
             double2 o;
             if constexpr (PREC == SWV_FP64)
@@ -113,6 +110,45 @@ __global__ __launch_bounds__(BLOCK) void k_adjoint(
             else
                 o = make_double2((double)sr[i] - (double)cr[i], (double)si[i] - (double)ci[i]);
             partial[chunk_id * n_pix + p] = o;
+        }
+    }
+}
+
+// Each wave of a tile owns PPL consecutive groups of 64 pixels (lane l of the
+// wave takes pixel l of each group), so the pixels past the last one gather
+// in whole groups at the end of the last tile, which are not computed (the
+// 955-pixel image of the major cycle in one 1,024-pixel tile: 64 of its 69
+// idle slots).  A pixel's sum is the same whichever lane takes it.
+template <int PPL, int BLOCK, int PREC>
+__global__ __launch_bounds__(BLOCK) void k_adjoint(
+    const double* __restrict__ u, const double* __restrict__ v, const double* __restrict__ w,
+    const double2* __restrict__ y, int64_t n_vis, int64_t chunk, const double* __restrict__ pl,
+    const double* __restrict__ pm, const double* __restrict__ pn, int64_t n_pix, double sgn,
+    int64_t n_chunks, int64_t tiles, int64_t bid0, double2* __restrict__ partial) {
+    int64_t chunk_id, tile;
+    chunk_tile(bid0 + blockIdx.x, tiles, chunk_id, tile);
+    if (chunk_id >= n_chunks) return;   // padding of the last XCD group
+    static_assert(BLOCK % 64 == 0, "whole waves");
+    const int wave = (int)(threadIdx.x / 64), lane = (int)(threadIdx.x % 64);
+    const int64_t g0 = tile * (BLOCK * PPL) + (int64_t)wave * (64 * PPL);
+    const int64_t left = n_pix - g0;   // the same for every lane of the wave
+    const int groups = __builtin_amdgcn_readfirstlane(
+        left <= 0 ? 0 : (left >= 64 * PPL ? PPL : (int)((left + 63) / 64)));
+    const int64_t q0 = g0 + lane;
+    if (groups >= PPL) {
+        adjoint_lane<PPL, PREC>(u, v, w, y, n_vis, chunk, pl, pm, pn, n_pix, sgn, chunk_id, q0,
+                                partial);
+    } else if constexpr (PPL >= 2) {
+        if (groups == 1)
+            adjoint_lane<1, PREC>(u, v, w, y, n_vis, chunk, pl, pm, pn, n_pix, sgn, chunk_id, q0,
+                                  partial);
+        if constexpr (PPL >= 4) {
+            if (groups == 2)
+                adjoint_lane<2, PREC>(u, v, w, y, n_vis, chunk, pl, pm, pn, n_pix, sgn, chunk_id,
+                                      q0, partial);
+            if (groups == 3)
+                adjoint_lane<3, PREC>(u, v, w, y, n_vis, chunk, pl, pm, pn, n_pix, sgn, chunk_id,
+                                      q0, partial);
         }
     }
 }
