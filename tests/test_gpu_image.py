@@ -59,6 +59,42 @@ def test_adjoint_small_vs_oracle(env, n_vis, n_pix):
     assert np.all(np.abs(got - ref) <= bound)
 
 
+FAM_ADJOINT = 3
+
+
+@pytest.mark.parametrize("ppl,block", [(p, b) for p in (1, 2, 4) for b in (64, 128, 256)])
+def test_adjoint_every_shape_group_edges(env, ppl, block):
+    """Every compiled tile shape at pixel counts on both sides of the 64-pixel
+    groups each wave owns and of the tile width (groups past the last pixel
+    are skipped): every pixel against the oracle, FP64 and F32C."""
+    torch, swv = env
+    ctx = swv.context()
+    small = 0   # size class of fewer than 2^20 rows
+    saved = ctx.tune_get(FAM_ADJOINT, small)
+    rng = np.random.default_rng(1000 * ppl + block)
+    n_vis = 777
+    u, v, w = (rng.uniform(-3e4, 3e4, n_vis) for _ in range(3))
+    y = models.random_complex(n_vis, rng)
+    U, V, Wd, Y = dev(u, torch), dev(v, torch), dev(w, torch), dev_c(y, torch)
+    tile = ppl * block
+    sizes = sorted({1, 63, 64, 65, tile - 1, tile, tile + 1, 2 * tile + 63, 3 * tile - 64})
+    try:
+        ctx.tune_set(FAM_ADJOINT, small, ppl, block)
+        for n_pix in sizes:
+            l, m, nm1 = _pixels(rng, n_pix, far=True)
+            L, M, N = dev(l, torch), dev(m, torch), dev(nm1, torch)
+            got = host(swv.adjoint(U, V, Wd, Y, L, M, N))
+            got32 = host(swv.adjoint(U, V, Wd, Y, L, M, N, prec="f32c"))
+            swv.synchronize()
+            ref = ov.adjoint(u, v, w, y, l, m, nm1)
+            bound = fp64_row_bound(l, m, nm1, u, v, w, np.abs(y))
+            assert np.all(np.abs(got - ref) <= bound), (ppl, block, n_pix)
+            e_max, _ = errors(got32, ref, np.abs(y).sum())
+            assert e_max <= TOL32, (ppl, block, n_pix, e_max)
+    finally:
+        ctx.tune_set(FAM_ADJOINT, small, *saved)
+
+
 def test_adjoint_cfg5_sampled_pixels(env, cfg5):
     torch, swv = env
     W, u, v, w, y, pix, pl, pm, pn = cfg5
