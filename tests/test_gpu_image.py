@@ -209,6 +209,40 @@ def test_grad_small_vs_oracle(env, alpha):
         assert np.all(np.abs(g - r) <= abs(alpha) * s)
 
 
+FAM_GRAD = 4
+
+
+@pytest.mark.parametrize("cpl", [1, 2, 4])
+def test_grad_every_shape_component_edges(env, cpl):
+    """Each components-per-lane shape at component counts on both sides of the
+    block widths it picks (128 .. 1024 threads) and of several tiles: every
+    component's three gradients against the oracle."""
+    torch, swv = env
+    ctx = swv.context()
+    small = 0   # size class of fewer than 2^20 rows
+    saved = ctx.tune_get(FAM_GRAD, small)
+    rng = np.random.default_rng(40 + cpl)
+    n = 613
+    u, v, w = (rng.uniform(-5e4, 5e4, n) for _ in range(3))
+    y = models.random_complex(n, rng)
+    U, V, Wd, Y = dev(u, torch), dev(v, torch), dev(w, torch), dev_c(y, torch)
+    sizes = sorted({1, 63, 65, 128 * cpl - 1, 128 * cpl + 1, 1024 * cpl, 1024 * cpl + 1,
+                    2048 * cpl + 63})
+    try:
+        ctx.tune_set(FAM_GRAD, small, cpl, 128)
+        for K in sizes:
+            l, m = rng.uniform(-0.03, 0.03, K), rng.uniform(-0.03, 0.03, K)
+            f = rng.lognormal(-3, 1, K)
+            got = [host(g) for g in swv.grad_direct(U, V, Wd, Y, dev(l, torch), dev(m, torch),
+                                                     dev(f, torch), alpha=-2.0)]
+            swv.synchronize()
+            ref = ov.grad_direct(u, v, w, y, l, m, f, alpha=-2.0)
+            for g, r, sc in zip(got, ref, _grad_scales(u, v, w, l, m, f, y)):
+                assert np.all(np.abs(g - r) <= 2.0 * sc), (cpl, K)
+    finally:
+        ctx.tune_set(FAM_GRAD, small, *saved)
+
+
 def test_grad_cfg5_sampled_components(env, cfg5):
     torch, swv = env
     W, u, v, w, y, *_ = cfg5
