@@ -36,7 +36,7 @@ PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop
 PEAK_FP32_TFLOPS = 157.3       # MI355X FP32 vector (packed)
 HBM_GBS = 8000.0
 TREE_LEVELS = (8, 9, 10)
-CPU_SHARE = 16                 # host cores of one GPU's share of the box
+CPU_SHARE = 16                 # host cores of one GPU's share of the host
 
 # Algorithmic flops per unit (FMA = 2, other arithmetic = 1; a rint counts 1):
 #   phase u l + v m + w (n-1): 1 mul + 2 FMA = 5; reduction rint + sub = 2;
