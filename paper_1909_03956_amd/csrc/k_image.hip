@@ -4,7 +4,8 @@
 //
 // Adjoint and gradients swap the roles of the direct kernel: lanes own the
 // outputs (pixels or components) and every lane of the wave walks the same
-// visibility rows, read with scalar loads.  The visibility axis is split
+// visibility rows (the adjoint reads them with scalar loads, the gradients
+// stage them through LDS).  The visibility axis is split
 // into fixed chunks; each (chunk, tile) block writes its partial sums, and a
 // second kernel adds the chunks in index order -- deterministic and free of
 // atomics.
