@@ -81,6 +81,17 @@ def tree_flops_per_row(st: dict) -> int:
             (st["n_leaves"] - roots) * FLOPS["tree_child"] + roots * FLOPS["tree_root"])
 
 
+def precision_errors(low, ref, scale: float) -> dict:
+    """A precision-form result against the FP64 form of the same call (device
+    tensors): E_max = max |low - ref| / scale (scale the sum of |flux| or of
+    |y|, as the tolerances are stated) and E_rms = ||low - ref|| / ||ref||."""
+    import torch
+    d = (low.to(torch.complex128) - ref).abs()
+    nrm = float(ref.abs().square().sum().sqrt())
+    return {"E_max_vs_fp64": float(f"{float(d.max()) / scale:.3e}"),
+            "E_rms_vs_fp64": float(f"{float(d.square().sum().sqrt()) / nrm:.3e}") if nrm else 0.0}
+
+
 def f32c_roofline(kind: str, terms_per_s: float, peaks: dict) -> dict:
     """Issue-time ceiling of an FP32-compensated kernel from the measured
     rates of the three units it uses: FP64 lane operations at half the FP64
@@ -946,6 +957,8 @@ def main():
     extra_routes["tree_speedup_f32c_over_fp64"] = round(
         extra_routes[f"tree_J{max(TREE_LEVELS)}_fp64"]["ms"] /
         extra_routes[f"tree_J{max(TREE_LEVELS)}_f32c"]["ms"], 3)
+    extra_routes[f"tree_J{max(TREE_LEVELS)}_f32c"].update(
+        precision_errors(vx, vt[max(TREE_LEVELS)], float(np.abs(f).sum())))
     # Eq. 16: the same model visibilities as the direct sum over the tree's
     # merged leaves at their pixel centres (swv_predict_tree_leaves)
     n_leaves = Tx.stats()["n_leaves"]
@@ -969,7 +982,8 @@ def main():
     # the adjoint's precision form on the step's residual (FP32 phasors,
     # products and Kahan sums; complex128 image)
     r_, _ = swv.residual_chi2(v_obs, v64, inv_s2, out=resid)
-    swv.adjoint(U, V, Wt, r_, PL, PM, PN, prec="f32c")
+    img64 = swv.adjoint(U, V, Wt, r_, PL, PM, PN)
+    img32 = swv.adjoint(U, V, Wt, r_, PL, PM, PN, prec="f32c")
     times = []
     for _ in range(max(3, args.steps // 2)):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -982,7 +996,8 @@ def main():
     extra_routes["adjoint_f32c"] = {
         "ms": round(ms, 4), "Gvis_terms_per_s": round(n_vis * n_pix / (ms * 1e-3) / 1e9, 2),
         "roofline": dict(f32c_roofline("adjoint_f32c", n_vis * n_pix / (ms * 1e-3), peaks),
-                         kernel="k_adjoint (SWV_F32C)")}
+                         kernel="k_adjoint (SWV_F32C)"),
+        **precision_errors(img32, img64, float(r_.abs().sum()))}
 
     # per-stage device times (median over steps)
     per = {s: [] for s in stages}
@@ -1014,6 +1029,8 @@ def main():
     routes["direct_fp64"]["hbm_GB_per_s"] = round(40 * n_vis / (med["direct_fp64"] * 1e-3) / 1e9, 2)
     routes["direct_f32c"]["hbm_GB_per_s"] = round(32 * n_vis / (med["direct_f32c"] * 1e-3) / 1e9, 2)
     routes["speedup_f32c_over_fp64"] = round(med["direct_fp64"] / med["direct_f32c"], 3)
+    # the last step's two direct sums, same inputs
+    routes["direct_f32c"].update(precision_errors(v32, v64, float(np.abs(f).sum())))
 
     # roofline of the dominant kernel (largest device time in the step)
     def tree_flops(J):
