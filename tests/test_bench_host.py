@@ -91,3 +91,17 @@ def test_cpu_baseline_record_on_a_small_sample():
     assert 1 <= b["cores"] <= bench.CPU_SHARE
     assert b["value"] > 0 and b["cpu_seconds"] > 0
     assert "64 seeded rows" in b["sample"]
+
+
+def test_precision_errors_of_a_known_difference():
+    """E_max over the stated scale and E_rms over the reference norm, with the
+    low-precision result widened before the difference."""
+    import numpy as np
+    import torch
+    ref = torch.tensor([3.0 + 4.0j, 0.0, 1.0j], dtype=torch.complex128)
+    low = (ref + torch.tensor([0.0, 0.5, -0.25j], dtype=torch.complex128)).to(torch.complex64)
+    e = bench.precision_errors(low, ref, scale=10.0)
+    assert e["E_max_vs_fp64"] == 0.05
+    want = float(np.sqrt(0.5 ** 2 + 0.25 ** 2) / np.sqrt(25.0 + 1.0))
+    assert abs(e["E_rms_vs_fp64"] - want) <= 1e-3 * want
+    assert bench.precision_errors(ref.to(torch.complex64), ref, 1.0)["E_max_vs_fp64"] == 0.0
