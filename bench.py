@@ -703,18 +703,20 @@ def run_threshold(swv, torch, np, dev, configs):
     return out
 
 
-def run_batched(swv, torch, np, dev, configs):
+def run_batched(swv, torch, np, dev, configs, peaks=None):
     """The batched workload: 64 channels x 4 pointings of the 256-antenna array,
     2M-8M unflagged rows each (1.29e9 in all), made on the device; one plan per
-    route (direct, tree) over all 256 instances, captured as a graph; each
-    graph launched once warm and then timed three times."""
+    route (direct FP64, direct FP32-compensated, tree) over all 256 instances,
+    captured as a graph; each graph launched once warm and then timed three
+    times."""
     B = configs.BatchedWorkload()
     ra, dec = configs.CFG2.ra_p, configs.CFG2.dec_p
 
     def D(x):
         return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
 
-    insts = {"direct": [], "tree": []}
+    insts = {"direct": [], "direct_f32c": [], "tree": []}
+    fluxsum = []
     keep = []
     rows = terms = leaves = tree_fl = 0
     t0 = time.perf_counter()
@@ -723,9 +725,14 @@ def run_batched(swv, torch, np, dev, configs):
         u, v, w = B.instance_uvw_torch(inst, kept, dev)
         out_d = torch.empty(kept.size, dtype=torch.complex128, device=dev)
         out_t = torch.empty(kept.size, dtype=torch.complex128, device=dev)
+        out_s = torch.empty(kept.size, dtype=torch.complex64, device=dev)
         tree = swv.Tree(inst.J, ra, dec, l, m, f)
-        insts["direct"].append(dict(route="direct", u=u, v=v, w=w, l=D(l), m=D(m), flux=D(f),
+        Ld, Md, Fd = D(l), D(m), D(f)
+        insts["direct"].append(dict(route="direct", u=u, v=v, w=w, l=Ld, m=Md, flux=Fd,
                                     out=out_d))
+        insts["direct_f32c"].append(dict(route="direct", prec="f32c", u=u, v=v, w=w, l=Ld,
+                                         m=Md, flux=Fd, out=out_s))
+        fluxsum.append(float(np.abs(f).sum()))
         insts["tree"].append(dict(route="tree", tree=tree, u=u, v=v, w=w, out=out_t))
         keep.append(tree)
         st = tree.stats()
@@ -740,7 +747,7 @@ def run_batched(swv, torch, np, dev, configs):
                        "20 km array, 2M-8M unflagged rows per instance, N_C 100-20,000, J 7-10",
            "instances": len(B.instances), "rows": rows, "terms": terms,
            "tree_nodes_x_rows": leaves}
-    for name in ("direct", "tree"):
+    for name in ("direct", "direct_f32c", "tree"):
         plan = swv.BatchPlan(insts[name])
         graph = plan.capture()
         graph.launch()
@@ -754,6 +761,22 @@ def run_batched(swv, torch, np, dev, configs):
             e1.synchronize()
             ts.append(e0.elapsed_time(e1))
         ms = float(np.median(ts))
+        if name == "direct_f32c":
+            # the precision form: its own three-unit ceiling, its speed-up and
+            # its error against the FP64 plan's visibilities, instance by instance
+            e_max = max(float((d32["out"].to(torch.complex128) - d64["out"]).abs().max()) / fs
+                        for d32, d64, fs in zip(insts["direct_f32c"], insts["direct"], fluxsum))
+            out[name] = {"ms": round(ms, 2),
+                         "Gvis_terms_per_s": round(terms / (ms * 1e-3) / 1e9, 1),
+                         "speedup_over_fp64": round(out["direct"]["ms"] / ms, 3),
+                         "E_max_vs_fp64": float(f"{e_max:.3e}"),
+                         "roofline": dict(f32c_roofline("direct_f32c", terms / (ms * 1e-3), peaks),
+                                          kernel="k_batch_direct (SWV_F32C)")
+                         if peaks else None}
+            log(f"batched {name}: {ms:.1f} ms")
+            graph.close()
+            plan.close()
+            continue
         fl = terms * FLOPS["direct_fp64"] if name == "direct" else tree_fl
         ach = fl / (ms * 1e-3) / 1e12
         out[name] = {"ms": round(ms, 2), "Gvis_terms_per_s": round(terms / (ms * 1e-3) / 1e9, 1),
@@ -829,7 +852,8 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     if args.batched:
-        print(json.dumps({"batched": run_batched(swv, torch, np, dev, configs)}), flush=True)
+        print(json.dumps({"batched": run_batched(swv, torch, np, dev, configs,
+                                                 swv.context(dev).measure_peaks())}), flush=True)
         return
     if args.precision:
         print(json.dumps({"precision": run_precision(swv, torch, np, dev, configs)}),
@@ -1109,7 +1133,7 @@ def main():
         out["precision_cfg3"] = run_precision(swv, torch, np, dev, configs, peaks)
     if not (args.no_cfg4 or args.profile):
         log("batched form on its own workload (cfg4) ...")
-        out["batched_cfg4"] = run_batched(swv, torch, np, dev, configs)
+        out["batched_cfg4"] = run_batched(swv, torch, np, dev, configs, peaks)
     if not (args.no_clean or args.profile):
         log("clean loop on the seven-source workload ...")
         out["clean_loop"] = run_clean(swv, torch, np, dev, configs)
