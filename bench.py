@@ -706,16 +706,16 @@ def run_threshold(swv, torch, np, dev, configs):
 def run_batched(swv, torch, np, dev, configs, peaks=None):
     """The batched workload: 64 channels x 4 pointings of the 256-antenna array,
     2M-8M unflagged rows each (1.29e9 in all), made on the device; one plan per
-    route (direct FP64, direct FP32-compensated, tree) over all 256 instances,
-    captured as a graph; each graph launched once warm and then timed three
-    times."""
+    route and precision (direct and tree, FP64 and FP32-compensated) over all
+    256 instances, captured as a graph; each graph launched once warm and then
+    timed three times."""
     B = configs.BatchedWorkload()
     ra, dec = configs.CFG2.ra_p, configs.CFG2.dec_p
 
     def D(x):
         return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
 
-    insts = {"direct": [], "direct_f32c": [], "tree": []}
+    insts = {"direct": [], "direct_f32c": [], "tree": [], "tree_f32c": []}
     fluxsum = []
     keep = []
     rows = terms = leaves = tree_fl = 0
@@ -726,6 +726,7 @@ def run_batched(swv, torch, np, dev, configs, peaks=None):
         out_d = torch.empty(kept.size, dtype=torch.complex128, device=dev)
         out_t = torch.empty(kept.size, dtype=torch.complex128, device=dev)
         out_s = torch.empty(kept.size, dtype=torch.complex64, device=dev)
+        out_ts = torch.empty(kept.size, dtype=torch.complex64, device=dev)
         tree = swv.Tree(inst.J, ra, dec, l, m, f)
         Ld, Md, Fd = D(l), D(m), D(f)
         insts["direct"].append(dict(route="direct", u=u, v=v, w=w, l=Ld, m=Md, flux=Fd,
@@ -734,6 +735,8 @@ def run_batched(swv, torch, np, dev, configs, peaks=None):
                                          m=Md, flux=Fd, out=out_s))
         fluxsum.append(float(np.abs(f).sum()))
         insts["tree"].append(dict(route="tree", tree=tree, u=u, v=v, w=w, out=out_t))
+        insts["tree_f32c"].append(dict(route="tree", prec="f32c", tree=tree, u=u, v=v, w=w,
+                                       out=out_ts))
         keep.append(tree)
         st = tree.stats()
         rows += kept.size
@@ -747,7 +750,7 @@ def run_batched(swv, torch, np, dev, configs, peaks=None):
                        "20 km array, 2M-8M unflagged rows per instance, N_C 100-20,000, J 7-10",
            "instances": len(B.instances), "rows": rows, "terms": terms,
            "tree_nodes_x_rows": leaves}
-    for name in ("direct", "direct_f32c", "tree"):
+    for name in ("direct", "direct_f32c", "tree", "tree_f32c"):
         plan = swv.BatchPlan(insts[name])
         graph = plan.capture()
         graph.launch()
@@ -761,18 +764,21 @@ def run_batched(swv, torch, np, dev, configs, peaks=None):
             e1.synchronize()
             ts.append(e0.elapsed_time(e1))
         ms = float(np.median(ts))
-        if name == "direct_f32c":
-            # the precision form: its own three-unit ceiling, its speed-up and
-            # its error against the FP64 plan's visibilities, instance by instance
+        if name.endswith("_f32c"):
+            # the precision form: its speed-up and its error against the FP64
+            # plan's visibilities, instance by instance; the direct sum also
+            # against its own three-unit ceiling
+            base = name[:-len("_f32c")]
             e_max = max(float((d32["out"].to(torch.complex128) - d64["out"]).abs().max()) / fs
-                        for d32, d64, fs in zip(insts["direct_f32c"], insts["direct"], fluxsum))
+                        for d32, d64, fs in zip(insts[name], insts[base], fluxsum))
             out[name] = {"ms": round(ms, 2),
                          "Gvis_terms_per_s": round(terms / (ms * 1e-3) / 1e9, 1),
-                         "speedup_over_fp64": round(out["direct"]["ms"] / ms, 3),
-                         "E_max_vs_fp64": float(f"{e_max:.3e}"),
-                         "roofline": dict(f32c_roofline("direct_f32c", terms / (ms * 1e-3), peaks),
-                                          kernel="k_batch_direct (SWV_F32C)")
-                         if peaks else None}
+                         "speedup_over_fp64": round(out[base]["ms"] / ms, 3),
+                         "E_max_vs_fp64": float(f"{e_max:.3e}")}
+            if base == "direct" and peaks:
+                out[name]["roofline"] = dict(
+                    f32c_roofline("direct_f32c", terms / (ms * 1e-3), peaks),
+                    kernel="k_batch_direct (SWV_F32C)")
             log(f"batched {name}: {ms:.1f} ms")
             graph.close()
             plan.close()
