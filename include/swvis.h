@@ -256,8 +256,9 @@ int swv_pixel_centres(int J, double ra_p, double dec_p, int64_t n, const int64_t
 
 /* Sorted level-J pixels whose centres lie within `radius` radians of the
  * phase centre, with their centres (l, m, n - 1).  At most `cap` entries are
- * written to the HOST arrays; *n_out receives the full count (call with
- * cap = 0 to size the arrays). */
+ * written to the HOST arrays, all four of which are required when cap > 0
+ * (SWV_EINVAL otherwise); *n_out receives the full count (call with cap = 0
+ * and null arrays to size them). */
 int swv_pixels_in_disk(int J, double ra_p, double dec_p, double radius, int64_t cap,
                        int64_t* pix, double* l, double* m, double* nm1, int64_t* n_out);
 

@@ -8,6 +8,8 @@
 
 #include "swvis.h"
 
+static const double kPi = 3.14159265358979323846;
+
 #define CHECK(cond, what)                                           \
     do {                                                            \
         if (!(cond)) {                                              \
@@ -40,7 +42,77 @@ int main(void) {
     double lf[2];
     CHECK(swv_tree_leaves(t, NULL, NULL, NULL, NULL, lf) == SWV_OK &&
               fabs(lf[0] + lf[1] - 3.5) < 1e-15, "leaf fluxes");
+    /* level 1 carries the whole flux: lambda_j A_j = sum of lambda_{j+1} A_{j+1}
+       (Eq. 9 with A_j = 4 A_{j+1}), and level J has no children */
+    const double A1 = 4.0 * kPi / 12.0;
+    int64_t pix1[12];
+    double lam1[12], lamJ[2];
+    int32_t maskJ[2];
+    CHECK(st.n_nodes[1] >= 1 && st.n_nodes[1] <= 12 &&
+              swv_tree_level(t, 1, pix1, NULL, lam1, NULL) == SWV_OK, "tree level 1");
+    double s1 = 0.0;
+    for (int k = 0; k < st.n_nodes[1]; ++k) s1 += lam1[k] * A1;
+    CHECK(fabs(s1 - 3.5) < 1e-13, "level-1 flux");
+    CHECK(swv_tree_level(t, 12, NULL, maskJ, lamJ, NULL) == SWV_OK && maskJ[0] == 0 &&
+              maskJ[1] == 0, "leaf level masks");
+
+    /* new leaf fluxes on the same pixels */
+    const double nf[2] = {2.0, 4.0};
+    CHECK(swv_tree_set_flux(t, nf) == SWV_OK && swv_tree_leaves(t, NULL, NULL, NULL, NULL, lf) ==
+              SWV_OK && lf[0] == 2.0 && lf[1] == 4.0, "set flux");
+    CHECK(swv_tree_level(t, 1, NULL, NULL, lam1, NULL) == SWV_OK, "level 1 after set flux");
+    s1 = 0.0;
+    for (int k = 0; k < st.n_nodes[1]; ++k) s1 += lam1[k] * A1;
+    CHECK(fabs(s1 - 6.0) < 1e-13, "level-1 flux after set flux");
+
+    /* thresholding: every coefficient kept, none kept, and an empty prune */
+    swv_tree all = NULL, none = NULL, pr = NULL;
+    int64_t kept[64], n_kept = -1, n_coeffs = -1;
+    CHECK(swv_tree_threshold(t, 1.0, &all) == SWV_OK && all, "threshold 1");
+    CHECK(swv_tree_kept(all, 64, kept, &n_kept, &n_coeffs) == SWV_OK &&
+              n_coeffs == 3 * st.n_internal && n_kept == n_coeffs, "all kept");
+    int increasing = 1;
+    for (int64_t k = 1; k < n_kept; ++k) increasing &= kept[k] > kept[k - 1];
+    CHECK(increasing, "kept indices increase");
+    CHECK(swv_tree_threshold(t, 0.0, &none) == SWV_OK &&
+              swv_tree_kept(none, 64, kept, &n_kept, &n_coeffs) == SWV_OK && n_kept == 0,
+          "none kept");
+    swv_tree_stats_t sn, sp;
+    CHECK(swv_tree_stats(none, &sn) == SWV_OK && sn.n_internal == 0 &&
+              sn.n_leaves == st.n_nodes[1], "collapsed to level 1");
+    CHECK(swv_tree_prune(t, 0, NULL, &pr) == SWV_OK && swv_tree_stats(pr, &sp) == SWV_OK &&
+              sp.n_leaves == sn.n_leaves && sp.n_records == sn.n_records, "empty prune");
+    CHECK(swv_tree_leaves(none, NULL, NULL, NULL, NULL, lf) == SWV_ENOTSUP,
+          "leaves of a thresholded tree refused");
+    swv_tree_destroy(pr);
+    swv_tree_destroy(none);
+    swv_tree_destroy(all);
     CHECK(swv_tree_destroy(t) == SWV_OK, "tree destroy");
+
+    /* the level-9 pixels within 2 deg: sized, filled, sorted, inside the disk */
+    const double rad = 2.0 * kPi / 180.0;
+    int64_t n_disk = -1;
+    CHECK(swv_pixels_in_disk(9, ra, dec, rad, 0, NULL, NULL, NULL, NULL, &n_disk) == SWV_OK &&
+              n_disk > 0, "disk count");
+    int64_t* dp = malloc(sizeof(int64_t) * (size_t)n_disk);
+    double* dl = malloc(sizeof(double) * (size_t)n_disk);
+    double* dm = malloc(sizeof(double) * (size_t)n_disk);
+    double* dn = malloc(sizeof(double) * (size_t)n_disk);
+    int64_t n_again = -1;
+    CHECK(dp && dl && dm && dn &&
+              swv_pixels_in_disk(9, ra, dec, rad, n_disk, dp, dl, dm, dn, &n_again) == SWV_OK &&
+              n_again == n_disk,
+          "disk fill");
+    int inside = 1, sorted = 1;
+    for (int64_t k = 0; k < n_disk; ++k) {
+        inside &= 1.0 + dn[k] >= cos(rad) - 1e-15;
+        if (k) sorted &= dp[k] > dp[k - 1];
+    }
+    free(dp);
+    free(dl);
+    free(dm);
+    free(dn);
+    CHECK(inside && sorted, "disk pixels sorted and inside");
 
     /* cross reference of a small image grid, and the tree from its pixels */
     int64_t xref[12];
