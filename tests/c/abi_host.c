@@ -67,16 +67,23 @@ int main(void) {
 
     /* thresholding: every coefficient kept, none kept, and an empty prune */
     swv_tree all = NULL, none = NULL, pr = NULL;
-    int64_t kept[64], n_kept = -1, n_coeffs = -1;
+    int64_t n_kept = -1, n_coeffs = -1;
     CHECK(swv_tree_threshold(t, 1.0, &all) == SWV_OK && all, "threshold 1");
-    CHECK(swv_tree_kept(all, 64, kept, &n_kept, &n_coeffs) == SWV_OK &&
+    /* sized by a first call with cap = 0 */
+    CHECK(swv_tree_kept(all, 0, NULL, &n_kept, &n_coeffs) == SWV_OK &&
               n_coeffs == 3 * st.n_internal && n_kept == n_coeffs, "all kept");
+    int64_t* kept = malloc(sizeof(int64_t) * (size_t)n_kept);
+    int64_t n_again = -1;
+    CHECK(kept && swv_tree_kept(all, n_kept, kept, &n_again, &n_coeffs) == SWV_OK &&
+              n_again == n_kept, "kept indices");
     int increasing = 1;
     for (int64_t k = 1; k < n_kept; ++k) increasing &= kept[k] > kept[k - 1];
-    CHECK(increasing, "kept indices increase");
+    CHECK(increasing && kept[0] == 0 && kept[n_kept - 1] == n_coeffs - 1,
+          "kept indices increase");
     CHECK(swv_tree_threshold(t, 0.0, &none) == SWV_OK &&
-              swv_tree_kept(none, 64, kept, &n_kept, &n_coeffs) == SWV_OK && n_kept == 0,
+              swv_tree_kept(none, n_kept, kept, &n_again, &n_coeffs) == SWV_OK && n_again == 0,
           "none kept");
+    free(kept);
     swv_tree_stats_t sn, sp;
     CHECK(swv_tree_stats(none, &sn) == SWV_OK && sn.n_internal == 0 &&
               sn.n_leaves == st.n_nodes[1], "collapsed to level 1");
@@ -98,7 +105,7 @@ int main(void) {
     double* dl = malloc(sizeof(double) * (size_t)n_disk);
     double* dm = malloc(sizeof(double) * (size_t)n_disk);
     double* dn = malloc(sizeof(double) * (size_t)n_disk);
-    int64_t n_again = -1;
+    n_again = -1;
     CHECK(dp && dl && dm && dn &&
               swv_pixels_in_disk(9, ra, dec, rad, n_disk, dp, dl, dm, dn, &n_again) == SWV_OK &&
               n_again == n_disk,
