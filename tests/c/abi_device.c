@@ -4,11 +4,14 @@
  * component equals its direct sum and its leaf sum, the adjoint of V = 1 at
  * the centre pixel is the row count (also without allocation), the residual
  * against a zero model is V with chi^2 = N / 2, and the gradients of a unit
- * source at the centre are (N, 0, 0). */
+ * source at the centre are (N, 0, 0); a batched plan over two direct
+ * instances and a tree instance, run and replayed as a captured graph, gives
+ * the single calls' bits. */
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include <hip/hip_runtime_api.h>
 
@@ -141,6 +144,72 @@ int main(void) {
     hipFree(d_r);
     hipFree(d_chi2);
     hipFree(d_g);
+    /* batched: two direct instances of different lengths and one tree instance in
+       one plan; the run and a replay of its captured graph give the single calls'
+       bits */
+    {
+        const double hb[9] = {0.013, -0.02, -0.004, 0.01, 0.7, 1.3, 0.0, 0.0, 1.0};
+        const int64_t nb = N - 1234, off = 1000;
+        double *d_cb = NULL, *d_o = NULL, *d_s = NULL;
+        CHECK(hipMalloc((void**)&d_cb, sizeof hb) == hipSuccess &&
+                  hipMalloc((void**)&d_o, 3 * 16 * N) == hipSuccess &&
+                  hipMalloc((void**)&d_s, 3 * 16 * N) == hipSuccess &&
+                  hipMemcpy(d_cb, hb, sizeof hb, hipMemcpyHostToDevice) == hipSuccess,
+              "batched buffers");
+        swv_tree tb = NULL;
+        CHECK(swv_tree_build(12, ra, dec, 2, hb, hb + 2, hb + 4, &tb) == SWV_OK, "batched tree");
+        CHECK(swv_predict_direct(ctx, N, u, v, w, 2, d_cb, d_cb + 2, d_cb + 4, -1, SWV_FP64,
+                                 d_s) == SWV_OK &&
+                  swv_predict_direct(ctx, nb, u + off, v + off, w + off, 1, d_cb + 6, d_cb + 7,
+                                     d_cb + 8, -1, SWV_FP64, d_s + 2 * N) == SWV_OK &&
+                  swv_predict_tree(ctx, tb, N, u, v, w, -1, SWV_FP64, d_s + 4 * N) == SWV_OK,
+              "single calls");
+        swv_instance in[3];
+        memset(in, 0, sizeof in);
+        in[0].route = SWV_ROUTE_DIRECT; in[0].prec = SWV_FP64; in[0].sign = -1;
+        in[0].n_vis = N; in[0].u = u; in[0].v = v; in[0].w = w;
+        in[0].n_comp = 2; in[0].l = d_cb; in[0].m = d_cb + 2; in[0].flux = d_cb + 4;
+        in[0].vis_out = d_o;
+        in[1] = in[0];
+        in[1].n_vis = nb; in[1].u = u + off; in[1].v = v + off; in[1].w = w + off;
+        in[1].n_comp = 1; in[1].l = d_cb + 6; in[1].m = d_cb + 7; in[1].flux = d_cb + 8;
+        in[1].vis_out = d_o + 2 * N;
+        in[2] = in[0];
+        in[2].route = SWV_ROUTE_TREE; in[2].n_comp = 0; in[2].l = in[2].m = in[2].flux = NULL;
+        in[2].tree = tb; in[2].vis_out = d_o + 4 * N;
+        swv_plan plan = NULL;
+        swv_plan_stats_t ps;
+        CHECK(swv_batch_plan(ctx, 3, in, &plan) == SWV_OK && plan &&
+                  swv_plan_stats(plan, &ps) == SWV_OK && ps.n_instances == 3 && ps.n_items > 0,
+              "batch plan");
+        double* a = (double*)malloc(3 * 16 * N);
+        double* b = (double*)malloc(3 * 16 * N);
+        const size_t sizes[3] = {16 * (size_t)N, 16 * (size_t)nb, 16 * (size_t)N};
+        CHECK(swv_batch_run(plan) == SWV_OK && swv_ctx_synchronize(ctx) == SWV_OK &&
+                  hipMemcpy(a, d_o, 3 * 16 * N, hipMemcpyDeviceToHost) == hipSuccess &&
+                  hipMemcpy(b, d_s, 3 * 16 * N, hipMemcpyDeviceToHost) == hipSuccess,
+              "batch run");
+        int same = 1;
+        for (int k = 0; k < 3; ++k) same &= memcmp(a + 2 * N * k, b + 2 * N * k, sizes[k]) == 0;
+        CHECK(same, "batched equals single calls bit for bit");
+        swv_graph g = NULL;
+        CHECK(hipMemset(d_o, 0, 3 * 16 * N) == hipSuccess && hipDeviceSynchronize() == hipSuccess &&
+                  swv_graph_capture(plan, &g) == SWV_OK && g &&
+                  swv_graph_launch(g) == SWV_OK && swv_ctx_synchronize(ctx) == SWV_OK &&
+                  hipMemcpy(a, d_o, 3 * 16 * N, hipMemcpyDeviceToHost) == hipSuccess,
+              "graph capture and replay");
+        same = 1;
+        for (int k = 0; k < 3; ++k) same &= memcmp(a + 2 * N * k, b + 2 * N * k, sizes[k]) == 0;
+        CHECK(same, "graph replay equals single calls bit for bit");
+        CHECK(swv_graph_destroy(g) == SWV_OK && swv_plan_destroy(plan) == SWV_OK &&
+                  swv_tree_destroy(tb) == SWV_OK,
+              "batched objects destroyed");
+        free(a);
+        free(b);
+        hipFree(d_cb);
+        hipFree(d_o);
+        hipFree(d_s);
+    }
     CHECK(swv_ctx_destroy(ctx) == SWV_OK, "context destroy");
     hipFree(d_uvw);
     hipFree(d_c);
