@@ -73,11 +73,11 @@ __device__ __forceinline__ void adjoint_lane(
     const auto* V = uniform_ptr(v + j0);
     const auto* W = uniform_ptr(w + j0);
     const auto* Y = uniform_ptr(y + j0);
+    if constexpr (PREC == SWV_FP64) {
 #pragma unroll 4
-    for (int j = 0; j < nrow; ++j) {
-        const double uj = U[j], vj = V[j], wj = W[j];
-        const double yr = Y[j].x, yi = Y[j].y;
-        if constexpr (PREC == SWV_FP64) {
+        for (int j = 0; j < nrow; ++j) {
+            const double uj = U[j], vj = V[j], wj = W[j];
+            const double yr = Y[j].x, yi = Y[j].y;
             const double y4r = 4.0 * sgn * yr, y4i = 4.0 * sgn * yi;
 #pragma unroll
             for (int i = 0; i < G; ++i) {
@@ -88,16 +88,50 @@ __device__ __forceinline__ void adjoint_lane(
                 ai[i] = fma(c, yi, ai[i]);
                 ai[i] = fma(-q, y4r, ai[i]);
             }
-        } else {
+        }
+    } else {
+        // rows in pairs: a pair's two terms are added in FP32 and the pair
+        // enters the compensated sum, so each row costs half a Kahan update
+        // (the extra rounding is at most 2^-24 of the pair); an odd last row
+        // enters alone
+        const auto term = [&](double uj, double vj, double wj, float fyr, float fyi,
+                              float fsyr, float fsyi, int i, float& xr, float& xi) {
+            const float r = (float)reduced_phase(uj, vj, wj, L[i], M[i], N[i]);
+            float c, s;
+            cis2pi_f32(r, c, s);
+            xr = fmaf(c, fyr, s * fsyi);
+            xi = fmaf(c, fyi, -(s * fsyr));
+        };
+        const int npair = nrow & ~1;
+#pragma unroll 2
+        for (int j = 0; j < npair; j += 2) {
+            const double u0 = U[j], v0 = V[j], w0 = W[j], yr0 = Y[j].x, yi0 = Y[j].y;
+            const double u1 = U[j + 1], v1 = V[j + 1], w1 = W[j + 1];
+            const double yr1 = Y[j + 1].x, yi1 = Y[j + 1].y;
+            const float fyr0 = (float)yr0, fyi0 = (float)yi0;
+            const float fsyr0 = (float)(sgn * yr0), fsyi0 = (float)(sgn * yi0);
+            const float fyr1 = (float)yr1, fyi1 = (float)yi1;
+            const float fsyr1 = (float)(sgn * yr1), fsyi1 = (float)(sgn * yi1);
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                float xr0, xi0, xr1, xi1;
+                term(u0, v0, w0, fyr0, fyi0, fsyr0, fsyi0, i, xr0, xi0);
+                term(u1, v1, w1, fyr1, fyi1, fsyr1, fsyi1, i, xr1, xi1);
+                kahan_add(xr0 + xr1, sr[i], cr[i]);
+                kahan_add(xi0 + xi1, si[i], ci[i]);
+            }
+        }
+        if (npair < nrow) {
+            const int j = npair;
+            const double yr = Y[j].x, yi = Y[j].y;
             const float fyr = (float)yr, fyi = (float)yi;
             const float fsyr = (float)(sgn * yr), fsyi = (float)(sgn * yi);
 #pragma unroll
             for (int i = 0; i < G; ++i) {
-                const float r = (float)reduced_phase(uj, vj, wj, L[i], M[i], N[i]);
-                float c, s;
-                cis2pi_f32(r, c, s);
-                kahan_add(fmaf(c, fyr, s * fsyi), sr[i], cr[i]);
-                kahan_add(fmaf(c, fyi, -(s * fsyr)), si[i], ci[i]);
+                float xr, xi;
+                term(U[j], V[j], W[j], fyr, fyi, fsyr, fsyi, i, xr, xi);
+                kahan_add(xr, sr[i], cr[i]);
+                kahan_add(xi, si[i], ci[i]);
             }
         }
     }
