@@ -62,13 +62,14 @@ PHASOR_FLOPS = 34
 # Algorithmic operations per term of the FP32-compensated forms, by the unit
 # that executes them: the FP64 phase and its exact reduction (1 mul, 2 FMA,
 # rint, sub); the conversion of r to FP32; the hardware sine and cosine; the
-# FP32 side -- direct: per re/im one FMA (the product I c, less the
-# compensation) and 3 additions of the Kahan update; adjoint: per re/im a
-# product and an FMA (conj(e) y), and for each pair of rows one addition and
-# the 4 operations of a Kahan update (half of 5 per row).
+# FP32 side, where terms enter the Kahan sums in pairs -- direct: per re/im a
+# pair's two FMAs (the products I c, less the compensation) and the 3
+# additions of a Kahan step, 5 per pair; adjoint: per re/im a pair's four FMAs
+# (conj(e) y of both rows, less the compensation) and the 3 additions, 7 per
+# pair.
 F32C_OPS = {
-    "direct_f32c": {"f64": 5, "cvt": 1, "trans": 2, "f32": 8},
-    "adjoint_f32c": {"f64": 5, "cvt": 1, "trans": 2, "f32": 9},
+    "direct_f32c": {"f64": 5, "cvt": 1, "trans": 2, "f32": 5},
+    "adjoint_f32c": {"f64": 5, "cvt": 1, "trans": 2, "f32": 7},
 }
 
 

@@ -90,22 +90,20 @@ __device__ __forceinline__ void cis2pi_f32(float r, float& c, float& s) {
     s = __builtin_amdgcn_sinf(r);
 }
 
-// Kahan-compensated accumulation of the product a b into (sum, comp); the
-// product is rounded once, inside the FMA that removes the compensation.
-__host__ __device__ __forceinline__ void kahan_add_prod(float a, float b, float& sum,
-                                                        float& comp) {
-    const float y = fmaf(a, b, -comp);
+// One Kahan step: y is the next addend with the running compensation already
+// subtracted; the rounding error of sum + y becomes the new compensation (the
+// compensated total is sum - comp).
+__host__ __device__ __forceinline__ void kahan_step(float y, float& sum, float& comp) {
     const float t = sum + y;
     comp = (t - sum) - y;
     sum = t;
 }
 
-// Kahan-compensated accumulation of x into (sum, comp).
-__host__ __device__ __forceinline__ void kahan_add(float x, float& sum, float& comp) {
-    const float y = x - comp;
-    const float t = sum + y;
-    comp = (t - sum) - y;
-    sum = t;
+// Kahan-compensated accumulation of the product a b into (sum, comp); the
+// product is rounded once, inside the FMA that removes the compensation.
+__host__ __device__ __forceinline__ void kahan_add_prod(float a, float b, float& sum,
+                                                        float& comp) {
+    kahan_step(fmaf(a, b, -comp), sum, comp);
 }
 
 }  // namespace swv

@@ -87,8 +87,28 @@ __device__ __forceinline__ void direct_rows_f32c(const int64_t (&j)[VPL], int64_
         sr[i] = cr[i] = si[i] = ci[i] = 0.0f;
     }
     const auto* cp = uniform_ptr(comp);
-    for (int k = 0; k < n_comp; ++k) {
-        const Comp cur{cp[k].l, cp[k].m, cp[k].nm1, cp[k].I};
+    // components in pairs: the pair's two products and the running
+    // compensation meet in two FMAs, then one Kahan step, so a component costs
+    // half a step (the pair's roundings stay within 2 x 2^-24 of its terms);
+    // an odd last component enters alone
+    const int npair = n_comp & ~1;
+    for (int k = 0; k < npair; k += 2) {
+        const Comp a{cp[k].l, cp[k].m, cp[k].nm1, cp[k].I};
+        const Comp b{cp[k + 1].l, cp[k + 1].m, cp[k + 1].nm1, cp[k + 1].I};
+        const float aI = (float)a.I, bI = (float)b.I;
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) {
+            const float ra = (float)reduced_phase(U[i], V[i], W[i], a.l, a.m, a.nm1);
+            const float rb = (float)reduced_phase(U[i], V[i], W[i], b.l, b.m, b.nm1);
+            float ca, sa, cb, sb;
+            cis2pi_f32(ra, ca, sa);
+            cis2pi_f32(rb, cb, sb);
+            kahan_step(fmaf(aI, ca, fmaf(bI, cb, -cr[i])), sr[i], cr[i]);
+            kahan_step(fmaf(aI, sa, fmaf(bI, sb, -ci[i])), si[i], ci[i]);
+        }
+    }
+    if (npair < n_comp) {
+        const Comp cur{cp[npair].l, cp[npair].m, cp[npair].nm1, cp[npair].I};
         const float cI = (float)cur.I;
 #pragma unroll
         for (int i = 0; i < VPL; ++i) {

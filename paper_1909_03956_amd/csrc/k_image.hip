@@ -90,17 +90,14 @@ __device__ __forceinline__ void adjoint_lane(
             }
         }
     } else {
-        // rows in pairs: a pair's two terms are added in FP32 and the pair
-        // enters the compensated sum, so each row costs half a Kahan update
-        // (the extra rounding is at most 2^-24 of the pair); an odd last row
-        // enters alone
-        const auto term = [&](double uj, double vj, double wj, float fyr, float fyi,
-                              float fsyr, float fsyi, int i, float& xr, float& xi) {
-            const float r = (float)reduced_phase(uj, vj, wj, L[i], M[i], N[i]);
-            float c, s;
-            cis2pi_f32(r, c, s);
-            xr = fmaf(c, fyr, s * fsyi);
-            xi = fmaf(c, fyi, -(s * fsyr));
+        // rows in pairs: the pair's four products and the running compensation
+        // meet in one chain of FMAs, then one Kahan step, so a row costs half a
+        // step (the chain's roundings stay within a few 2^-24 of the pair's
+        // terms); an odd last row enters alone
+        // sgn is +-1, so fsg * (float)y is (float)(sgn * y) bit for bit
+        const float fsg = (float)sgn;
+        const auto cis = [&](double uj, double vj, double wj, int i, float& c, float& s) {
+            cis2pi_f32((float)reduced_phase(uj, vj, wj, L[i], M[i], N[i]), c, s);
         };
         const int npair = nrow & ~1;
 #pragma unroll 2
@@ -109,29 +106,31 @@ __device__ __forceinline__ void adjoint_lane(
             const double u1 = U[j + 1], v1 = V[j + 1], w1 = W[j + 1];
             const double yr1 = Y[j + 1].x, yi1 = Y[j + 1].y;
             const float fyr0 = (float)yr0, fyi0 = (float)yi0;
-            const float fsyr0 = (float)(sgn * yr0), fsyi0 = (float)(sgn * yi0);
+            const float fsyr0 = fsg * fyr0, fsyi0 = fsg * fyi0;
             const float fyr1 = (float)yr1, fyi1 = (float)yi1;
-            const float fsyr1 = (float)(sgn * yr1), fsyi1 = (float)(sgn * yi1);
+            const float fsyr1 = fsg * fyr1, fsyi1 = fsg * fyi1;
 #pragma unroll
             for (int i = 0; i < G; ++i) {
-                float xr0, xi0, xr1, xi1;
-                term(u0, v0, w0, fyr0, fyi0, fsyr0, fsyi0, i, xr0, xi0);
-                term(u1, v1, w1, fyr1, fyi1, fsyr1, fsyi1, i, xr1, xi1);
-                kahan_add(xr0 + xr1, sr[i], cr[i]);
-                kahan_add(xi0 + xi1, si[i], ci[i]);
+                float c0, s0, c1, s1;
+                cis(u0, v0, w0, i, c0, s0);
+                cis(u1, v1, w1, i, c1, s1);
+                kahan_step(fmaf(c0, fyr0, fmaf(s0, fsyi0, fmaf(c1, fyr1, fmaf(s1, fsyi1, -cr[i])))),
+                           sr[i], cr[i]);
+                kahan_step(fmaf(c0, fyi0, fmaf(-s0, fsyr0, fmaf(c1, fyi1, fmaf(-s1, fsyr1, -ci[i])))),
+                           si[i], ci[i]);
             }
         }
         if (npair < nrow) {
             const int j = npair;
             const double yr = Y[j].x, yi = Y[j].y;
             const float fyr = (float)yr, fyi = (float)yi;
-            const float fsyr = (float)(sgn * yr), fsyi = (float)(sgn * yi);
+            const float fsyr = fsg * fyr, fsyi = fsg * fyi;
 #pragma unroll
             for (int i = 0; i < G; ++i) {
-                float xr, xi;
-                term(U[j], V[j], W[j], fyr, fyi, fsyr, fsyi, i, xr, xi);
-                kahan_add(xr, sr[i], cr[i]);
-                kahan_add(xi, si[i], ci[i]);
+                float c, s;
+                cis(U[j], V[j], W[j], i, c, s);
+                kahan_step(fmaf(c, fyr, fmaf(s, fsyi, -cr[i])), sr[i], cr[i]);
+                kahan_step(fmaf(c, fyi, fmaf(-s, fsyr, -ci[i])), si[i], ci[i]);
             }
         }
     }
