@@ -60,16 +60,16 @@ FLOPS = {
 PHASOR_FLOPS = 34
 
 # Algorithmic operations per term of the FP32-compensated forms, by the unit
-# that executes them: the FP64 phase and its exact reduction (1 mul, 2 FMA,
-# rint, sub); the conversion of r to FP32; the hardware sine and cosine; the
+# that executes them: the FP64 phase and its exact reduction to [0, 1) (1 mul,
+# 2 FMA, fract); the conversion of r to FP32; the hardware sine and cosine; the
 # FP32 side, where terms enter the Kahan sums in pairs -- direct: per re/im a
 # pair's two FMAs (the products I c, less the compensation) and the 3
 # additions of a Kahan step, 5 per pair; adjoint: per re/im a pair's four FMAs
 # (conj(e) y of both rows, less the compensation) and the 3 additions, 7 per
 # pair.
 F32C_OPS = {
-    "direct_f32c": {"f64": 5, "cvt": 1, "trans": 2, "f32": 5},
-    "adjoint_f32c": {"f64": 5, "cvt": 1, "trans": 2, "f32": 7},
+    "direct_f32c": {"f64": 4, "cvt": 1, "trans": 2, "f32": 5},
+    "adjoint_f32c": {"f64": 4, "cvt": 1, "trans": 2, "f32": 7},
 }
 
 

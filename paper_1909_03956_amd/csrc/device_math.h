@@ -29,6 +29,16 @@ __host__ __device__ __forceinline__ double reduced_phase(double u, double v, dou
     return ph - rint(ph);
 }
 
+// The same phase reduced to [0, 1) by the hardware fract, one FP64
+// instruction against rint and a subtraction, and exact as well (|phase| is
+// far below 2^52). For the FP32 phasor only: its sine and cosine take any
+// angle in [-256, 256] revolutions, and the conversion of r to FP32 then
+// rounds by at most 2^-25 cycles.
+__device__ __forceinline__ double fract_phase(double u, double v, double w, double l, double m,
+                                              double nm1) {
+    return __builtin_amdgcn_fract(fma(u, l, fma(v, m, w * nm1)));
+}
+
 // Fused multiply-add as one 3-operand v_fma_f64 on VGPRs: the same rounding
 // as fma(), but never the two-address form (a copy of the addend into the
 // destination, then v_fmac_f64) that the compiler picks when the addend is a

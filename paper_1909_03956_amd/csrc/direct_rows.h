@@ -98,8 +98,8 @@ __device__ __forceinline__ void direct_rows_f32c(const int64_t (&j)[VPL], int64_
         const float aI = (float)a.I, bI = (float)b.I;
 #pragma unroll
         for (int i = 0; i < VPL; ++i) {
-            const float ra = (float)reduced_phase(U[i], V[i], W[i], a.l, a.m, a.nm1);
-            const float rb = (float)reduced_phase(U[i], V[i], W[i], b.l, b.m, b.nm1);
+            const float ra = (float)fract_phase(U[i], V[i], W[i], a.l, a.m, a.nm1);
+            const float rb = (float)fract_phase(U[i], V[i], W[i], b.l, b.m, b.nm1);
             float ca, sa, cb, sb;
             cis2pi_f32(ra, ca, sa);
             cis2pi_f32(rb, cb, sb);
@@ -112,7 +112,7 @@ __device__ __forceinline__ void direct_rows_f32c(const int64_t (&j)[VPL], int64_
         const float cI = (float)cur.I;
 #pragma unroll
         for (int i = 0; i < VPL; ++i) {
-            const float r = (float)reduced_phase(U[i], V[i], W[i], cur.l, cur.m, cur.nm1);
+            const float r = (float)fract_phase(U[i], V[i], W[i], cur.l, cur.m, cur.nm1);
             float c, s;
             cis2pi_f32(r, c, s);
             kahan_add_prod(cI, c, sr[i], cr[i]);

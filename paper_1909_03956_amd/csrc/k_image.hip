@@ -97,7 +97,7 @@ __device__ __forceinline__ void adjoint_lane(
         // sgn is +-1, so fsg * (float)y is (float)(sgn * y) bit for bit
         const float fsg = (float)sgn;
         const auto cis = [&](double uj, double vj, double wj, int i, float& c, float& s) {
-            cis2pi_f32((float)reduced_phase(uj, vj, wj, L[i], M[i], N[i]), c, s);
+            cis2pi_f32((float)fract_phase(uj, vj, wj, L[i], M[i], N[i]), c, s);
         };
         const int npair = nrow & ~1;
 #pragma unroll 2

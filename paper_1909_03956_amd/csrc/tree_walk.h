@@ -212,13 +212,13 @@ template <bool VOP3, bool F32>
 __device__ __forceinline__ void leaf_wave(RecPtr rec, unsigned me, double u, double v, double w,
                                           double& er, double& ei) {
     const RecPtr q = rec_at(rec, me);
-    const double r = reduced_phase(u, v, w, q->a, q->b, q->c);
     if constexpr (F32) {
         float c32, s32;
-        cis2pi_f32((float)r, c32, s32);
+        cis2pi_f32((float)fract_phase(u, v, w, q->a, q->b, q->c), c32, s32);
         er = (double)c32;
         ei = 0.25 * (double)s32;
     } else {
+        const double r = reduced_phase(u, v, w, q->a, q->b, q->c);
         double c, q;
         if constexpr (VOP3)
             cis2pi_q_vop3(r, c, q);

@@ -5,8 +5,9 @@ The oracle reduces the phase exactly; the GPU rounds phi ~ 1e4 cycles in
 FP64 (one ulp ~ 2e-12 cycles), so per-term phase errors are ~1e-12 rad and
 average down over components.
 Tolerance (FP32-compensated): E_max <= 1e-6, the bound of the form's per-term
-rounding: FP32 rounding of r (2 pi 2^-26), FP32 sincos (measured below),
-the FP32 flux and product (2 x 2^-24), and the Kahan sums (2 x 2^-24).
+rounding: FP32 rounding of r in [0, 1) (2 pi 2^-25), FP32 sincos (measured below),
+the FP32 flux (2^-24), the two FMAs through which a pair of components' products
+enters the sums (at most 2 x 2^-24 of a term), and the Kahan sums (2 x 2^-24).
 """
 import numpy as np
 import pytest
@@ -119,6 +120,24 @@ def test_precision_form_cfg3(env, prec):
     ref = ov.predict_direct(u[rows], v[rows], w[rows], l, m, f)
     e_max, e_rms = errors(got, ref, f.sum())
     note(f"cfg3 direct {prec}: E_max={e_max:.3e} E_rms={e_rms:.3e}")
+    assert e_max <= TOL32
+
+
+@pytest.mark.parametrize("n_comp", [1, 2, 3, 16, 17, 1000, 1001])
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_f32c_component_pairs(env, n_comp, sign):
+    """The FP32-compensated form sums components in pairs with an odd last
+    one alone: even and odd counts, both signs, against the oracle at the
+    form's bound, on 8,195 rows of cfg1 (a multiple of no block size)."""
+    rng = np.random.default_rng(n_comp * 10 + (sign > 0))
+    u, v, w = configs.CFG1.track.uvw()
+    u, v, w = u[:8195], v[:8195], w[:8195]
+    l, m = rng.uniform(-0.03, 0.03, n_comp), rng.uniform(-0.03, 0.03, n_comp)
+    f = rng.lognormal(-3, 1, n_comp)
+    got = _run(env, u, v, w, l, m, f, sign, "f32c").astype(np.complex128)
+    ref = ov.predict_direct(u, v, w, l, m, f, sign)
+    e_max, e_rms = errors(got, ref, f.sum())
+    note(f"direct f32c {n_comp} components sign={sign}: E_max={e_max:.3e} E_rms={e_rms:.3e}")
     assert e_max <= TOL32
 
 
