@@ -92,9 +92,9 @@ __host__ __device__ __forceinline__ void cis2pi_q_vop3(double r, double& c, doub
     cis2pi_q_impl<true>(r, c, q);
 }
 
-// FP32 phasor of a reduced phase |r| <= 1/2 in cycles: cos(2 pi r), sin(2 pi r)
-// from the hardware transcendental unit (v_cos_f32 / v_sin_f32 take the angle
-// in revolutions and are valid on [-256, 256]).
+// FP32 phasor of a reduced phase r in cycles (the callers pass r in [0, 1)):
+// cos(2 pi r), sin(2 pi r) from the hardware transcendental unit (v_cos_f32 /
+// v_sin_f32 take the angle in revolutions and are valid on [-256, 256]).
 __device__ __forceinline__ void cis2pi_f32(float r, float& c, float& s) {
     c = __builtin_amdgcn_cosf(r);
     s = __builtin_amdgcn_sinf(r);
