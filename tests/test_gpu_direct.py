@@ -155,6 +155,40 @@ def test_phasor_accuracy_dense(env, prec):
     assert err <= (2e-15 if prec == "fp64" else 2.5e-7)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "f32c"])
+def test_every_tile_shape_same_bits(env, prec):
+    """A row's arithmetic does not depend on the tile shape (rows per lane,
+    threads per block): all nine shapes give the same bits, on a row count
+    that is a multiple of no tile, with an odd component count."""
+    torch, swv = env
+    ctx = swv.context()
+    fam, small = (0 if prec == "fp64" else 1), 0
+    saved = ctx.tune_get(fam, small)
+    rng = np.random.default_rng(77)
+    n_vis, n_comp = 5003, 101
+    u, v, w = (rng.uniform(-2e5, 2e5, n_vis) for _ in range(3))
+    l, m = rng.uniform(-0.03, 0.03, n_comp), rng.uniform(-0.03, 0.03, n_comp)
+    f = rng.lognormal(-3, 1, n_comp)
+    outs = {}
+    try:
+        for vpl in (1, 2, 4):
+            for block in (64, 128, 256):
+                ctx.tune_set(fam, small, vpl, block)
+                outs[(vpl, block)] = _run(env, u, v, w, l, m, f, -1, prec)
+    finally:
+        ctx.tune_set(fam, small, *saved)
+    first = outs[(1, 64)]
+    for shape, got in outs.items():
+        assert np.array_equal(got, first), shape
+    ref = ov.predict_direct(u, v, w, l, m, f)
+    if prec == "fp64":
+        # few components do not average the per-term phase rounding
+        assert np.all(np.abs(first - ref) <= fp64_row_bound(u, v, w, l, m, ov.n_minus_1(l, m), f))
+    else:
+        e_max, _ = errors(first.astype(np.complex128), ref, f.sum())
+        assert e_max <= TOL32
+
+
 def test_run_to_run_bitwise(env):
     W = configs.CFG1
     u, v, w = W.track.uvw()
